@@ -1,0 +1,216 @@
+/*
+ * gsr.h -- C interface of libgsr, an MI355X (gfx950) implementation of the
+ * hot path of the Gaia AVU-GSR solver (Cesare et al., "The Gaia AVU-GSR
+ * solver: a CPU + GPU parallel code toward Exascale systems").
+ *
+ * The library solves the overdetermined system A x = b of Sec. 2, Eq. (1),
+ * with preconditioned LSQR (Paige & Saunders 1982), computing per iteration
+ * the two products of Eq. (2) and Eq. (3), the variances, and the
+ * covariances of Eq. (4) for a selected set of unknowns.
+ *
+ * Matrix form (Sec. 2): A is held as a "dense" [m][24] coefficient array with
+ * N_Astro = 5, N_Att = 12, N_Instr = 6 and N_Glob = 1 values per row.
+ *   slot  0..4   astrometric: columns 5*s .. 5*s+4 of the row's star s
+ *   slot  5..16  attitude: axis a = (k-5)/4 uses column
+ *                N_A + a*n_att + att_start[r] + (k-5)%4   (N_A = 5*n_stars)
+ *   slot 17..22  instrumental: column N_A + 3*n_att + instr_col[r][k-17]
+ *   slot 23      global: column N_A + 3*n_att + n_instr  (ignored if n_glob = 0)
+ * Unknowns: [astrometric, star-major][attitude, axis-major][instrumental][global],
+ * n = 5*n_stars + 3*n_att + n_instr + n_glob.  Rows are sorted by star: star s
+ * owns rows star_row_ptr[s] .. star_row_ptr[s+1]-1.
+ *
+ * Conventions for every entry point:
+ *  - Return 0 (GSR_OK) or a negative GSR_E* code; gsr_last_error() then gives
+ *    a message (thread-local).  LSQR convergence outcomes are not errors:
+ *    they come back in gsr_lsqr_result.istop.
+ *  - Pointers marked "device" must be device memory of the current HIP
+ *    device (e.g. from hipMalloc or a PyTorch tensor); "host" pointers are
+ *    ordinary host memory.  Arrays are dense and C-ordered.
+ *  - The system arrays are BORROWED by the handle (never copied): the caller
+ *    keeps them alive and unchanged until gsr_destroy.  The library allocates
+ *    and frees its own workspaces (vectors of the solve, scalars, partial
+ *    sums, covariance buffers).
+ *  - `stream` is a hipStream_t (NULL: the null stream).  Calls are
+ *    asynchronous on it unless stated otherwise.  A handle is not
+ *    thread-safe and its calls must be ordered on one stream; separate
+ *    handles are independent.
+ */
+#ifndef GSR_H
+#define GSR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gsr_system gsr_system;
+typedef struct gsr_mlp gsr_mlp;
+typedef void *gsr_stream; /* hipStream_t */
+
+enum {
+    GSR_OK = 0,
+    GSR_EINVAL = -1, /* bad argument, bad index data, unknown handle */
+    GSR_ENOMEM = -2, /* device allocation failed */
+    GSR_EHIP = -3,   /* a HIP runtime call failed */
+    GSR_ESTATE = -4  /* call out of order (e.g. iterate without begin) */
+};
+
+enum { GSR_F64 = 0, GSR_F32 = 1 };          /* storage type of the coefficients */
+enum { GSR_PROD_F64 = 0, GSR_PROD_F32 = 1 }; /* how a product a*x is formed */
+
+typedef struct {
+    int64_t n_stars; /* >= 0 */
+    int64_t m;       /* rows (observations), >= 0 */
+    int64_t n_att;   /* attitude spline coefficients per axis, >= 4 */
+    int64_t n_instr; /* instrumental unknowns, >= 6 */
+    int32_t n_glob;  /* 0 or 1 */
+    int32_t value_type; /* GSR_F64 or GSR_F32 */
+} gsr_dims;
+
+/* n = 5*n_stars + 3*n_att + n_instr + n_glob, or -1 for invalid dims. */
+int64_t gsr_num_unknowns(const gsr_dims *d);
+const char *gsr_last_error(void);
+const char *gsr_version(void);
+
+/*
+ * Create a handle over a system (Sec. 2, Eq. 1; the 24-slot form above).
+ *   vals          device, [m][24] double (GSR_F64) or float (GSR_F32), 16-byte aligned
+ *   star_row_ptr  device, [n_stars+1] int64, star_row_ptr[0] = 0, nondecreasing,
+ *                 star_row_ptr[n_stars] = m
+ *   att_start     device, [m] int32 in [0, n_att-4]
+ *   instr_col     device, [m][6] int32 in [0, n_instr), 8-byte aligned
+ * The index arrays are validated on the device; the first offending row or
+ * star is reported with GSR_EINVAL.  Synchronous.  *out is set on success.
+ */
+int gsr_create(gsr_system **out, const gsr_dims *d, const void *vals, const int64_t *star_row_ptr,
+               const int32_t *att_start, const int32_t *instr_col, gsr_stream stream);
+/* Free the handle's workspaces (synchronises the device first).  NULL is a no-op. */
+int gsr_destroy(gsr_system *sys);
+
+/*
+ * aprod 1 (Sec. 2, Eq. 2): y <- scale_y * y + A x.
+ *   x device [n], y device [m] (must not overlap).  scale_y = 1 gives the
+ *   paper's "b += A x"; scale_y = 0 overwrites y without reading it.
+ *   product GSR_PROD_F32 (FP32 systems only) forms each a*x in FP32 from
+ *   fl32(x); sums are always FP64.
+ */
+int gsr_aprod1(gsr_system *sys, const double *x, double *y, double scale_y, int32_t product,
+               gsr_stream stream);
+/*
+ * aprod 2 (Sec. 2, Eq. 3): x <- scale_x * x + A^T y.
+ *   y device [m], x device [n] (must not overlap).  Same conventions as
+ *   gsr_aprod1.  Attitude / instrumental / global sums use FP64 atomics, so
+ *   their summation order (and last bits) may vary between calls.
+ */
+int gsr_aprod2(gsr_system *sys, const double *y, double *x, double scale_x, int32_t product,
+               gsr_stream stream);
+/*
+ * Column scaling used by the preconditioner (Sec. 2, solver step 2; read as
+ * diagonal column scaling): scale[j] = 1/||a_j||_2 (1 for an empty column).
+ * Computed once per handle and cached.  scale_out device [n] or NULL.
+ */
+int gsr_column_scale(gsr_system *sys, double *scale_out, gsr_stream stream);
+
+typedef struct {
+    double damp;      /* >= 0: minimise ||A x - b||^2 + damp^2 ||S^-1 (x - x0)||^2 */
+    double atol, btol; /* Paige-Saunders tolerances, >= 0 */
+    double conlim;    /* > 0: stop when cond(A S) estimate exceeds it; 0 = off */
+    int64_t itmax;    /* >= 0 */
+    int32_t precond;  /* 1: column scaling S = diag(1/||a_j||); 0: S = I */
+    int32_t product;  /* GSR_PROD_F64 or GSR_PROD_F32 (FP32 systems) for the iteration products */
+    int32_t outer_max;  /* gsr_lsqr_refine only: maximum outer steps (>= 1) */
+    double outer_tol;   /* gsr_lsqr_refine only: stop when ||dx|| <= outer_tol ||x|| */
+} gsr_lsqr_opts;
+
+typedef struct {
+    int32_t istop;      /* 0: x0 solves it (b - A x0 = 0 or A^T(b - A x0) = 0); 1: compatible
+                           system solved to atol/btol; 2: least-squares solution to atol;
+                           3: conlim reached; 4-6: as 1-3 at machine precision; 7: itmax */
+    int32_t outer_steps; /* gsr_lsqr_refine: outer steps taken */
+    int64_t itn;        /* iterations (refine: inner iterations of the last step) */
+    int64_t inner_total; /* refine: inner iterations summed over the outer steps */
+    double rnorm, arnorm, anorm, acond, xnorm, bnorm; /* Paige-Saunders estimates; xnorm = ||y||
+                           of the scaled problem, computed directly */
+} gsr_lsqr_result;
+
+/*
+ * Preconditioned LSQR (Sec. 2 solver outline): precondition, initial
+ * conditions with aprod 2, iterate aprod 1 / aprod 2 / variances /
+ * covariance vectors, de-precondition.  Returns x = x0 + S y where y solves
+ * min ||[A S; damp I] y - [b - A x0; 0]||, and the variances
+ * var_j = s_j^2 sum_i d_i[j]^2 (d_i = w_i / rho_i).
+ *   b device [m]; x0 device [n] or NULL (zero start); x device [n] (output);
+ *   var device [n] or NULL; opts host; res host or NULL.
+ * Every iteration runs on the device without host round trips; the call
+ * returns once the solve has stopped (synchronous).
+ */
+int gsr_lsqr_solve(gsr_system *sys, const double *b, const double *x0, double *x, double *var,
+                   const gsr_lsqr_opts *opts, gsr_lsqr_result *res, gsr_stream stream);
+
+/* The same solve in steps: begin (asynchronous), iterate n more iterations
+ * (asynchronous; iterations after a stop are no-ops), status (synchronises
+ * and reads the scalars), peek (current x = x0 + S y into device [n]),
+ * end (flush covariances, write x / var, read the result; synchronous).
+ * b and x0 must stay valid until end. */
+int gsr_lsqr_begin(gsr_system *sys, const double *b, const double *x0, const gsr_lsqr_opts *opts,
+                   gsr_stream stream);
+int gsr_lsqr_iterate(gsr_system *sys, int64_t n_iter, gsr_stream stream);
+int gsr_lsqr_status(gsr_system *sys, gsr_lsqr_result *res, gsr_stream stream);
+int gsr_lsqr_peek(gsr_system *sys, double *x, gsr_stream stream);
+int gsr_lsqr_end(gsr_system *sys, double *x, double *var, gsr_lsqr_result *res, gsr_stream stream);
+
+/*
+ * FP32 form with FP64 iterative refinement (FP32 systems).  Each outer step
+ * forms r = b - A x with FP64 products on the FP32 coefficients (exact
+ * upcast), solves A dx ~ r with LSQR using `inner` (normally
+ * product = GSR_PROD_F32 and loose atol/btol), and updates x += dx, until
+ * ||dx|| <= outer_tol ||x|| or outer_max steps.  Arguments as gsr_lsqr_solve.
+ */
+int gsr_lsqr_refine(gsr_system *sys, const double *b, const double *x0, double *x,
+                    const gsr_lsqr_opts *inner, gsr_lsqr_result *res, gsr_stream stream);
+
+/*
+ * Covariances of Eq. (4) for a selected set of unknowns, read as
+ * C = S_sel (sum_i d_i[sel] d_i[sel]^T) S_sel with d_i = w_i / rho_i.
+ * gsr_cov_request attaches the selection to the handle for the next solves:
+ *   sel host [k] in [0, n) (k = 0 detaches), block in [1, 1024]: iterations
+ *   buffered on the device (d_i[sel] gathered every iteration, as the
+ *   x_Cycle buffer of Sec. 2.2 with itnCovCP = block) before each FP64 MFMA
+ *   SYRK update C += D D^T.  Synchronous.
+ * gsr_cov_get writes C of the last solve: device [k][k], full symmetric,
+ * diagonal = var[sel].
+ * gsr_cov_bytes: bytes of the per-cycle buffer of the two pipeline
+ * versions of Sec. 2.2 (Eq. 5: version 1, 8*itn_cov_cp*n_unk; Eq. 6:
+ * version 2, 8*itn_cov_cp*n_indexes), or -1 for bad arguments.
+ */
+int gsr_cov_request(gsr_system *sys, const int64_t *sel, int64_t k, int32_t block);
+int gsr_cov_get(gsr_system *sys, double *C, gsr_stream stream);
+int64_t gsr_cov_bytes(int32_t version, int64_t itn_cov_cp, int64_t count);
+
+/*
+ * One covariance update C += D[:, :cols] D[:, :cols]^T (Eq. 4 over a block of
+ * buffered vectors) on the upper triangle of 32x32 tiles of C.
+ *   D device [k][ldd] (cols <= ldd), C device [k][k]; lower-triangle tiles
+ *   are not written.
+ */
+int gsr_syrk(const double *D, int64_t k, int64_t cols, int64_t ldd, double *C, gsr_stream stream);
+
+/* Launch tuning of the row-streaming kernels (waves per CU, LDS staging on/off). */
+int gsr_set_tuning(gsr_system *sys, int32_t waves_per_cu, int32_t stage);
+
+/* Per-kernel timing with HIP events on the solve's stream (off by default).
+ * gsr_timing_get synchronises, returns the totals since the last get and
+ * resets them. */
+typedef struct {
+    double aprod1_ms, aprod2_ms, tail_ms, update_ms, syrk_ms;
+    int64_t aprod1_n, aprod2_n, tail_n, update_n, syrk_n;
+} gsr_timing;
+int gsr_timing_enable(gsr_system *sys, int32_t on);
+int gsr_timing_get(gsr_system *sys, gsr_timing *t);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSR_H */

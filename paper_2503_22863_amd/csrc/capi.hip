@@ -1,0 +1,705 @@
+// C-ABI layer of libgsr: handles, argument checks, workspace management and
+// the host side of the device-resident LSQR driver.  All arithmetic of the
+// method runs in the kernels (aprod.hip, lsqr.hip, mlp.hip); this file only
+// validates, allocates and enqueues.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <set>
+#include <vector>
+
+#include "internal.h"
+
+using namespace gsr;
+
+// ------------------------------------------------------------------ errors
+static thread_local char g_err[512] = "";
+
+static int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+#define HIPCHK(call)                                                                                  \
+  do {                                                                                                \
+    hipError_t e_ = (call);                                                                           \
+    if (e_ != hipSuccess)                                                                             \
+      return fail(e_ == hipErrorOutOfMemory ? GSR_ENOMEM : GSR_EHIP, "%s failed: %s", #call,          \
+                  hipGetErrorString(e_));                                                             \
+  } while (0)
+
+#define CHK(expr)              \
+  do {                         \
+    int rc_ = (expr);          \
+    if (rc_ != GSR_OK) return rc_; \
+  } while (0)
+
+extern "C" const char* gsr_last_error(void) { return g_err; }
+extern "C" const char* gsr_version(void) { return "gsr 0.1 (gfx950)"; }
+
+// ------------------------------------------------------------------ handle
+struct PendingTime {
+  int kind;
+  hipEvent_t a, b;
+};
+
+struct gsr_system {
+  SysView s;
+  int device = 0;
+  int cus = 256;
+  int waves_per_cu = 32;
+  int stage = 1;
+  StreamShape sh{};
+  Scalars* sc = nullptr;
+  Scalars* sc_host = nullptr;  // pinned
+  Work wk{};
+  double* acc = nullptr;  // tail accumulators [tail_len]
+  double* S = nullptr;
+  int S_valid = 0;
+  // LSQR vectors
+  double *u = nullptr, *v = nullptr, *vg = nullptr, *w = nullptr, *y = nullptr, *var = nullptr;
+  // refinement buffers
+  double *r = nullptr, *xr = nullptr, *dx = nullptr, *nrm2 = nullptr;
+  // covariances
+  int64_t nsel = 0;
+  int32_t dblock = 64;
+  int64_t* sel = nullptr;
+  double* D = nullptr;
+  double* Cacc = nullptr;
+  int cov_precond = 0;
+  // session
+  int in_session = 0;
+  int precond = 0;
+  int pmode = 0;
+  const double* x0 = nullptr;
+  int64_t itmax = 0;
+  int64_t enq = 0;
+  // timing
+  int timing = 0;
+  std::vector<hipEvent_t> pool;
+  std::vector<PendingTime> pending;
+  double tms[5] = {0, 0, 0, 0, 0};
+  int64_t tn[5] = {0, 0, 0, 0, 0};
+};
+
+static std::mutex g_mu;
+static std::set<gsr_system*> g_live;
+
+static int check_handle(gsr_system* s) {
+  if (!s) return fail(GSR_EINVAL, "null handle");
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!g_live.count(s)) return fail(GSR_EINVAL, "unknown or destroyed handle");
+  return GSR_OK;
+}
+
+static int dev_alloc(void** p, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    return fail(GSR_ENOMEM, "device allocation of %zu bytes failed", bytes);
+  }
+  if (e != hipSuccess) return fail(GSR_EHIP, "hipMalloc: %s", hipGetErrorString(e));
+  return GSR_OK;
+}
+
+template <typename T>
+static int dalloc(T** p, size_t count) {
+  return dev_alloc(reinterpret_cast<void**>(p), count * sizeof(T));
+}
+
+static void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+static int is_device_ptr(const void* p) {
+  if (!p) return 0;
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+#define NEED_DEV(p, name)                                                                          \
+  do {                                                                                             \
+    if (!is_device_ptr(p)) return fail(GSR_EINVAL, "%s must be a device pointer", name);            \
+  } while (0)
+
+int gsr::device_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return 256;
+  return cus;
+}
+
+extern "C" int64_t gsr_num_unknowns(const gsr_dims* d) {
+  if (!d || d->n_stars < 0 || d->m < 0 || d->n_att < 4 || d->n_instr < 6 || (d->n_glob != 0 && d->n_glob != 1))
+    return -1;
+  return 5 * d->n_stars + 3 * d->n_att + d->n_instr + d->n_glob;
+}
+
+static void reshape(gsr_system* s) { s->sh = stream_shape(s->s, s->cus, s->waves_per_cu, s->stage); }
+
+static void release(gsr_system* s) {
+  (void)hipDeviceSynchronize();
+  dfree(s->sc);
+  if (s->sc_host) (void)hipHostFree(s->sc_host);
+  dfree(s->wk.part_a);
+  dfree(s->wk.part_b);
+  dfree(s->wk.part_c);
+  dfree(s->wk.tickets);
+  dfree(s->acc);
+  dfree(s->S);
+  dfree(s->u);
+  dfree(s->v);
+  dfree(s->vg);
+  dfree(s->w);
+  dfree(s->y);
+  dfree(s->var);
+  dfree(s->r);
+  dfree(s->xr);
+  dfree(s->dx);
+  dfree(s->nrm2);
+  dfree(s->sel);
+  dfree(s->D);
+  dfree(s->Cacc);
+  for (auto e : s->pool) (void)hipEventDestroy(e);
+  for (auto& p : s->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  delete s;
+}
+
+extern "C" int gsr_create(gsr_system** out, const gsr_dims* d, const void* vals, const int64_t* star_row_ptr,
+                          const int32_t* att_start, const int32_t* instr_col, gsr_stream stream) {
+  if (!out) return fail(GSR_EINVAL, "out is null");
+  *out = nullptr;
+  if (gsr_num_unknowns(d) < 0)
+    return fail(GSR_EINVAL, "bad dims: need n_stars >= 0, m >= 0, n_att >= 4, n_instr >= 6, n_glob in {0,1}");
+  if (d->value_type != GSR_F64 && d->value_type != GSR_F32) return fail(GSR_EINVAL, "bad value_type");
+  if (d->n_att > INT32_MAX || d->n_instr > INT32_MAX) return fail(GSR_EINVAL, "n_att / n_instr too large");
+  NEED_DEV(star_row_ptr, "star_row_ptr");
+  if (d->m > 0) {
+    NEED_DEV(vals, "vals");
+    NEED_DEV(att_start, "att_start");
+    NEED_DEV(instr_col, "instr_col");
+    if ((uintptr_t)vals % 16) return fail(GSR_EINVAL, "vals must be 16-byte aligned");
+    if ((uintptr_t)instr_col % 8) return fail(GSR_EINVAL, "instr_col must be 8-byte aligned");
+    if ((uintptr_t)att_start % 4) return fail(GSR_EINVAL, "att_start must be 4-byte aligned");
+  }
+  if ((uintptr_t)star_row_ptr % 8) return fail(GSR_EINVAL, "star_row_ptr must be 8-byte aligned");
+  if (d->n_stars == 0 && d->m > 0) return fail(GSR_EINVAL, "rows without stars");
+  if (d->n_instr + 1 > kLdsTailMax) return fail(GSR_EINVAL, "n_instr above %d is not supported", kLdsTailMax - 1);
+
+  gsr_system* s = new gsr_system();
+  hipStream_t st = (hipStream_t)stream;
+  SysView& v = s->s;
+  v.n_stars = d->n_stars;
+  v.m = d->m;
+  v.n_att = d->n_att;
+  v.n_instr = d->n_instr;
+  v.n_glob = d->n_glob;
+  v.value_type = d->value_type;
+  v.n_astro = 5 * d->n_stars;
+  v.tail_len = 3 * d->n_att + d->n_instr + d->n_glob;
+  v.n = v.n_astro + v.tail_len;
+  v.vals = vals;
+  v.row_ptr = star_row_ptr;
+  v.att_start = att_start;
+  v.instr_col = instr_col;
+  v.has_empty_stars = 0;
+  (void)hipGetDevice(&s->device);
+  s->cus = device_cus();
+
+  int rc = GSR_OK;
+  auto bail = [&](int code) {
+    release(s);
+    return code;
+  };
+  if ((rc = dalloc(&s->sc, 1)) || (rc = dalloc(&s->wk.part_a, kMaxPartials)) ||
+      (rc = dalloc(&s->wk.part_b, kMaxPartials)) || (rc = dalloc(&s->wk.part_c, kMaxPartials)) ||
+      (rc = dalloc(&s->wk.tickets, 8)) || (rc = dalloc(&s->acc, (size_t)v.tail_len)))
+    return bail(rc);
+  if (hipHostMalloc((void**)&s->sc_host, sizeof(Scalars), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return bail(fail(GSR_ENOMEM, "pinned host allocation failed"));
+  }
+  if (hipMemsetAsync(s->wk.tickets, 0, 8 * sizeof(unsigned), st) != hipSuccess ||
+      hipMemsetAsync(s->acc, 0, (size_t)v.tail_len * sizeof(double), st) != hipSuccess)
+    return bail(fail(GSR_EHIP, "workspace clear failed"));
+
+  // index validation on the device
+  unsigned long long* bad = nullptr;
+  if ((rc = dalloc(&bad, 3))) return bail(rc);
+  unsigned long long hb[3] = {~0ull, ~0ull, 0ull};
+  hipError_t e = hipMemcpyAsync(bad, hb, sizeof hb, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = launch_validate(v, bad, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(hb, bad, sizeof hb, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  dfree(bad);
+  if (e != hipSuccess) return bail(fail(GSR_EHIP, "validation failed: %s", hipGetErrorString(e)));
+  if (hb[1] != ~0ull) return bail(fail(GSR_EINVAL, "star_row_ptr invalid at star %llu", hb[1]));
+  if (d->n_stars > 0) {
+    int64_t ends[2];
+    if (hipMemcpy(ends, star_row_ptr, sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(ends + 1, star_row_ptr + d->n_stars, sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess)
+      return bail(fail(GSR_EHIP, "reading star_row_ptr failed"));
+    if (ends[0] != 0 || ends[1] != d->m) return bail(fail(GSR_EINVAL, "star_row_ptr must run from 0 to m"));
+  }
+  if (hb[0] != ~0ull) return bail(fail(GSR_EINVAL, "att_start / instr_col out of range at row %llu", hb[0]));
+  v.has_empty_stars = hb[2] != 0;
+  reshape(s);
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_live.insert(s);
+  }
+  *out = s;
+  return GSR_OK;
+}
+
+extern "C" int gsr_destroy(gsr_system* s) {
+  if (!s) return GSR_OK;
+  CHK(check_handle(s));
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_live.erase(s);
+  }
+  release(s);
+  return GSR_OK;
+}
+
+extern "C" int gsr_set_tuning(gsr_system* s, int32_t waves_per_cu, int32_t stage) {
+  CHK(check_handle(s));
+  if (waves_per_cu < 1 || waves_per_cu > 256 || (stage != 0 && stage != 1))
+    return fail(GSR_EINVAL, "waves_per_cu in [1,256], stage in {0,1}");
+  s->waves_per_cu = waves_per_cu;
+  s->stage = stage;
+  reshape(s);
+  return GSR_OK;
+}
+
+// ------------------------------------------------------------------ timing
+static int ev_get(gsr_system* s, hipEvent_t* e) {
+  if (!s->pool.empty()) {
+    *e = s->pool.back();
+    s->pool.pop_back();
+    return GSR_OK;
+  }
+  HIPCHK(hipEventCreate(e));
+  return GSR_OK;
+}
+
+struct TimeScope {
+  gsr_system* s;
+  int kind;
+  hipStream_t st;
+  hipEvent_t a{}, b{};
+  bool on;
+  TimeScope(gsr_system* s_, int k, hipStream_t st_) : s(s_), kind(k), st(st_), on(s_->timing != 0) {
+    if (on && (ev_get(s, &a) != GSR_OK || ev_get(s, &b) != GSR_OK || hipEventRecord(a, st) != hipSuccess)) on = false;
+  }
+  ~TimeScope() {
+    if (!on) return;
+    if (hipEventRecord(b, st) == hipSuccess) s->pending.push_back({kind, a, b});
+  }
+};
+
+extern "C" int gsr_timing_enable(gsr_system* s, int32_t on) {
+  CHK(check_handle(s));
+  s->timing = on != 0;
+  return GSR_OK;
+}
+
+extern "C" int gsr_timing_get(gsr_system* s, gsr_timing* t) {
+  CHK(check_handle(s));
+  if (!t) return fail(GSR_EINVAL, "t is null");
+  for (auto& p : s->pending) {
+    HIPCHK(hipEventSynchronize(p.b));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
+    s->tms[p.kind] += ms;
+    s->tn[p.kind] += 1;
+    s->pool.push_back(p.a);
+    s->pool.push_back(p.b);
+  }
+  s->pending.clear();
+  t->aprod1_ms = s->tms[0];
+  t->aprod2_ms = s->tms[1];
+  t->tail_ms = s->tms[2];
+  t->update_ms = s->tms[3];
+  t->syrk_ms = s->tms[4];
+  t->aprod1_n = s->tn[0];
+  t->aprod2_n = s->tn[1];
+  t->tail_n = s->tn[2];
+  t->update_n = s->tn[3];
+  t->syrk_n = s->tn[4];
+  for (int i = 0; i < 5; ++i) {
+    s->tms[i] = 0;
+    s->tn[i] = 0;
+  }
+  return GSR_OK;
+}
+
+// ------------------------------------------------------------------ products
+static int check_product(gsr_system* s, int32_t product) {
+  if (product != GSR_PROD_F64 && product != GSR_PROD_F32) return fail(GSR_EINVAL, "bad product mode");
+  if (product == GSR_PROD_F32 && s->s.value_type != GSR_F32)
+    return fail(GSR_EINVAL, "FP32 products need an FP32 system");
+  return GSR_OK;
+}
+
+extern "C" int gsr_aprod1(gsr_system* s, const double* x, double* y, double scale_y, int32_t product,
+                          gsr_stream stream) {
+  CHK(check_handle(s));
+  CHK(check_product(s, product));
+  NEED_DEV(x, "x");
+  if (s->s.m > 0) NEED_DEV(y, "y");
+  if (s->s.m == 0) return GSR_OK;
+  TimeScope ts(s, 0, (hipStream_t)stream);
+  HIPCHK(launch_aprod1(s->s, s->sh, x, y, scale_y, 1.0, product, nullptr, s->wk, 0, (hipStream_t)stream));
+  return GSR_OK;
+}
+
+static int aprod2_raw(gsr_system* s, const double* y, double* x, double scale_x, int32_t product, int square,
+                      hipStream_t st) {
+  {
+    TimeScope ts(s, 1, st);
+    HIPCHK(launch_aprod2(s->s, s->sh, y, x, s->acc, nullptr, scale_x, 1.0, product, square, nullptr, s->wk, st));
+  }
+  TimeScope ts(s, 2, st);
+  HIPCHK(launch_tail(s->s, x, s->acc, nullptr, scale_x, square, nullptr, s->wk, 0, 0, nullptr, nullptr, nullptr, st));
+  return GSR_OK;
+}
+
+extern "C" int gsr_aprod2(gsr_system* s, const double* y, double* x, double scale_x, int32_t product,
+                          gsr_stream stream) {
+  CHK(check_handle(s));
+  CHK(check_product(s, product));
+  NEED_DEV(x, "x");
+  if (s->s.m > 0) NEED_DEV(y, "y");
+  return aprod2_raw(s, y, x, scale_x, product, 0, (hipStream_t)stream);
+}
+
+static int ensure_scale(gsr_system* s, hipStream_t st) {
+  if (s->S_valid) return GSR_OK;
+  if (!s->S) CHK(dalloc(&s->S, (size_t)s->s.n));
+  // column sums of squares with the aprod 2 machinery, then 1/sqrt
+  CHK(aprod2_raw(s, nullptr, s->S, 0.0, 0, 1, st));
+  HIPCHK(launch_scale_from_sq(s->s.n, s->S, st));
+  s->S_valid = 1;
+  return GSR_OK;
+}
+
+extern "C" int gsr_column_scale(gsr_system* s, double* out, gsr_stream stream) {
+  CHK(check_handle(s));
+  hipStream_t st = (hipStream_t)stream;
+  CHK(ensure_scale(s, st));
+  if (out) {
+    NEED_DEV(out, "scale_out");
+    HIPCHK(hipMemcpyAsync(out, s->S, (size_t)s->s.n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  }
+  return GSR_OK;
+}
+
+// ------------------------------------------------------------------ LSQR
+static int check_opts(const gsr_lsqr_opts* o) {
+  if (!o) return fail(GSR_EINVAL, "opts is null");
+  if (!(o->damp >= 0) || !(o->atol >= 0) || !(o->btol >= 0) || !(o->conlim >= 0) || o->itmax < 0)
+    return fail(GSR_EINVAL, "opts: damp, atol, btol, conlim and itmax must be >= 0");
+  if (o->precond != 0 && o->precond != 1) return fail(GSR_EINVAL, "opts.precond must be 0 or 1");
+  return GSR_OK;
+}
+
+static int ensure_vectors(gsr_system* s) {
+  const size_t m = (size_t)s->s.m, n = (size_t)s->s.n;
+  if (!s->u) CHK(dalloc(&s->u, m));
+  if (!s->v) CHK(dalloc(&s->v, n));
+  if (!s->vg) CHK(dalloc(&s->vg, n));
+  if (!s->w) CHK(dalloc(&s->w, n));
+  if (!s->y) CHK(dalloc(&s->y, n));
+  if (!s->var) CHK(dalloc(&s->var, n));
+  return GSR_OK;
+}
+
+static int lsqr_begin(gsr_system* s, const double* b, const double* x0, const gsr_lsqr_opts* o, int32_t product,
+                      hipStream_t st) {
+  CHK(check_opts(o));
+  CHK(check_product(s, product));
+  if (s->s.m > 0) NEED_DEV(b, "b");
+  if (x0) NEED_DEV(x0, "x0");
+  CHK(ensure_vectors(s));
+  if (o->precond) CHK(ensure_scale(s, st));
+  s->precond = o->precond;
+  s->pmode = product;
+  s->x0 = x0;
+  s->itmax = o->itmax;
+  s->enq = 0;
+  const double* S = o->precond ? s->S : nullptr;
+
+  Scalars h;
+  memset(&h, 0, sizeof h);
+  h.damp = o->damp;
+  h.atol = o->atol;
+  h.btol = o->btol;
+  h.ctol = o->conlim > 0 ? 1.0 / o->conlim : 0.0;
+  h.itmax = o->itmax;
+  h.nsel = s->nsel;
+  h.dblock = s->dblock;
+  *s->sc_host = h;
+  HIPCHK(hipMemcpyAsync(s->sc, s->sc_host, sizeof(Scalars), hipMemcpyHostToDevice, st));
+  if (s->nsel > 0) {
+    HIPCHK(launch_fill(s->Cacc, s->nsel * s->nsel, 0.0, st));
+    s->cov_precond = o->precond;
+  }
+  // r0 = b - A x0
+  HIPCHK(launch_copy(b, s->u, s->s.m, st));
+  if (x0 && s->s.m > 0)
+    HIPCHK(launch_aprod1(s->s, s->sh, x0, s->u, 1.0, -1.0, 0, nullptr, s->wk, 0, st));
+  HIPCHK(launch_norm_init(s->u, s->s.m, s->sc, s->wk, st));
+  // alpha_1 v_1 = S A^T u_1
+  HIPCHK(launch_aprod2(s->s, s->sh, s->u, s->v, s->acc, S, 0.0, 1.0, product, 0, s->sc, s->wk, st));
+  HIPCHK(launch_tail(s->s, s->v, s->acc, S, 0.0, 0, s->sc, s->wk, 0, s->sh.blocks, s->sel, s->w, s->D, st));
+  HIPCHK(launch_init_vectors(s->s.n, s->v, s->vg, s->w, s->y, s->var, S, s->sc, st));
+  s->in_session = 1;
+  return GSR_OK;
+}
+
+extern "C" int gsr_lsqr_begin(gsr_system* s, const double* b, const double* x0, const gsr_lsqr_opts* o,
+                              gsr_stream stream) {
+  CHK(check_handle(s));
+  if (!o) return fail(GSR_EINVAL, "opts is null");
+  return lsqr_begin(s, b, x0, o, o->product, (hipStream_t)stream);
+}
+
+static int lsqr_iterate(gsr_system* s, int64_t nit, hipStream_t st) {
+  const double* S = s->precond ? s->S : nullptr;
+  double* vg = s->precond ? s->vg : s->v;
+  for (int64_t i = 0; i < nit && s->enq < s->itmax; ++i) {
+    {
+      TimeScope ts(s, 0, st);
+      HIPCHK(launch_aprod1(s->s, s->sh, vg, s->u, 0.0, 1.0, s->pmode, s->sc, s->wk, 1, st));
+    }
+    {
+      TimeScope ts(s, 1, st);
+      HIPCHK(launch_aprod2(s->s, s->sh, s->u, s->v, s->acc, S, 0.0, 1.0, s->pmode, 0, s->sc, s->wk, st));
+    }
+    {
+      TimeScope ts(s, 2, st);
+      HIPCHK(launch_tail(s->s, s->v, s->acc, S, 0.0, 0, s->sc, s->wk, 1, s->sh.blocks, s->sel, s->w, s->D, st));
+    }
+    {
+      TimeScope ts(s, 3, st);
+      HIPCHK(launch_update(s->s.n, s->v, vg, s->w, s->y, s->var, S, s->sc, s->wk, st));
+    }
+    s->enq += 1;
+    if (s->nsel > 0 && s->enq % s->dblock == 0) {
+      TimeScope ts(s, 4, st);
+      HIPCHK(launch_syrk(s->D, s->nsel, s->dblock, s->Cacc, s->sc, s->wk, -1, st));
+    }
+  }
+  return GSR_OK;
+}
+
+extern "C" int gsr_lsqr_iterate(gsr_system* s, int64_t n_iter, gsr_stream stream) {
+  CHK(check_handle(s));
+  if (!s->in_session) return fail(GSR_ESTATE, "gsr_lsqr_iterate without gsr_lsqr_begin");
+  if (n_iter < 0) return fail(GSR_EINVAL, "n_iter < 0");
+  return lsqr_iterate(s, n_iter, (hipStream_t)stream);
+}
+
+static int read_status(gsr_system* s, gsr_lsqr_result* r, hipStream_t st) {
+  HIPCHK(hipMemcpyAsync(s->sc_host, s->sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const Scalars& h = *s->sc_host;
+  if (r) {
+    r->istop = h.istop;
+    r->itn = h.itn;
+    r->rnorm = h.rnorm;
+    r->arnorm = h.arnorm;
+    r->anorm = sqrt(h.anorm2);
+    r->acond = h.acond;
+    r->xnorm = h.xnorm;
+    r->bnorm = h.bnorm;
+    r->outer_steps = 0;
+    r->inner_total = h.itn;
+  }
+  return GSR_OK;
+}
+
+extern "C" int gsr_lsqr_status(gsr_system* s, gsr_lsqr_result* r, gsr_stream stream) {
+  CHK(check_handle(s));
+  if (!s->in_session) return fail(GSR_ESTATE, "no solve in progress");
+  return read_status(s, r, (hipStream_t)stream);
+}
+
+extern "C" int gsr_lsqr_peek(gsr_system* s, double* x, gsr_stream stream) {
+  CHK(check_handle(s));
+  if (!s->in_session) return fail(GSR_ESTATE, "no solve in progress");
+  NEED_DEV(x, "x");
+  HIPCHK(launch_finish(s->s.n, s->y, s->var, s->precond ? s->S : nullptr, s->x0, x, nullptr, (hipStream_t)stream));
+  return GSR_OK;
+}
+
+static int lsqr_end(gsr_system* s, double* x, double* var, gsr_lsqr_result* r, hipStream_t st) {
+  if (x) NEED_DEV(x, "x");
+  if (var) NEED_DEV(var, "var");
+  if (s->nsel > 0) {
+    TimeScope ts(s, 4, st);
+    HIPCHK(launch_syrk(s->D, s->nsel, s->dblock, s->Cacc, s->sc, s->wk, -1, st));
+  }
+  HIPCHK(launch_finish(s->s.n, s->y, s->var, s->precond ? s->S : nullptr, s->x0, x, var, st));
+  CHK(read_status(s, r, st));
+  s->in_session = 0;
+  return GSR_OK;
+}
+
+extern "C" int gsr_lsqr_end(gsr_system* s, double* x, double* var, gsr_lsqr_result* r, gsr_stream stream) {
+  CHK(check_handle(s));
+  if (!s->in_session) return fail(GSR_ESTATE, "no solve in progress");
+  return lsqr_end(s, x, var, r, (hipStream_t)stream);
+}
+
+static int lsqr_run(gsr_system* s, hipStream_t st) {
+  // enqueue in growing chunks; iterations queued after a stop are no-ops
+  int64_t chunk = 8;
+  for (;;) {
+    CHK(lsqr_iterate(s, chunk, st));
+    CHK(read_status(s, nullptr, st));
+    if (s->sc_host->done || s->enq >= s->itmax) break;
+    chunk = std::min<int64_t>(chunk * 2, 64);
+  }
+  return GSR_OK;
+}
+
+extern "C" int gsr_lsqr_solve(gsr_system* s, const double* b, const double* x0, double* x, double* var,
+                              const gsr_lsqr_opts* o, gsr_lsqr_result* r, gsr_stream stream) {
+  CHK(check_handle(s));
+  if (!o) return fail(GSR_EINVAL, "opts is null");
+  NEED_DEV(x, "x");
+  hipStream_t st = (hipStream_t)stream;
+  CHK(lsqr_begin(s, b, x0, o, o->product, st));
+  CHK(lsqr_run(s, st));
+  return lsqr_end(s, x, var, r, st);
+}
+
+extern "C" int gsr_lsqr_refine(gsr_system* s, const double* b, const double* x0, double* x,
+                               const gsr_lsqr_opts* o, gsr_lsqr_result* res, gsr_stream stream) {
+  CHK(check_handle(s));
+  CHK(check_opts(o));
+  if (s->s.value_type != GSR_F32) return fail(GSR_EINVAL, "gsr_lsqr_refine needs an FP32 system");
+  if (o->outer_max < 1 || !(o->outer_tol >= 0)) return fail(GSR_EINVAL, "outer_max >= 1, outer_tol >= 0");
+  NEED_DEV(x, "x");
+  if (s->s.m > 0) NEED_DEV(b, "b");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t m = (size_t)s->s.m, n = (size_t)s->s.n;
+  if (!s->r) CHK(dalloc(&s->r, m));
+  if (!s->xr) CHK(dalloc(&s->xr, n));
+  if (!s->dx) CHK(dalloc(&s->dx, n));
+  if (!s->nrm2) CHK(dalloc(&s->nrm2, 2));
+  if (x0) {
+    NEED_DEV(x0, "x0");
+    HIPCHK(launch_copy(x0, s->xr, (int64_t)n, st));
+  } else {
+    HIPCHK(launch_fill(s->xr, (int64_t)n, 0.0, st));
+  }
+  const int64_t keep_sel = s->nsel;
+  s->nsel = 0;  // covariances are not accumulated across refinement steps
+  int64_t total = 0;
+  int32_t steps = 0;
+  gsr_lsqr_result last{};
+  int rc = GSR_OK;
+  for (int32_t it = 0; it < o->outer_max; ++it) {
+    // r = b - A x with FP64 products on the stored FP32 coefficients
+    if ((rc = (launch_copy(b, s->r, (int64_t)m, st) == hipSuccess ? GSR_OK : fail(GSR_EHIP, "copy failed")))) break;
+    if (m > 0 && launch_aprod1(s->s, s->sh, s->xr, s->r, 1.0, -1.0, 0, nullptr, s->wk, 0, st) != hipSuccess) {
+      rc = fail(GSR_EHIP, "aprod1 launch failed");
+      break;
+    }
+    if ((rc = lsqr_begin(s, s->r, nullptr, o, o->product, st))) break;
+    if ((rc = lsqr_run(s, st))) break;
+    if ((rc = lsqr_end(s, s->dx, nullptr, &last, st))) break;
+    total += last.itn;
+    steps = it + 1;
+    if (launch_axpy_norms((int64_t)n, s->dx, s->xr, s->nrm2, s->wk, st) != hipSuccess) {
+      rc = fail(GSR_EHIP, "update launch failed");
+      break;
+    }
+    double h2[2];
+    if (hipMemcpyAsync(h2, s->nrm2, sizeof h2, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      rc = fail(GSR_EHIP, "reading norms failed");
+      break;
+    }
+    if (sqrt(h2[0]) <= o->outer_tol * sqrt(h2[1])) break;
+  }
+  s->nsel = keep_sel;
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(x, s->xr, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (res) {
+    *res = last;
+    res->outer_steps = steps;
+    res->inner_total = total;
+  }
+  return GSR_OK;
+}
+
+// ------------------------------------------------------------------ covariances
+extern "C" int64_t gsr_cov_bytes(int32_t version, int64_t itn_cov_cp, int64_t count) {
+  if ((version != 1 && version != 2) || itn_cov_cp < 0 || count < 0) return -1;
+  return 8 * itn_cov_cp * count;  // Eq. (5) with count = N_unk, Eq. (6) with count = N_cov,indexes
+}
+
+extern "C" int gsr_cov_request(gsr_system* s, const int64_t* sel, int64_t k, int32_t block) {
+  CHK(check_handle(s));
+  if (k < 0) return fail(GSR_EINVAL, "k < 0");
+  if (k > 0 && !sel) return fail(GSR_EINVAL, "sel is null");
+  if (block < 1 || block > 1024) return fail(GSR_EINVAL, "block must be in [1, 1024]");
+  for (int64_t p = 0; p < k; ++p)
+    if (sel[p] < 0 || sel[p] >= s->s.n) return fail(GSR_EINVAL, "sel[%lld] = %lld out of range", (long long)p,
+                                                     (long long)sel[p]);
+  (void)hipDeviceSynchronize();
+  dfree(s->sel);
+  dfree(s->D);
+  dfree(s->Cacc);
+  s->sel = nullptr;
+  s->D = nullptr;
+  s->Cacc = nullptr;
+  s->nsel = 0;
+  if (k == 0) return GSR_OK;
+  CHK(dalloc(&s->sel, (size_t)k));
+  CHK(dalloc(&s->D, (size_t)k * block));
+  CHK(dalloc(&s->Cacc, (size_t)k * k));
+  HIPCHK(hipMemcpy(s->sel, sel, (size_t)k * sizeof(int64_t), hipMemcpyHostToDevice));
+  HIPCHK(hipMemset(s->Cacc, 0, (size_t)k * k * sizeof(double)));
+  s->nsel = k;
+  s->dblock = block;
+  return GSR_OK;
+}
+
+extern "C" int gsr_cov_get(gsr_system* s, double* C, gsr_stream stream) {
+  CHK(check_handle(s));
+  if (s->nsel == 0) return fail(GSR_ESTATE, "no covariance selection");
+  NEED_DEV(C, "C");
+  HIPCHK(launch_cov_out(s->Cacc, s->nsel, s->cov_precond ? s->S : nullptr, s->sel, C, (hipStream_t)stream));
+  return GSR_OK;
+}
+
+extern "C" int gsr_syrk(const double* D, int64_t k, int64_t cols, int64_t ldd, double* C, gsr_stream stream) {
+  if (k < 0 || cols < 0 || ldd < cols) return fail(GSR_EINVAL, "need k >= 0, 0 <= cols <= ldd");
+  if (k == 0 || cols == 0) return GSR_OK;
+  NEED_DEV(D, "D");
+  NEED_DEV(C, "C");
+  Work none{};
+  HIPCHK(launch_syrk(D, k, ldd, C, nullptr, none, cols, (hipStream_t)stream));
+  return GSR_OK;
+}

@@ -1,0 +1,168 @@
+// Device helpers shared by the kernels: 16-byte streaming loads, wave and
+// workgroup reductions, the last-workgroup ticket, and the LSQR scalar
+// recurrences (Paige & Saunders 1982) run by that last workgroup.
+#pragma once
+
+#include "internal.h"
+
+namespace gsr {
+
+typedef unsigned u4 __attribute__((ext_vector_type(4)));
+typedef int i2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ u4 ld_stream(const u4* p) { return __builtin_nontemporal_load(p); }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Sum of one double per thread over a kBlock-thread workgroup, fixed order.
+// Every thread gets the result.  Uses `red` (kWavesPerBlock doubles of LDS).
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int i = 0; i < kWavesPerBlock; ++i) t += red[i];
+  return t;
+}
+
+// Publishes this workgroup's partial and returns true in the single workgroup
+// that finishes last; that workgroup then sees every other partial.
+__device__ __forceinline__ bool last_block(unsigned* ticket, int* flag_lds) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned t = atomicAdd(ticket, 1u);
+    *flag_lds = (t == gridDim.x - 1);
+  }
+  __syncthreads();
+  bool last = *flag_lds != 0;
+  if (last) __threadfence();
+  return last;
+}
+
+// Fixed-order sum of `n` partials by the whole workgroup.
+__device__ __forceinline__ double sum_partials(const double* p, int n, double* red) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += kBlock) v += __builtin_nontemporal_load(p + i);
+  return block_sum(v, red);
+}
+
+// ---- LSQR scalar steps (run by one thread) --------------------------------
+
+// beta_{i+1} = ||A v_i - alpha_i u_i|| (or beta_1 = ||b - A x0|| at init).
+__device__ inline void epi_beta(Scalars* sc, double sumsq, int init) {
+  const double beta = sqrt(sumsq);
+  sc->beta = beta;
+  if (init) {
+    sc->bnorm = beta;
+    sc->rnorm = beta;
+    sc->v_scale = 0.0;  // no previous v
+    sc->inv_beta = beta > 0.0 ? 1.0 / beta : 0.0;
+    sc->do_v = beta > 0.0;
+    if (!(beta > 0.0)) {
+      sc->alpha = 0.0;
+      sc->arnorm = 0.0;
+      sc->istop = 0;
+      sc->done = 1;
+    }
+    return;
+  }
+  if (beta > 0.0) {
+    const double a = sc->alpha;
+    sc->anorm2 = sc->anorm2 + a * a + beta * beta + sc->damp * sc->damp;
+    sc->inv_beta = 1.0 / beta;
+    sc->v_scale = -beta;
+    sc->do_v = 1;
+  } else {
+    sc->do_v = 0;
+  }
+}
+
+// alpha_{i+1} and the two plane rotations of iteration i.
+__device__ inline void epi_alpha(Scalars* sc, double sumsq, int init) {
+  if (init) {
+    const double alpha = sqrt(sumsq);
+    sc->alpha = alpha;
+    sc->inv_alpha = alpha > 0.0 ? 1.0 / alpha : 1.0;
+    sc->rhobar = alpha;
+    sc->phibar = sc->beta;
+    sc->arnorm = alpha * sc->beta;
+    sc->u_scale = sc->beta > 0.0 ? -alpha / sc->beta : 0.0;
+    if (sc->arnorm == 0.0) {
+      sc->istop = 0;
+      sc->done = 1;
+    }
+    return;
+  }
+  if (sc->do_v) {
+    const double alpha = sqrt(sumsq);
+    sc->alpha = alpha;
+    sc->inv_alpha = alpha > 0.0 ? 1.0 / alpha : 1.0;
+  } else {
+    sc->inv_alpha = 1.0;  // v untouched this iteration
+  }
+  const double alpha = sc->alpha, beta = sc->beta, damp = sc->damp;
+  double rhobar = sc->rhobar, phibar = sc->phibar;
+  double rhobar1, psi;
+  if (damp > 0.0) {
+    rhobar1 = sqrt(rhobar * rhobar + damp * damp);
+    const double cs1 = rhobar / rhobar1, sn1 = damp / rhobar1;
+    psi = sn1 * phibar;
+    phibar = cs1 * phibar;
+  } else {
+    rhobar1 = rhobar;
+    psi = 0.0;
+  }
+  const double rho = sqrt(rhobar1 * rhobar1 + beta * beta);
+  const double cs = rhobar1 / rho, sn = beta / rho;
+  const double theta = sn * alpha;
+  rhobar = -cs * alpha;
+  const double phi = cs * phibar;
+  phibar = sn * phibar;
+  const double tau = sn * phi;
+  sc->rhobar = rhobar;
+  sc->phibar = phibar;
+  sc->t1 = phi / rho;
+  sc->t2 = -theta / rho;
+  sc->t3 = 1.0 / rho;
+  sc->res2 = sc->res2 + psi * psi;
+  sc->rnorm = sqrt(phibar * phibar + sc->res2);
+  sc->arnorm = alpha * fabs(tau);
+  sc->u_scale = beta > 0.0 ? -alpha / beta : 0.0;
+}
+
+// Estimates and stopping tests after the x / w update of iteration i.
+__device__ inline void epi_update(Scalars* sc, double xsq, double ddsq) {
+  sc->itn = sc->itn + 1;
+  sc->xnorm = sqrt(xsq);
+  sc->ddnorm = sc->ddnorm + ddsq;
+  const double anorm = sqrt(sc->anorm2);
+  sc->acond = anorm * sqrt(sc->ddnorm);
+  const double bnorm = sc->bnorm, rnorm = sc->rnorm, xnorm = sc->xnorm;
+  const double test1 = rnorm / bnorm;
+  const double test2 = (anorm * rnorm > 0.0) ? sc->arnorm / (anorm * rnorm) : 0.0;
+  const double test3 = (sc->acond > 0.0) ? 1.0 / sc->acond : __builtin_inf();
+  const double tt1 = test1 / (1.0 + anorm * xnorm / bnorm);
+  const double rtol = sc->btol + sc->atol * anorm * xnorm / bnorm;
+  int istop = 0;
+  if (sc->itn >= sc->itmax) istop = 7;
+  if (1.0 + test3 <= 1.0) istop = 6;
+  if (1.0 + test2 <= 1.0) istop = 5;
+  if (1.0 + tt1 <= 1.0) istop = 4;
+  if (test3 <= sc->ctol) istop = 3;
+  if (test2 <= sc->atol) istop = 2;
+  if (test1 <= rtol) istop = 1;
+  if (istop) {
+    sc->istop = istop;
+    sc->done = 1;
+  }
+}
+
+}  // namespace gsr

@@ -1,0 +1,113 @@
+// Internal declarations shared by the HIP kernels and the C-ABI layer.
+// Not installed; the public interface is include/gsr.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gsr.h"
+
+namespace gsr {
+
+constexpr int kWave = 64;          // CDNA wavefront
+constexpr int kBlock = 256;        // threads per workgroup (4 waves)
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kSlots = 24;         // coefficients per row: 5 astro, 12 attitude, 6 instr, 1 global
+constexpr int kMaxPartials = 4096; // upper bound on workgroups of a reducing launch
+constexpr int kLdsTailMax = 2048;  // tail columns accumulated in LDS when they fit (16 KB)
+
+// Device-resident LSQR state.  Written only by the single "last" workgroup of
+// a launch (ticket pattern) or by the host before a solve; every other
+// workgroup reads it at kernel entry.
+struct Scalars {
+  // bidiagonalisation
+  double alpha, beta;        // alpha_i, beta_i (beta also the scale of the stored u)
+  double u_scale;            // -alpha_i / beta_i : aprod1 multiplier of the stored u
+  double inv_beta;           // 1 / beta_{i+1}    : aprod2 multiplier of u
+  double v_scale;            // -beta_{i+1}       : aprod2 multiplier of v_i
+  double inv_alpha;          // 1 / alpha_{i+1}   : update-pass normaliser of v
+  // rotations
+  double rhobar, phibar;
+  double t1, t2, t3;         // phi/rho, -theta/rho, 1/rho
+  // estimates
+  double anorm2, ddnorm, res2, xnorm, rnorm, arnorm, acond, bnorm;
+  // options
+  double damp, atol, btol, ctol;
+  int64_t itn, itmax;
+  int32_t istop;             // Paige-Saunders stop code
+  int32_t done;              // 1 once the solve has stopped (any reason)
+  int32_t do_v;              // 1 if aprod2 runs this iteration (beta_{i+1} > 0)
+  int32_t dcount;            // covariance columns buffered since the last SYRK flush
+  int64_t dblock;            // columns per covariance block
+  int64_t nsel;              // selected unknowns (0: no covariances)
+};
+
+// Reduction workspace: per-launch workgroup partials and tickets.
+struct Work {
+  double* part_a;            // [kMaxPartials] partial sums of a reducing launch
+  double* part_b;            // [kMaxPartials] second set (astro part of ||v||^2)
+  double* part_c;            // [kMaxPartials] third set (sum of d^2 in the update pass)
+  unsigned* tickets;         // [8] last-workgroup tickets, one per kernel kind
+};
+
+enum Ticket { T_APROD1 = 0, T_APROD2 = 1, T_TAIL = 2, T_UPDATE = 3, T_INIT = 4, T_SYRK = 5, T_VALID = 6 };
+
+// A borrowed view of the caller's system arrays plus the sizes derived from them.
+struct SysView {
+  int64_t n_stars, m, n_att, n_instr;
+  int32_t n_glob, value_type;
+  int64_t n_astro, tail_len, n;
+  const void* vals;
+  const int64_t* row_ptr;
+  const int32_t* att_start;
+  const int32_t* instr_col;
+  int32_t has_empty_stars;
+};
+
+// Launch shape of the row-streaming kernels: each wave owns a contiguous range
+// of whole stars holding about m / waves rows.
+struct StreamShape {
+  int blocks;
+  int waves;
+  int stage;  // 1: coefficient tiles staged through LDS, 0: direct row loads
+};
+StreamShape stream_shape(const SysView& s, int cus, int waves_per_cu, int stage);
+
+// ---- launchers (all asynchronous on `st`) ---------------------------------
+// y <- scale*y + ax * A x (or with the LSQR scalars: scale = sc->u_scale, ax = 1,
+// and the last workgroup forms beta_{i+1}); mode: 0 FP64 products, 1 FP32 products.
+hipError_t launch_aprod1(const SysView& s, StreamShape sh, const double* x, double* y, double scale,
+                         double ax, int pmode, Scalars* sc, Work w, int lsqr_stage, hipStream_t st);
+// astro part of x <- scale*x + S*(A^T (inv_beta*y)); tail part accumulated in acc.
+hipError_t launch_aprod2(const SysView& s, StreamShape sh, const double* y, double* x, double* acc,
+                         const double* S, double scale, double inv_beta, int pmode, int square,
+                         Scalars* sc, Work w, hipStream_t st);
+// tail part: x_t <- scale*x_t + S_t * acc_t, acc cleared; LSQR epilogue when sc != nullptr.
+hipError_t launch_tail(const SysView& s, double* x, double* acc, const double* S, double scale,
+                       int square, Scalars* sc, Work w, int lsqr_stage, int astro_parts,
+                       const int64_t* sel, const double* wv, double* D, hipStream_t st);
+// bad[0] <- first row with an out-of-range index, bad[1] <- first bad star, bad[2] <- 1 if a star is empty
+hipError_t launch_validate(const SysView& s, unsigned long long* bad, hipStream_t st);
+hipError_t launch_scale_from_sq(int64_t n, double* S, hipStream_t st);
+
+// LSQR vector kernels
+hipError_t launch_copy(const double* src, double* dst, int64_t n, hipStream_t st);
+hipError_t launch_norm_init(const double* u, int64_t m, Scalars* sc, Work w, hipStream_t st);
+hipError_t launch_init_vectors(int64_t n, double* v, double* vg, double* w, double* y, double* var,
+                               const double* S, Scalars* sc, hipStream_t st);
+hipError_t launch_update(int64_t n, double* v, double* vg, double* w, double* y, double* var,
+                         const double* S, Scalars* sc, Work w_, hipStream_t st);
+hipError_t launch_finish(int64_t n, const double* y, const double* var, const double* S, const double* x0,
+                         double* x_out, double* var_out, hipStream_t st);
+hipError_t launch_syrk(const double* D, int64_t k, int64_t ldd, double* C, Scalars* sc, Work w,
+                       int64_t fixed_cols, hipStream_t st);
+hipError_t launch_cov_out(const double* C, int64_t k, const double* S, const int64_t* sel, double* out,
+                          hipStream_t st);
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
+hipError_t launch_axpy_norms(int64_t n, const double* dx, double* x, double* out2, Work w, hipStream_t st);
+int tail_mode_of(const SysView& s);
+
+// number of compute units of the current device (cached)
+int device_cus();
+
+}  // namespace gsr

@@ -1,0 +1,282 @@
+// n-sized LSQR passes (initial vectors, the per-iteration x / w / variance
+// update, de-preconditioning), the covariance SYRK on FP64 MFMA, and small
+// utility kernels.  Scalar recurrences run in the last workgroup of each
+// reducing launch (device_common.h), so the host never waits inside a solve.
+#include <algorithm>
+
+#include "device_common.h"
+
+namespace gsr {
+
+static int blocks_for(int64_t n, int cap = 2048) {
+  return (int)std::min<int64_t>(cap, std::max<int64_t>(1, (n + kBlock - 1) / kBlock));
+}
+
+__global__ void k_fill(double* __restrict__ p, int64_t n, double v) {
+  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) p[j] = v;
+}
+
+__global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
+  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) b[j] = a[j];
+}
+
+// beta_1 = ||u|| for u = b (or b - A x0); the last workgroup starts the recurrences.
+__global__ void __launch_bounds__(kBlock) k_norm_init(const double* __restrict__ u, int64_t m, Scalars* sc, Work wk) {
+  __shared__ double red[kWavesPerBlock];
+  __shared__ int flag;
+  double s = 0.0;
+  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < m; j += (int64_t)gridDim.x * kBlock) {
+    const double v = u[j];
+    s += v * v;
+  }
+  const double bs = block_sum(s, red);
+  if (threadIdx.x == 0) wk.part_a[blockIdx.x] = bs;
+  if (last_block(wk.tickets + T_INIT, &flag)) {
+    const double tot = sum_partials(wk.part_a, gridDim.x, red);
+    if (threadIdx.x == 0) {
+      epi_beta(sc, tot, 1);
+      wk.tickets[T_INIT] = 0;
+    }
+  }
+}
+
+// v_1 = (S A^T u_1) / alpha_1, its scaled copy for the gathers of aprod 1,
+// w_1 = v_1, y = 0, var = 0.
+__global__ void k_init_vectors(int64_t n, double* __restrict__ v, double* __restrict__ vg, double* __restrict__ w,
+                               double* __restrict__ y, double* __restrict__ var, const double* __restrict__ S,
+                               const Scalars* sc) {
+  const double ia = sc->do_v ? sc->inv_alpha : 1.0;
+  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) {
+    const double vj = sc->do_v ? v[j] * ia : 0.0;
+    v[j] = vj;
+    if (S) vg[j] = S[j] * vj;
+    w[j] = vj;
+    y[j] = 0.0;
+    var[j] = 0.0;
+  }
+}
+
+// Iteration i, after alpha_{i+1} and the rotations are known:
+//   v <- v / alpha_{i+1};  d = w / rho;  y += (phi/rho) w;  var += d^2;
+//   w <- v - (theta/rho) w;  partial sums of ||y||^2 and ||d||^2.
+// The last workgroup evaluates the stopping tests.
+__global__ void __launch_bounds__(kBlock) k_update(int64_t n, double* __restrict__ v, double* __restrict__ vg,
+                                                   double* __restrict__ w, double* __restrict__ y,
+                                                   double* __restrict__ var, const double* __restrict__ S,
+                                                   Scalars* sc, Work wk) {
+  __shared__ double red[kWavesPerBlock];
+  __shared__ int flag;
+  if (sc->done) return;
+  const double ia = sc->inv_alpha, t1 = sc->t1, t2 = sc->t2, t3 = sc->t3;
+  double xs = 0.0, ds = 0.0;
+  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) {
+    const double vj = v[j] * ia;
+    v[j] = vj;
+    if (S) vg[j] = S[j] * vj;
+    const double wj = w[j];
+    const double d = t3 * wj;
+    const double yj = y[j] + t1 * wj;
+    y[j] = yj;
+    var[j] = var[j] + d * d;
+    w[j] = vj + t2 * wj;
+    xs += yj * yj;
+    ds += d * d;
+  }
+  const double bx = block_sum(xs, red);
+  const double bd = block_sum(ds, red);
+  if (threadIdx.x == 0) {
+    wk.part_a[blockIdx.x] = bx;
+    wk.part_c[blockIdx.x] = bd;
+  }
+  if (last_block(wk.tickets + T_UPDATE, &flag)) {
+    const double tx = sum_partials(wk.part_a, gridDim.x, red);
+    const double td = sum_partials(wk.part_c, gridDim.x, red);
+    if (threadIdx.x == 0) {
+      epi_update(sc, tx, td);
+      wk.tickets[T_UPDATE] = 0;
+    }
+  }
+}
+
+// x = x0 + S y, var_out = S^2 var (de-preconditioning, the solver's last step).
+__global__ void k_finish(int64_t n, const double* __restrict__ y, const double* __restrict__ var,
+                         const double* __restrict__ S, const double* __restrict__ x0, double* __restrict__ x,
+                         double* __restrict__ vo) {
+  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) {
+    const double s = S ? S[j] : 1.0;
+    if (x) x[j] = (x0 ? x0[j] : 0.0) + s * y[j];
+    if (vo) vo[j] = (s * s) * var[j];
+  }
+}
+
+// ---------------------------------------------------------------- SYRK
+// C += D D^T over the first `cols` columns of D ([k][ldd], row-major), on the
+// upper triangle of 32 x 32 tiles of C ([k][k], row-major).  One wave per
+// tile, 2 x 2 blocks of v_mfma_f64_16x16x4f64.  The k index of an MFMA step
+// is permuted (lane group g holds columns 16g + s at step s) so that every
+// lane reads 16 consecutive doubles of a D row; A and B use the same
+// permutation, so the contraction is unchanged.
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(kBlock) k_syrk(const double* __restrict__ D, int64_t k, int64_t ldd,
+                                                 double* __restrict__ C, Scalars* sc, Work wk, int64_t fixed_cols,
+                                                 int64_t T, int64_t ntiles) {
+  __shared__ int flag;
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int64_t cols = fixed_cols >= 0 ? fixed_cols : (int64_t)sc->dcount;
+  const int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + wid;
+  if (tile < ntiles && cols > 0) {
+    int64_t ti = 0, rem = tile;
+    while (rem >= T - ti) {
+      rem -= T - ti;
+      ++ti;
+    }
+    const int64_t tj = ti + rem;
+    const int64_t row0 = ti * 32, col0 = tj * 32;
+    const int i16 = lane & 15, g = lane >> 4;
+    d4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int64_t kc = 0; kc < cols; kc += 64) {
+      double av[2][16], bv[2][16];
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi) {
+        const int64_t ra = row0 + 16 * bi + i16, rb = col0 + 16 * bi + i16;
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+          const int64_t kk = kc + 16 * g + s;
+          av[bi][s] = (ra < k && kk < cols) ? D[ra * ldd + kk] : 0.0;
+          bv[bi][s] = (rb < k && kk < cols) ? D[rb * ldd + kk] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < 16; ++s)
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj)
+            acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bi][s], bv[bj][s], acc[bi][bj], 0, 0, 0);
+    }
+    // accumulator layout: element e of lane l is row 4*(l/16)+e, column l%16
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t r = row0 + 16 * bi + 4 * g + e, c = col0 + 16 * bj + i16;
+          if (r < k && c < k) C[r * k + c] += acc[bi][bj][e];
+        }
+  }
+  if (fixed_cols < 0) {
+    if (last_block(wk.tickets + T_SYRK, &flag) && threadIdx.x == 0) {
+      sc->dcount = 0;
+      wk.tickets[T_SYRK] = 0;
+    }
+  }
+}
+
+// out[p][q] = s_p s_q C[min(p,q)][max(p,q)], s = column scaling at the selected unknowns.
+__global__ void k_cov_out(const double* __restrict__ C, int64_t k, const double* __restrict__ S,
+                          const int64_t* __restrict__ sel, double* __restrict__ out) {
+  const int64_t n = k * k;
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (int64_t)gridDim.x * kBlock) {
+    const int64_t p = e / k, q = e - p * k;
+    const double c = (p <= q) ? C[p * k + q] : C[q * k + p];
+    const double s = S ? S[sel[p]] * S[sel[q]] : 1.0;
+    out[e] = s * c;
+  }
+}
+
+// dx accumulation of an outer refinement step: x += dx, partial ||dx||^2 and ||x||^2.
+__global__ void __launch_bounds__(kBlock) k_axpy_norms(int64_t n, const double* __restrict__ dx,
+                                                       double* __restrict__ x, double* out2, Work wk) {
+  __shared__ double red[kWavesPerBlock];
+  __shared__ int flag;
+  double a = 0.0, b = 0.0;
+  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) {
+    const double d = dx[j];
+    const double xn = x[j] + d;
+    x[j] = xn;
+    a += d * d;
+    b += xn * xn;
+  }
+  const double ba = block_sum(a, red);
+  const double bb = block_sum(b, red);
+  if (threadIdx.x == 0) {
+    wk.part_a[blockIdx.x] = ba;
+    wk.part_c[blockIdx.x] = bb;
+  }
+  if (last_block(wk.tickets + T_VALID, &flag)) {
+    const double ta = sum_partials(wk.part_a, gridDim.x, red);
+    const double tb = sum_partials(wk.part_c, gridDim.x, red);
+    if (threadIdx.x == 0) {
+      out2[0] = ta;
+      out2[1] = tb;
+      wk.tickets[T_VALID] = 0;
+    }
+  }
+}
+
+// ------------------------------------------------------------ launchers
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3(blocks_for(n)), dim3(kBlock), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const double* src, double* dst, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy, dim3(blocks_for(n)), dim3(kBlock), 0, st, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_norm_init(const double* u, int64_t m, Scalars* sc, Work w, hipStream_t st) {
+  hipLaunchKernelGGL(k_norm_init, dim3(blocks_for(m)), dim3(kBlock), 0, st, u, m, sc, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_vectors(int64_t n, double* v, double* vg, double* w, double* y, double* var, const double* S,
+                               Scalars* sc, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_vectors, dim3(blocks_for(n)), dim3(kBlock), 0, st, n, v, vg, w, y, var, S, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_update(int64_t n, double* v, double* vg, double* w, double* y, double* var, const double* S,
+                         Scalars* sc, Work w_, hipStream_t st) {
+  hipLaunchKernelGGL(k_update, dim3(blocks_for(n)), dim3(kBlock), 0, st, n, v, vg, w, y, var, S, sc, w_);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish(int64_t n, const double* y, const double* var, const double* S, const double* x0,
+                         double* x_out, double* var_out, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_finish, dim3(blocks_for(n)), dim3(kBlock), 0, st, n, y, var, S, x0, x_out, var_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_syrk(const double* D, int64_t k, int64_t ldd, double* C, Scalars* sc, Work w, int64_t fixed_cols,
+                       hipStream_t st) {
+  const int64_t T = (k + 31) / 32;
+  const int64_t ntiles = T * (T + 1) / 2;
+  const int64_t blocks = std::max<int64_t>(1, (ntiles + kWavesPerBlock - 1) / kWavesPerBlock);
+  hipLaunchKernelGGL(k_syrk, dim3((unsigned)blocks), dim3(kBlock), 0, st, D, k, ldd, C, sc, w, fixed_cols, T,
+                     ntiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_cov_out(const double* C, int64_t k, const double* S, const int64_t* sel, double* out,
+                          hipStream_t st) {
+  if (k <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cov_out, dim3(blocks_for(k * k)), dim3(kBlock), 0, st, C, k, S, sel, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_norms(int64_t n, const double* dx, double* x, double* out2, Work w, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpy_norms, dim3(blocks_for(n)), dim3(kBlock), 0, st, n, dx, x, out2, w);
+  return hipGetLastError();
+}
+
+}  // namespace gsr

@@ -1,0 +1,208 @@
+"""Parity of the device-resident LSQR (variances, covariances, FP32 form with
+refinement) with the CPU oracle.
+
+LSQR iterates past the point where the Krylov basis loses orthogonality are
+themselves sensitive to rounding (the oracle perturbed at the last bit of b
+moves them by up to ~1e-8 on the unscaled 1,000-star system).  Converged
+solutions are held to 1e-10; fixed-count runs are held to 1e-12 or, when
+the oracle's own sensitivity is larger, to 20x that sensitivity."""
+import numpy as np
+import pytest
+import torch
+
+import gsr_synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import paper_2503_22863_amd as gsr
+
+    gsr.lib()
+    return gsr
+
+
+@pytest.fixture(scope="module")
+def tiny(dev, oracle_lib):
+    g = gsr_synth.tiny()
+    o = oracle_lib.OSystem(g)
+    b = oracle_lib.known_terms(o, g.x_true, g.noise)
+    S = dev.System.from_generated(g)
+    return g, o, b, S
+
+
+def _sensitivity(oracle_lib, o, b, **kw):
+    r1 = oracle_lib.lsqr(o, b, **kw)
+    bp = b * (1 + 2e-16 * np.random.default_rng(5).standard_normal(b.size))
+    r2 = oracle_lib.lsqr(o, bp, **kw)
+    return r1, _rel(r2["x"], r1["x"]), _rel(r2["var"], r1["var"])
+
+
+def test_lsqr_converged_tiny_precond(dev, oracle_lib, tiny):
+    print("[lsqr] tiny, column-scaled, to tolerance", flush=True)
+    g, o, b, S = tiny
+    ref = oracle_lib.lsqr(o, b, atol=1e-12, btol=1e-12, itmax=200, precond=True)
+    x, var, r = S.lsqr_solve(torch.from_numpy(b).cuda(), atol=1e-12, btol=1e-12, itmax=200, precond=True)
+    x, var = x.cpu().numpy(), var.cpu().numpy()
+    print(f"  gpu istop={r['istop']} itn={r['itn']}  oracle istop={ref['istop']} itn={ref['itn']}", flush=True)
+    assert r["istop"] == ref["istop"]
+    assert abs(r["itn"] - ref["itn"]) <= 1
+    assert _rel(x, ref["x"]) <= 1e-10
+    assert _rel(var, ref["var"]) <= 1e-6
+    for k in ("rnorm", "arnorm", "anorm", "acond", "xnorm", "bnorm"):
+        assert abs(r[k] - ref[k]) <= 1e-6 * abs(ref[k]) + 1e-300, k
+
+
+@pytest.mark.parametrize("precond,itmax", [(True, 5), (True, 30), (False, 20)])
+def test_lsqr_fixed_iterations(dev, oracle_lib, tiny, precond, itmax):
+    print(f"[lsqr] tiny fixed count precond={precond} itmax={itmax}", flush=True)
+    g, o, b, S = tiny
+    ref, sx, sv = _sensitivity(oracle_lib, o, b, atol=0, btol=0, itmax=itmax, precond=precond)
+    x, var, r = S.lsqr_solve(torch.from_numpy(b).cuda(), atol=0, btol=0, itmax=itmax, precond=precond)
+    assert r["itn"] == itmax and r["istop"] == 7
+    assert _rel(x.cpu().numpy(), ref["x"]) <= max(1e-12, 20 * sx)
+    assert _rel(var.cpu().numpy(), ref["var"]) <= max(1e-12, 20 * sv)
+
+
+def test_lsqr_unscaled_as_written(dev, oracle_lib, tiny):
+    """The 1,000-star system without scaling, damp 0, atol = btol = 1e-12, itmax 200."""
+    print("[lsqr] tiny unscaled itmax=200", flush=True)
+    g, o, b, S = tiny
+    ref, sx, _ = _sensitivity(oracle_lib, o, b, atol=1e-12, btol=1e-12, itmax=200, precond=False)
+    x, _, r = S.lsqr_solve(torch.from_numpy(b).cuda(), atol=1e-12, btol=1e-12, itmax=200, precond=False)
+    print(f"  oracle self-sensitivity {sx:.2e}; gpu istop={r['istop']} itn={r['itn']}", flush=True)
+    assert r["istop"] == ref["istop"] == 7
+    assert _rel(x.cpu().numpy(), ref["x"]) <= max(1e-12, 20 * sx)
+
+
+def test_lsqr_damped_and_warm_start(dev, oracle_lib):
+    print("[lsqr] damp > 0, warm start", flush=True)
+    g = gsr_synth.make_system(300, (10, 30), 20, 10, 1, seed=12)
+    o = oracle_lib.OSystem(g)
+    b = oracle_lib.known_terms(o, g.x_true, g.noise)
+    S = dev.System.from_generated(g)
+    bt = torch.from_numpy(b).cuda()
+    ref = oracle_lib.lsqr(o, b, damp=0.3, atol=1e-13, btol=1e-13, itmax=1000, precond=True)
+    x, _, r = S.lsqr_solve(bt, damp=0.3, atol=1e-13, btol=1e-13, itmax=1000, precond=True)
+    assert _rel(x.cpu().numpy(), ref["x"]) <= 1e-10
+    x0 = ref["x"] + 1e-3 * np.random.default_rng(0).standard_normal(g.dims.n)
+    ref0 = oracle_lib.lsqr(o, b, x0=x0, atol=1e-13, btol=1e-13, itmax=1000, precond=True)
+    x, _, r = S.lsqr_solve(bt, x0=torch.from_numpy(x0).cuda(), atol=1e-13, btol=1e-13, itmax=1000, precond=True)
+    assert _rel(x.cpu().numpy(), ref0["x"]) <= 1e-10
+    assert abs(r["itn"] - ref0["itn"]) <= 1
+    S.close()
+
+
+def test_lsqr_edge_cases(dev, oracle_lib):
+    print("[lsqr] b = 0, itmax = 0, exact x0", flush=True)
+    g = gsr_synth.make_system(50, 8, 8, 6, 1, seed=13)
+    o = oracle_lib.OSystem(g)
+    S = dev.System.from_generated(g)
+    z = torch.zeros(g.dims.m, dtype=torch.float64, device="cuda")
+    x, var, r = S.lsqr_solve(z, itmax=50)
+    assert r["istop"] == 0 and r["itn"] == 0 and torch.all(x == 0) and torch.all(var == 0)
+    b = oracle_lib.known_terms(o, g.x_true, g.noise)
+    x, _, r = S.lsqr_solve(torch.from_numpy(b).cuda(), itmax=0)
+    assert r["itn"] == 0 and torch.all(x == 0)
+    b0 = oracle_lib.known_terms(o, g.x_true, np.zeros(g.dims.m))
+    x0 = torch.from_numpy(g.x_true).cuda()
+    x, _, r = S.lsqr_solve(torch.from_numpy(b0).cuda(), x0=x0, itmax=50)
+    assert r["itn"] == 0 and torch.equal(x, x0)
+    S.close()
+
+
+def test_identity_solution(dev, oracle_lib):
+    """Sec. 3: x_true = 1 and noise-free known terms give the identity solution."""
+    print("[lsqr] identity solution", flush=True)
+    g = gsr_synth.tiny(x_kind="ones", noise_std=0.0)
+    o = oracle_lib.OSystem(g)
+    b = oracle_lib.known_terms(o, g.x_true, g.noise)
+    S = dev.System.from_generated(g)
+    x, _, r = S.lsqr_solve(torch.from_numpy(b).cuda(), atol=1e-12, btol=1e-12, itmax=500, precond=True)
+    assert r["istop"] == 1
+    assert float((x - 1).abs().max()) < 1e-9
+    S.close()
+
+
+def test_session_api_matches_solve(dev, oracle_lib, tiny):
+    print("[lsqr] begin / iterate / peek / end", flush=True)
+    g, o, b, S = tiny
+    bt = torch.from_numpy(b).cuda()
+    S.lsqr_begin(bt, atol=0, btol=0, itmax=40, precond=True)
+    S.lsqr_iterate(10)
+    st = S.lsqr_status()
+    assert st["itn"] == 10
+    xp = S.lsqr_peek().cpu().numpy()
+    ref10 = oracle_lib.lsqr(o, b, atol=0, btol=0, itmax=10, precond=True)
+    assert _rel(xp, ref10["x"]) <= 1e-12
+    S.lsqr_iterate(100)  # capped by itmax
+    x, var, r = S.lsqr_end()
+    assert r["itn"] == 40 and r["istop"] == 7
+    with pytest.raises(dev.GsrError):
+        S.lsqr_iterate(1)
+
+
+@pytest.mark.parametrize("block", [64, 7])
+def test_covariances(dev, oracle_lib, block):
+    print(f"[cov] block={block}", flush=True)
+    g = gsr_synth.make_system(400, 20, 32, 16, 1, seed=14)
+    o = oracle_lib.OSystem(g)
+    b = oracle_lib.known_terms(o, g.x_true, g.noise)
+    sel = gsr_synth.covariance_selection(g.dims, 30, 10, 8, seed=3)
+    S = dev.System.from_generated(g)
+    S.cov_request(sel, block=block)
+    itmax = 45  # below convergence: a stable comparison, and not a multiple of the block
+    ref = oracle_lib.lsqr(o, b, atol=0, btol=0, itmax=itmax, precond=True, sel=sel)
+    x, var, r = S.lsqr_solve(torch.from_numpy(b).cuda(), atol=0, btol=0, itmax=itmax, precond=True)
+    Cg = S.cov_get().cpu().numpy()
+    assert _rel(Cg, ref["cov"]) <= 1e-12
+    np.testing.assert_array_equal(Cg, Cg.T)
+    assert _rel(np.diag(Cg), var.cpu().numpy()[sel]) <= 1e-13
+    S.close()
+
+
+def test_syrk_entry_point(dev):
+    """C += D D^T on the upper tiles for ragged sizes and column counts."""
+    print("[syrk]", flush=True)
+    rng = np.random.default_rng(7)
+    for k, cols, ldd in [(1, 1, 1), (37, 5, 9), (100, 64, 64), (130, 150, 160)]:
+        D = rng.standard_normal((k, ldd))
+        C0 = rng.standard_normal((k, k))
+        Ct = torch.from_numpy(C0.copy()).cuda()
+        dev.syrk(torch.from_numpy(D).cuda(), k, cols, ldd, Ct)
+        ref = C0 + D[:, :cols] @ D[:, :cols].T
+        got = Ct.cpu().numpy()
+        T = (k + 31) // 32
+        for ti in range(T):
+            for tj in range(T):
+                blk = (slice(32 * ti, 32 * ti + 32), slice(32 * tj, 32 * tj + 32))
+                if ti <= tj:
+                    np.testing.assert_allclose(got[blk], ref[blk], rtol=1e-13, atol=1e-12)
+                else:
+                    np.testing.assert_array_equal(got[blk], C0[blk])
+
+
+def test_fp32_refinement(dev, oracle_lib):
+    print("[fp32 refine] tiny", flush=True)
+    g = gsr_synth.tiny().as_f32()
+    o = oracle_lib.OSystem(g)
+    b = oracle_lib.known_terms(o, g.x_true, g.noise)
+    ref = oracle_lib.lsqr(o, b, atol=1e-14, btol=1e-14, itmax=1000, precond=True)
+    S = dev.System.from_generated(g)
+    bt = torch.from_numpy(b).cuda()
+    # inner LSQR with FP32 products alone: parity with the oracle's FP32-product LSQR
+    ref32 = oracle_lib.lsqr(o, b, atol=1e-6, btol=1e-6, itmax=1000, precond=True, mode=oracle_lib.P32)
+    x32, _, r32 = S.lsqr_solve(bt, atol=1e-6, btol=1e-6, itmax=1000, precond=True, product="f32")
+    assert abs(r32["itn"] - ref32["itn"]) <= 1
+    assert _rel(x32.cpu().numpy(), ref32["x"]) <= 1e-10
+    xr, rr = S.lsqr_refine(bt, atol=1e-6, btol=1e-6, itmax=1000, precond=True, outer_max=10, outer_tol=1e-11)
+    e = _rel(xr.cpu().numpy(), ref["x"])
+    print(f"  refined error {e:.2e} after {rr['outer_steps']} outer / {rr['inner_total']} inner", flush=True)
+    assert e <= 1e-10
+    S.close()
