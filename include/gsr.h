@@ -196,8 +196,12 @@ int64_t gsr_cov_bytes(int32_t version, int64_t itn_cov_cp, int64_t count);
  */
 int gsr_syrk(const double *D, int64_t k, int64_t cols, int64_t ldd, double *C, gsr_stream stream);
 
-/* Launch tuning of the row-streaming kernels (waves per CU, LDS staging on/off). */
-int gsr_set_tuning(gsr_system *sys, int32_t waves_per_cu, int32_t stage);
+/* Launch tuning of the row-streaming kernels: waves per CU (1..256), LDS
+ * staging of coefficient tiles (stage 0/1), attitude sums of aprod 2 into one
+ * private copy per XCD instead of one shared copy (xcd_copies 0/1; only used
+ * when the attitude block does not fit in LDS).  Results are unchanged up to
+ * the order of the atomic FP64 additions. */
+int gsr_set_tuning(gsr_system *sys, int32_t waves_per_cu, int32_t stage, int32_t xcd_copies);
 
 /* Per-kernel timing with HIP events on the solve's stream (off by default).
  * gsr_timing_get synchronises, returns the totals since the last get and
@@ -208,6 +212,48 @@ typedef struct {
 } gsr_timing;
 int gsr_timing_enable(gsr_system *sys, int32_t on);
 int gsr_timing_get(gsr_system *sys, gsr_timing *t);
+
+/*
+ * Learned warm start.  Not part of the paper's method: a per-star regression
+ * from system features to the 5 astrometric unknowns, used only to choose
+ * x0 for gsr_lsqr_solve (LSQR from x0 converges to the same solution).
+ *
+ * gsr_features: F device [n_stars][28] FP64 per star s:
+ *   [0..14] upper triangle (row-major) of A_s^T A_s, A_s = the star's rows on its
+ *   5 astrometric columns; [15..19] A_s^T bt, bt = b - A_other x_other (the known
+ *   terms minus the attitude / instrumental / global part at x_other);
+ *   [20] rows; [21] mean(att_start)/n_att; [22] population std of att_start/n_att;
+ *   [23] rms attitude coefficient; [24] rms instrumental; [25] rms global (0 if none);
+ *   [26] ||bt_s||/sqrt(rows); [27] sum_r a_glob bt_r / rows.
+ *   b device [m], x_other device [n - 5*n_stars].
+ * gsr_mean_rows: out[j] = mean_i X[i][j]; X device [k][len], out device [len].
+ */
+int gsr_features(gsr_system *sys, const double *b, const double *x_other, double *F, gsr_stream stream);
+int gsr_mean_rows(const double *X, int64_t k, int64_t len, double *out, gsr_stream stream);
+
+/*
+ * FP32 network n_in -> n_hidden -> n_hidden -> n_out with ReLU on the hidden
+ * layers.  params (host, FP64, copied and rounded to FP32):
+ * W1 [n_hidden][n_in], b1, W2 [n_hidden][n_hidden], b2, W3 [n_out][n_hidden], b3.
+ * Inputs and targets are standardised with the column mean / population
+ * standard deviation set by gsr_mlp_fit_norm (identity until then).
+ *   forward: X device [N][n_in] FP64 -> Y device [N][n_out] FP64 (de-standardised).
+ *   grad: mean squared error on the standardised targets and its gradient with
+ *         respect to every parameter (device FP32 [param count], same order as
+ *         params) without updating; loss to *loss_host.  Synchronous.
+ *   train: `steps` full-batch Adam steps (beta1 0.9, beta2 0.999, eps 1e-8,
+ *          learning rate lr); final loss to *loss_host.  Synchronous.
+ *   get_params: host FP64 copy of the current parameters.
+ */
+int gsr_mlp_create(gsr_mlp **out, int32_t n_in, int32_t n_hidden, int32_t n_out, const double *params);
+int gsr_mlp_destroy(gsr_mlp *net);
+int gsr_mlp_get_params(gsr_mlp *net, double *params);
+int gsr_mlp_fit_norm(gsr_mlp *net, const double *X, const double *T, int64_t N, gsr_stream stream);
+int gsr_mlp_forward(gsr_mlp *net, const double *X, int64_t N, double *Y, gsr_stream stream);
+int gsr_mlp_grad(gsr_mlp *net, const double *X, const double *T, int64_t N, double *loss_host, float *grads,
+                 gsr_stream stream);
+int gsr_mlp_train(gsr_mlp *net, const double *X, const double *T, int64_t N, int32_t steps, double lr,
+                  double *loss_host, gsr_stream stream);
 
 #ifdef __cplusplus
 }

@@ -79,9 +79,20 @@ _SIGS = {
     "gsr_cov_get": (C.c_int, [C.c_void_p] * 3),
     "gsr_cov_bytes": (C.c_int64, [C.c_int32, C.c_int64, C.c_int64]),
     "gsr_syrk": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p]),
-    "gsr_set_tuning": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "gsr_set_tuning": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]),
     "gsr_timing_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "gsr_timing_get": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "gsr_features": (C.c_int, [C.c_void_p] * 5),
+    "gsr_mean_rows": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p]),
+    "gsr_mlp_create": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p]),
+    "gsr_mlp_destroy": (C.c_int, [C.c_void_p]),
+    "gsr_mlp_get_params": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "gsr_mlp_fit_norm": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
+    "gsr_mlp_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    "gsr_mlp_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                               C.c_void_p]),
+    "gsr_mlp_train": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_double,
+                                C.c_void_p, C.c_void_p]),
 }
 
 
@@ -141,6 +152,70 @@ def cov_bytes(version, itn_cov_cp, count):
 
 def syrk(D, k, cols, ldd, Cmat, stream=None):
     _check(lib().gsr_syrk(_ptr(D), k, cols, ldd, _ptr(Cmat), _stream(stream)))
+
+
+def mean_rows(X, stream=None):
+    """Mean of the k rows of a [k][len] device matrix (e.g. the mean of training solutions)."""
+    k, ln = X.shape
+    out = torch.empty(ln, dtype=torch.float64, device=X.device)
+    _check(lib().gsr_mean_rows(_ptr(X), k, ln, _ptr(out), _stream(stream)))
+    return out
+
+
+class MLP:
+    """FP32 network n_in -> hidden -> hidden -> n_out (ReLU), trained on the device with Adam.
+    params: [W1 (H,I), b1, W2 (H,H), b2, W3 (O,H), b3] (host numpy, any float dtype)."""
+
+    def __init__(self, params):
+        W1, b1, W2, b2, W3, b3 = params
+        self.n_in, self.n_hidden, self.n_out = W1.shape[1], W1.shape[0], W3.shape[0]
+        flat = np.ascontiguousarray(np.concatenate([np.asarray(p, dtype=np.float64).reshape(-1) for p in params]))
+        self.size = flat.size
+        h = C.c_void_p()
+        _check(lib().gsr_mlp_create(C.byref(h), self.n_in, self.n_hidden, self.n_out, flat.ctypes.data))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(lib().gsr_mlp_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self):
+        flat = np.empty(self.size)
+        _check(lib().gsr_mlp_get_params(self._h, flat.ctypes.data))
+        I, H, O = self.n_in, self.n_hidden, self.n_out
+        out, o = [], 0
+        for shp in ((H, I), (H,), (H, H), (H,), (O, H), (O,)):
+            k = int(np.prod(shp))
+            out.append(flat[o:o + k].reshape(shp))
+            o += k
+        return out
+
+    def fit_norm(self, X, T, stream=None):
+        _check(lib().gsr_mlp_fit_norm(self._h, _ptr(X), _ptr(T), X.shape[0], _stream(stream)))
+
+    def forward(self, X, stream=None):
+        Y = torch.empty((X.shape[0], self.n_out), dtype=torch.float64, device=X.device)
+        _check(lib().gsr_mlp_forward(self._h, _ptr(X), X.shape[0], _ptr(Y), _stream(stream)))
+        return Y
+
+    def grad(self, X, T, stream=None):
+        g = torch.empty(self.size, dtype=torch.float32, device=X.device)
+        loss = C.c_double()
+        _check(lib().gsr_mlp_grad(self._h, _ptr(X), _ptr(T), X.shape[0], C.byref(loss), _ptr(g), _stream(stream)))
+        return loss.value, g
+
+    def train(self, X, T, steps, lr=1e-3, stream=None):
+        loss = C.c_double()
+        _check(lib().gsr_mlp_train(self._h, _ptr(X), _ptr(T), X.shape[0], int(steps), float(lr), C.byref(loss),
+                                   _stream(stream)))
+        return loss.value
 
 
 def _opts(damp=0.0, atol=1e-12, btol=1e-12, conlim=0.0, itmax=200, precond=True, product="f64",
@@ -278,9 +353,16 @@ class System:
         _check(lib().gsr_cov_get(self._h, _ptr(out), _stream(stream)))
         return out
 
+    # ---- learned warm start
+    def features(self, b, x_other, stream=None):
+        """Per-star features [n_stars, 28] (FP64) with bt = b - A_other x_other."""
+        F = torch.empty((self.n_stars, 28), dtype=torch.float64, device=self.device)
+        _check(lib().gsr_features(self._h, _ptr(b), _ptr(x_other), _ptr(F), _stream(stream)))
+        return F
+
     # ---- tuning and timing
-    def set_tuning(self, waves_per_cu, stage):
-        _check(lib().gsr_set_tuning(self._h, int(waves_per_cu), int(stage)))
+    def set_tuning(self, waves_per_cu, stage, xcd_copies=0):
+        _check(lib().gsr_set_tuning(self._h, int(waves_per_cu), int(stage), int(xcd_copies)))
 
     def timing_enable(self, on=True):
         _check(lib().gsr_timing_enable(self._h, int(bool(on))))

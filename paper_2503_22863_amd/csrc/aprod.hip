@@ -185,6 +185,10 @@ __global__ void __launch_bounds__(kBlock) k_aprod1(SysView s, int waves, const d
 // ---------------------------------------------------------------- aprod2
 // tail_mode 0: the whole tail (attitude, instrumental, global) in LDS.
 // tail_mode 1: attitude by device-scope atomics, instrumental + global in LDS.
+// tail_mode 2: attitude by atomics into a private copy per XCD (each XCD has
+//   its own L2; the copy of XCD x is only touched by waves running on x, so
+//   the atomics stay in that L2), instrumental + global in LDS.  The tail
+//   pass adds the copies.
 template <typename VT, int STAGE>
 __global__ void __launch_bounds__(kBlock) k_aprod2(SysView s, int waves, const double* __restrict__ y,
                                                    double* __restrict__ x, double* __restrict__ acc,
@@ -203,6 +207,8 @@ __global__ void __launch_bounds__(kBlock) k_aprod2(SysView s, int waves, const d
   // LDS-private tail: [0, 3*n_att) attitude (mode 0 only), then instr, then global
   const int64_t hoff = (tail_mode == 0) ? 0 : 3 * s.n_att;  // tail index of hist[0]
   const int64_t hlen = s.tail_len - hoff;
+  double* acc_att = acc;
+  if (tail_mode == 2) acc_att = acc + s.tail_len + (int64_t)xcc_id() * 3 * s.n_att;
   for (int64_t j = threadIdx.x; j < hlen; j += kBlock) hist[j] = 0.0;
   __syncthreads();
 
@@ -244,8 +250,10 @@ __global__ void __launch_bounds__(kBlock) k_aprod2(SysView s, int waves, const d
             const double c = square ? (double)av * (double)av : prod<VT>(av, t, pmode);
             if (tail_mode == 0)
               atomicAdd(hist + col + j, c);
+            else if (tail_mode == 1)
+              atomicAdd(acc_att + col + j, c);
             else
-              atomicAdd(acc + col + j, c);
+              __hip_atomic_fetch_add(acc_att + col + j, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
           }
         }
 #pragma unroll
@@ -337,7 +345,7 @@ struct TailLsqr {
 
 __global__ void __launch_bounds__(kBlock) k_tail(SysView s, double* __restrict__ x, double* __restrict__ acc,
                                                  const double* __restrict__ S, double scale, Scalars* sc, Work wk,
-                                                 TailLsqr L) {
+                                                 TailLsqr L, int xcd_copies) {
   __shared__ double red[kWavesPerBlock];
   __shared__ int flag;
   int work = 1;
@@ -348,9 +356,18 @@ __global__ void __launch_bounds__(kBlock) k_tail(SysView s, double* __restrict__
   }
   double sumsq = 0.0;
   if (work) {
+    const int64_t natt = 3 * s.n_att;
     for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < s.tail_len; j += (int64_t)gridDim.x * kBlock) {
-      const double a = acc[j];
+      double a = acc[j];
       acc[j] = 0.0;
+      if (xcd_copies && j < natt) {
+#pragma unroll
+        for (int x = 0; x < kXcds; ++x) {
+          double* q = acc + s.tail_len + x * natt + j;
+          a += *q;
+          *q = 0.0;
+        }
+      }
       const int64_t c = s.n_astro + j;
       const double xo = (scale == 0.0) ? 0.0 : scale * x[c];
       const double xn = xo + (S ? S[c] : 1.0) * a;
@@ -410,7 +427,7 @@ __global__ void k_scale_from_sq(int64_t n, double* S) {
 }
 
 // ------------------------------------------------------------ launchers
-StreamShape stream_shape(const SysView& s, int cus, int waves_per_cu, int stage) {
+StreamShape stream_shape(const SysView& s, int cus, int waves_per_cu, int stage, int xcd_copies) {
   // never more waves than stars or row tiles, never more blocks than partial slots
   int64_t waves = (int64_t)cus * waves_per_cu;
   waves = std::min(waves, (int64_t)kMaxPartials * kWavesPerBlock);
@@ -421,6 +438,7 @@ StreamShape stream_shape(const SysView& s, int cus, int waves_per_cu, int stage)
   sh.waves = (int)waves;
   sh.blocks = (int)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
   sh.stage = stage;
+  sh.xcd_copies = xcd_copies;
   return sh;
 }
 
@@ -444,7 +462,10 @@ hipError_t launch_aprod1(const SysView& s, StreamShape sh, const double* x, doub
   return hipGetLastError();
 }
 
-int tail_mode_of(const SysView& s) { return s.tail_len <= kLdsTailMax ? 0 : 1; }
+int tail_mode_of(const SysView& s, int xcd_copies) {
+  if (s.tail_len <= kLdsTailMax) return 0;
+  return xcd_copies ? 2 : 1;
+}
 
 template <int STAGE>
 static void aprod2_go(const SysView& s, StreamShape sh, const double* y, double* x, double* acc, const double* S,
@@ -461,7 +482,7 @@ static void aprod2_go(const SysView& s, StreamShape sh, const double* y, double*
 hipError_t launch_aprod2(const SysView& s, StreamShape sh, const double* y, double* x, double* acc, const double* S,
                          double scale, double inv_beta, int pmode, int square, Scalars* sc, Work w,
                          hipStream_t st) {
-  const int tm = tail_mode_of(s);
+  const int tm = tail_mode_of(s, sh.xcd_copies);
   const size_t hbytes = sizeof(double) * (size_t)(tm == 0 ? s.tail_len : s.tail_len - 3 * s.n_att);
   if (sh.stage)
     aprod2_go<1>(s, sh, y, x, acc, S, scale, inv_beta, pmode, square, tm, hbytes, sc, w, st);
@@ -472,11 +493,12 @@ hipError_t launch_aprod2(const SysView& s, StreamShape sh, const double* y, doub
 
 hipError_t launch_tail(const SysView& s, double* x, double* acc, const double* S, double scale, int square,
                        Scalars* sc, Work w, int lsqr_stage, int astro_parts, const int64_t* sel, const double* wv,
-                       double* D, hipStream_t st) {
+                       double* D, int xcd_copies, hipStream_t st) {
   (void)square;
   int blocks = (int)std::min<int64_t>(256, std::max<int64_t>(1, (s.tail_len + kBlock - 1) / kBlock));
   TailLsqr L{lsqr_stage, astro_parts, sel, wv, D};
-  hipLaunchKernelGGL(k_tail, dim3(blocks), dim3(kBlock), 0, st, s, x, acc, S, scale, sc, w, L);
+  hipLaunchKernelGGL(k_tail, dim3(blocks), dim3(kBlock), 0, st, s, x, acc, S, scale, sc, w, L,
+                     tail_mode_of(s, xcd_copies) == 2 ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -55,6 +55,7 @@ struct gsr_system {
   int cus = 256;
   int waves_per_cu = 32;
   int stage = 1;
+  int xcd_copies = 0;
   StreamShape sh{};
   Scalars* sc = nullptr;
   Scalars* sc_host = nullptr;  // pinned
@@ -146,7 +147,9 @@ extern "C" int64_t gsr_num_unknowns(const gsr_dims* d) {
   return 5 * d->n_stars + 3 * d->n_att + d->n_instr + d->n_glob;
 }
 
-static void reshape(gsr_system* s) { s->sh = stream_shape(s->s, s->cus, s->waves_per_cu, s->stage); }
+static void reshape(gsr_system* s) {
+  s->sh = stream_shape(s->s, s->cus, s->waves_per_cu, s->stage, s->xcd_copies);
+}
 
 static void release(gsr_system* s) {
   (void)hipDeviceSynchronize();
@@ -227,14 +230,14 @@ extern "C" int gsr_create(gsr_system** out, const gsr_dims* d, const void* vals,
   };
   if ((rc = dalloc(&s->sc, 1)) || (rc = dalloc(&s->wk.part_a, kMaxPartials)) ||
       (rc = dalloc(&s->wk.part_b, kMaxPartials)) || (rc = dalloc(&s->wk.part_c, kMaxPartials)) ||
-      (rc = dalloc(&s->wk.tickets, 8)) || (rc = dalloc(&s->acc, (size_t)v.tail_len)))
+      (rc = dalloc(&s->wk.tickets, 8)) || (rc = dalloc(&s->acc, (size_t)(v.tail_len + kXcds * 3 * v.n_att))))
     return bail(rc);
   if (hipHostMalloc((void**)&s->sc_host, sizeof(Scalars), hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
     return bail(fail(GSR_ENOMEM, "pinned host allocation failed"));
   }
   if (hipMemsetAsync(s->wk.tickets, 0, 8 * sizeof(unsigned), st) != hipSuccess ||
-      hipMemsetAsync(s->acc, 0, (size_t)v.tail_len * sizeof(double), st) != hipSuccess)
+      hipMemsetAsync(s->acc, 0, (size_t)(v.tail_len + kXcds * 3 * v.n_att) * sizeof(double), st) != hipSuccess)
     return bail(fail(GSR_EHIP, "workspace clear failed"));
 
   // index validation on the device
@@ -277,12 +280,13 @@ extern "C" int gsr_destroy(gsr_system* s) {
   return GSR_OK;
 }
 
-extern "C" int gsr_set_tuning(gsr_system* s, int32_t waves_per_cu, int32_t stage) {
+extern "C" int gsr_set_tuning(gsr_system* s, int32_t waves_per_cu, int32_t stage, int32_t xcd_copies) {
   CHK(check_handle(s));
-  if (waves_per_cu < 1 || waves_per_cu > 256 || (stage != 0 && stage != 1))
-    return fail(GSR_EINVAL, "waves_per_cu in [1,256], stage in {0,1}");
+  if (waves_per_cu < 1 || waves_per_cu > 256 || (stage != 0 && stage != 1) || (xcd_copies != 0 && xcd_copies != 1))
+    return fail(GSR_EINVAL, "waves_per_cu in [1,256], stage and xcd_copies in {0,1}");
   s->waves_per_cu = waves_per_cu;
   s->stage = stage;
+  s->xcd_copies = xcd_copies;
   reshape(s);
   return GSR_OK;
 }
@@ -376,7 +380,8 @@ static int aprod2_raw(gsr_system* s, const double* y, double* x, double scale_x,
     HIPCHK(launch_aprod2(s->s, s->sh, y, x, s->acc, nullptr, scale_x, 1.0, product, square, nullptr, s->wk, st));
   }
   TimeScope ts(s, 2, st);
-  HIPCHK(launch_tail(s->s, x, s->acc, nullptr, scale_x, square, nullptr, s->wk, 0, 0, nullptr, nullptr, nullptr, st));
+  HIPCHK(launch_tail(s->s, x, s->acc, nullptr, scale_x, square, nullptr, s->wk, 0, 0, nullptr, nullptr, nullptr,
+                     s->sh.xcd_copies, st));
   return GSR_OK;
 }
 
@@ -467,7 +472,8 @@ static int lsqr_begin(gsr_system* s, const double* b, const double* x0, const gs
   HIPCHK(launch_norm_init(s->u, s->s.m, s->sc, s->wk, st));
   // alpha_1 v_1 = S A^T u_1
   HIPCHK(launch_aprod2(s->s, s->sh, s->u, s->v, s->acc, S, 0.0, 1.0, product, 0, s->sc, s->wk, st));
-  HIPCHK(launch_tail(s->s, s->v, s->acc, S, 0.0, 0, s->sc, s->wk, 0, s->sh.blocks, s->sel, s->w, s->D, st));
+  HIPCHK(launch_tail(s->s, s->v, s->acc, S, 0.0, 0, s->sc, s->wk, 0, s->sh.blocks, s->sel, s->w, s->D,
+                     s->sh.xcd_copies, st));
   HIPCHK(launch_init_vectors(s->s.n, s->v, s->vg, s->w, s->y, s->var, S, s->sc, st));
   s->in_session = 1;
   return GSR_OK;
@@ -494,7 +500,8 @@ static int lsqr_iterate(gsr_system* s, int64_t nit, hipStream_t st) {
     }
     {
       TimeScope ts(s, 2, st);
-      HIPCHK(launch_tail(s->s, s->v, s->acc, S, 0.0, 0, s->sc, s->wk, 1, s->sh.blocks, s->sel, s->w, s->D, st));
+      HIPCHK(launch_tail(s->s, s->v, s->acc, S, 0.0, 0, s->sc, s->wk, 1, s->sh.blocks, s->sel, s->w, s->D,
+                         s->sh.xcd_copies, st));
     }
     {
       TimeScope ts(s, 3, st);
@@ -701,5 +708,273 @@ extern "C" int gsr_syrk(const double* D, int64_t k, int64_t cols, int64_t ldd, d
   NEED_DEV(C, "C");
   Work none{};
   HIPCHK(launch_syrk(D, k, ldd, C, nullptr, none, cols, (hipStream_t)stream));
+  return GSR_OK;
+}
+
+// ------------------------------------------------------------------ learned warm start
+
+extern "C" int gsr_features(gsr_system* s, const double* b, const double* x_other, double* F, gsr_stream stream) {
+  CHK(check_handle(s));
+  if (s->s.m > 0) NEED_DEV(b, "b");
+  NEED_DEV(x_other, "x_other");
+  if (s->s.n_stars > 0) NEED_DEV(F, "F");
+  HIPCHK(launch_features(s->s, b, x_other, F, (hipStream_t)stream));
+  return GSR_OK;
+}
+
+extern "C" int gsr_mean_rows(const double* X, int64_t k, int64_t len, double* out, gsr_stream stream) {
+  if (k < 1 || len < 0) return fail(GSR_EINVAL, "need k >= 1, len >= 0");
+  if (len == 0) return GSR_OK;
+  NEED_DEV(X, "X");
+  NEED_DEV(out, "out");
+  HIPCHK(launch_mean_rows(X, k, len, out, (hipStream_t)stream));
+  return GSR_OK;
+}
+
+struct gsr_mlp {
+  int I = 0, H = 0, O = 0;
+  int64_t P = 0;
+  float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
+  double *mu_x = nullptr, *sd_x = nullptr, *mu_t = nullptr, *sd_t = nullptr;
+  int norm_set = 0;
+  int64_t t = 0;
+  int64_t cap = 0;
+  float *Xs = nullptr, *Z1 = nullptr, *H1 = nullptr, *Z2 = nullptr, *H2 = nullptr, *Y = nullptr, *Ts = nullptr;
+  float *dY = nullptr, *dZ2 = nullptr, *dZ1 = nullptr;
+  double* loss = nullptr;
+  double* loss_host = nullptr;
+  // parameter views
+  float *W1() { return p; }
+  float *b1() { return p + (int64_t)H * I; }
+  float *W2() { return b1() + H; }
+  float *b2() { return W2() + (int64_t)H * H; }
+  float *W3() { return b2() + H; }
+  float *b3() { return W3() + (int64_t)O * H; }
+};
+
+static std::set<gsr_mlp*> g_live_mlp;
+
+static int check_mlp(gsr_mlp* n) {
+  if (!n) return fail(GSR_EINVAL, "null network");
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!g_live_mlp.count(n)) return fail(GSR_EINVAL, "unknown or destroyed network");
+  return GSR_OK;
+}
+
+static void mlp_release(gsr_mlp* n) {
+  (void)hipDeviceSynchronize();
+  for (void* q : {(void*)n->p, (void*)n->g, (void*)n->m, (void*)n->v, (void*)n->mu_x, (void*)n->sd_x,
+                  (void*)n->mu_t, (void*)n->sd_t, (void*)n->Xs, (void*)n->Z1, (void*)n->H1, (void*)n->Z2,
+                  (void*)n->H2, (void*)n->Y, (void*)n->Ts, (void*)n->dY, (void*)n->dZ2, (void*)n->dZ1,
+                  (void*)n->loss})
+    dfree(q);
+  if (n->loss_host) (void)hipHostFree(n->loss_host);
+  delete n;
+}
+
+extern "C" int gsr_mlp_create(gsr_mlp** out, int32_t n_in, int32_t n_hidden, int32_t n_out, const double* params) {
+  if (!out) return fail(GSR_EINVAL, "out is null");
+  *out = nullptr;
+  if (n_in < 1 || n_hidden < 1 || n_out < 1 || n_in > 4096 || n_hidden > 4096 || n_out > 4096)
+    return fail(GSR_EINVAL, "layer sizes must be in [1, 4096]");
+  if (!params) return fail(GSR_EINVAL, "params is null");
+  gsr_mlp* n = new gsr_mlp();
+  n->I = n_in;
+  n->H = n_hidden;
+  n->O = n_out;
+  n->P = (int64_t)n_hidden * n_in + n_hidden + (int64_t)n_hidden * n_hidden + n_hidden + (int64_t)n_out * n_hidden +
+         n_out;
+  int rc;
+  if ((rc = dalloc(&n->p, n->P)) || (rc = dalloc(&n->g, n->P)) || (rc = dalloc(&n->m, n->P)) ||
+      (rc = dalloc(&n->v, n->P)) || (rc = dalloc(&n->mu_x, n_in)) || (rc = dalloc(&n->sd_x, n_in)) ||
+      (rc = dalloc(&n->mu_t, n_out)) || (rc = dalloc(&n->sd_t, n_out)) || (rc = dalloc(&n->loss, 1))) {
+    mlp_release(n);
+    return rc;
+  }
+  if (hipHostMalloc((void**)&n->loss_host, sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    mlp_release(n);
+    return fail(GSR_ENOMEM, "pinned host allocation failed");
+  }
+  std::vector<float> h((size_t)n->P);
+  for (int64_t i = 0; i < n->P; ++i) h[i] = (float)params[i];
+  std::vector<double> ones(std::max(n_in, n_out), 1.0), zeros(std::max(n_in, n_out), 0.0);
+  if (hipMemcpy(n->p, h.data(), n->P * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(n->m, 0, n->P * sizeof(float)) != hipSuccess || hipMemset(n->v, 0, n->P * sizeof(float)) != hipSuccess ||
+      hipMemcpy(n->mu_x, zeros.data(), n_in * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(n->sd_x, ones.data(), n_in * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(n->mu_t, zeros.data(), n_out * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(n->sd_t, ones.data(), n_out * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+    mlp_release(n);
+    return fail(GSR_EHIP, "network upload failed");
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_live_mlp.insert(n);
+  }
+  *out = n;
+  return GSR_OK;
+}
+
+extern "C" int gsr_mlp_destroy(gsr_mlp* n) {
+  if (!n) return GSR_OK;
+  CHK(check_mlp(n));
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_live_mlp.erase(n);
+  }
+  mlp_release(n);
+  return GSR_OK;
+}
+
+extern "C" int gsr_mlp_get_params(gsr_mlp* n, double* params) {
+  CHK(check_mlp(n));
+  if (!params) return fail(GSR_EINVAL, "params is null");
+  std::vector<float> h((size_t)n->P);
+  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(hipMemcpy(h.data(), n->p, n->P * sizeof(float), hipMemcpyDeviceToHost));
+  for (int64_t i = 0; i < n->P; ++i) params[i] = h[i];
+  return GSR_OK;
+}
+
+extern "C" int gsr_mlp_fit_norm(gsr_mlp* n, const double* X, const double* T, int64_t N, gsr_stream stream) {
+  CHK(check_mlp(n));
+  if (N < 1) return fail(GSR_EINVAL, "N < 1");
+  NEED_DEV(X, "X");
+  NEED_DEV(T, "T");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(mlp_col_stats(X, N, n->I, n->mu_x, n->sd_x, st));
+  HIPCHK(mlp_col_stats(T, N, n->O, n->mu_t, n->sd_t, st));
+  n->norm_set = 1;
+  return GSR_OK;
+}
+
+static int mlp_reserve(gsr_mlp* n, int64_t N) {
+  if (N <= n->cap) return GSR_OK;
+  HIPCHK(hipDeviceSynchronize());
+  for (float** q : {&n->Xs, &n->Z1, &n->H1, &n->Z2, &n->H2, &n->Y, &n->Ts, &n->dY, &n->dZ2, &n->dZ1}) {
+    dfree(*q);
+    *q = nullptr;
+  }
+  n->cap = 0;
+  const size_t I = n->I, H = n->H, O = n->O;
+  CHK(dalloc(&n->Xs, N * I));
+  CHK(dalloc(&n->Z1, N * H));
+  CHK(dalloc(&n->H1, N * H));
+  CHK(dalloc(&n->Z2, N * H));
+  CHK(dalloc(&n->H2, N * H));
+  CHK(dalloc(&n->Y, N * O));
+  CHK(dalloc(&n->Ts, N * O));
+  CHK(dalloc(&n->dY, N * O));
+  CHK(dalloc(&n->dZ2, N * H));
+  CHK(dalloc(&n->dZ1, N * H));
+  n->cap = N;
+  return GSR_OK;
+}
+
+// forward on standardized inputs n->Xs (N rows); output n->Y (standardized)
+static int mlp_fwd(gsr_mlp* n, int64_t N, hipStream_t st) {
+  const int I = n->I, H = n->H, O = n->O;
+  GemmArgs g1{(int)N, H, I, n->Xs, I, 1, n->W1(), 1, I, n->H1, H, n->b1(), 1, n->Z1, nullptr};
+  HIPCHK(mlp_gemm(g1, 1, st));
+  GemmArgs g2{(int)N, H, H, n->H1, H, 1, n->W2(), 1, H, n->H2, H, n->b2(), 1, n->Z2, nullptr};
+  HIPCHK(mlp_gemm(g2, 1, st));
+  GemmArgs g3{(int)N, O, H, n->H2, H, 1, n->W3(), 1, H, n->Y, O, n->b3(), 0, nullptr, nullptr};
+  HIPCHK(mlp_gemm(g3, 1, st));
+  return GSR_OK;
+}
+
+// gradients of the mean squared error into n->g (loss accumulated into n->loss)
+static int mlp_bwd(gsr_mlp* n, int64_t N, hipStream_t st) {
+  const int I = n->I, H = n->H, O = n->O;
+  const int splits = (int)std::max<int64_t>(1, std::min<int64_t>(64, N / 256));
+  float* gW1 = n->g;
+  float* gb1 = gW1 + (int64_t)H * I;
+  float* gW2 = gb1 + H;
+  float* gb2 = gW2 + (int64_t)H * H;
+  float* gW3 = gb2 + H;
+  float* gb3 = gW3 + (int64_t)O * H;
+  HIPCHK(mlp_mse(n->Y, n->Ts, N * O, n->dY, n->loss, st));
+  GemmArgs w3{O, H, (int)N, n->dY, 1, O, n->H2, H, 1, gW3, H, nullptr, 0, nullptr, nullptr};
+  HIPCHK(mlp_gemm(w3, splits, st));
+  HIPCHK(mlp_colsum(n->dY, N, O, gb3, st));
+  GemmArgs h2{(int)N, H, O, n->dY, O, 1, n->W3(), H, 1, n->dZ2, H, nullptr, 0, nullptr, n->Z2};
+  HIPCHK(mlp_gemm(h2, 1, st));
+  GemmArgs w2{H, H, (int)N, n->dZ2, 1, H, n->H1, H, 1, gW2, H, nullptr, 0, nullptr, nullptr};
+  HIPCHK(mlp_gemm(w2, splits, st));
+  HIPCHK(mlp_colsum(n->dZ2, N, H, gb2, st));
+  GemmArgs h1{(int)N, H, H, n->dZ2, H, 1, n->W2(), H, 1, n->dZ1, H, nullptr, 0, nullptr, n->Z1};
+  HIPCHK(mlp_gemm(h1, 1, st));
+  GemmArgs w1{H, I, (int)N, n->dZ1, 1, H, n->Xs, I, 1, gW1, I, nullptr, 0, nullptr, nullptr};
+  HIPCHK(mlp_gemm(w1, splits, st));
+  HIPCHK(mlp_colsum(n->dZ1, N, H, gb1, st));
+  return GSR_OK;
+}
+
+static int mlp_load(gsr_mlp* n, const double* X, const double* T, int64_t N, hipStream_t st) {
+  CHK(mlp_reserve(n, N));
+  HIPCHK(mlp_standardize(X, N, n->I, n->mu_x, n->sd_x, n->Xs, st));
+  if (T) HIPCHK(mlp_standardize(T, N, n->O, n->mu_t, n->sd_t, n->Ts, st));
+  return GSR_OK;
+}
+
+extern "C" int gsr_mlp_forward(gsr_mlp* n, const double* X, int64_t N, double* Y, gsr_stream stream) {
+  CHK(check_mlp(n));
+  if (N < 0) return fail(GSR_EINVAL, "N < 0");
+  if (N == 0) return GSR_OK;
+  NEED_DEV(X, "X");
+  NEED_DEV(Y, "Y");
+  hipStream_t st = (hipStream_t)stream;
+  CHK(mlp_load(n, X, nullptr, N, st));
+  CHK(mlp_fwd(n, N, st));
+  HIPCHK(mlp_destandardize(n->Y, N, n->O, n->mu_t, n->sd_t, Y, st));
+  return GSR_OK;
+}
+
+extern "C" int gsr_mlp_grad(gsr_mlp* n, const double* X, const double* T, int64_t N, double* loss_host,
+                            float* grads, gsr_stream stream) {
+  CHK(check_mlp(n));
+  if (N < 1) return fail(GSR_EINVAL, "N < 1");
+  NEED_DEV(X, "X");
+  NEED_DEV(T, "T");
+  hipStream_t st = (hipStream_t)stream;
+  CHK(mlp_load(n, X, T, N, st));
+  HIPCHK(hipMemsetAsync(n->loss, 0, sizeof(double), st));
+  CHK(mlp_fwd(n, N, st));
+  CHK(mlp_bwd(n, N, st));
+  if (grads) {
+    NEED_DEV(grads, "grads");
+    HIPCHK(hipMemcpyAsync(grads, n->g, n->P * sizeof(float), hipMemcpyDeviceToDevice, st));
+  }
+  HIPCHK(hipMemcpyAsync(n->loss_host, n->loss, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (loss_host) *loss_host = *n->loss_host;
+  return GSR_OK;
+}
+
+extern "C" int gsr_mlp_train(gsr_mlp* n, const double* X, const double* T, int64_t N, int32_t steps, double lr,
+                             double* loss_host, gsr_stream stream) {
+  CHK(check_mlp(n));
+  if (N < 1 || steps < 0 || !(lr > 0)) return fail(GSR_EINVAL, "need N >= 1, steps >= 0, lr > 0");
+  NEED_DEV(X, "X");
+  NEED_DEV(T, "T");
+  hipStream_t st = (hipStream_t)stream;
+  CHK(mlp_load(n, X, T, N, st));
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  for (int32_t i = 0; i < steps; ++i) {
+    CHK(mlp_fwd(n, N, st));
+    HIPCHK(hipMemsetAsync(n->loss, 0, sizeof(double), st));
+    CHK(mlp_bwd(n, N, st));
+    n->t += 1;
+    const float c1 = (float)(1.0 - pow(0.9, (double)n->t)), c2 = (float)(1.0 - pow(0.999, (double)n->t));
+    HIPCHK(mlp_adam(n->p, n->g, n->m, n->v, n->P, (float)lr, b1, b2, eps, c1, c2, st));
+  }
+  // loss of the final parameters
+  HIPCHK(hipMemsetAsync(n->loss, 0, sizeof(double), st));
+  CHK(mlp_fwd(n, N, st));
+  HIPCHK(mlp_mse(n->Y, n->Ts, N * n->O, n->dY, n->loss, st));
+  HIPCHK(hipMemcpyAsync(n->loss_host, n->loss, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (loss_host) *loss_host = *n->loss_host;
   return GSR_OK;
 }

@@ -12,6 +12,12 @@ typedef int i2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ u4 ld_stream(const u4* p) { return __builtin_nontemporal_load(p); }
 
+// Index of the XCD (accelerator complex die) the wave runs on: hardware
+// register XCC_ID (20), bits 3:0 on gfx942 / gfx950; kept in [0, kXcds).
+__device__ __forceinline__ unsigned xcc_id() {
+  return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & (kXcds - 1);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);

@@ -14,6 +14,7 @@ constexpr int kBlock = 256;        // threads per workgroup (4 waves)
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kSlots = 24;         // coefficients per row: 5 astro, 12 attitude, 6 instr, 1 global
 constexpr int kMaxPartials = 4096; // upper bound on workgroups of a reducing launch
+constexpr int kXcds = 8;           // XCDs of an MI355X, each with its own L2
 constexpr int kLdsTailMax = 2048;  // tail columns accumulated in LDS when they fit (16 KB)
 
 // Device-resident LSQR state.  Written only by the single "last" workgroup of
@@ -69,9 +70,10 @@ struct SysView {
 struct StreamShape {
   int blocks;
   int waves;
-  int stage;  // 1: coefficient tiles staged through LDS, 0: direct row loads
+  int stage;       // 1: coefficient tiles staged through LDS, 0: direct row loads
+  int xcd_copies;  // 1: attitude atomics into one private copy per XCD
 };
-StreamShape stream_shape(const SysView& s, int cus, int waves_per_cu, int stage);
+StreamShape stream_shape(const SysView& s, int cus, int waves_per_cu, int stage, int xcd_copies);
 
 // ---- launchers (all asynchronous on `st`) ---------------------------------
 // y <- scale*y + ax * A x (or with the LSQR scalars: scale = sc->u_scale, ax = 1,
@@ -85,7 +87,7 @@ hipError_t launch_aprod2(const SysView& s, StreamShape sh, const double* y, doub
 // tail part: x_t <- scale*x_t + S_t * acc_t, acc cleared; LSQR epilogue when sc != nullptr.
 hipError_t launch_tail(const SysView& s, double* x, double* acc, const double* S, double scale,
                        int square, Scalars* sc, Work w, int lsqr_stage, int astro_parts,
-                       const int64_t* sel, const double* wv, double* D, hipStream_t st);
+                       const int64_t* sel, const double* wv, double* D, int xcd_copies, hipStream_t st);
 // bad[0] <- first row with an out-of-range index, bad[1] <- first bad star, bad[2] <- 1 if a star is empty
 hipError_t launch_validate(const SysView& s, unsigned long long* bad, hipStream_t st);
 hipError_t launch_scale_from_sq(int64_t n, double* S, hipStream_t st);
@@ -105,7 +107,36 @@ hipError_t launch_cov_out(const double* C, int64_t k, const double* S, const int
                           hipStream_t st);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
 hipError_t launch_axpy_norms(int64_t n, const double* dx, double* x, double* out2, Work w, hipStream_t st);
-int tail_mode_of(const SysView& s);
+int tail_mode_of(const SysView& s, int xcd_copies);
+
+// learned warm start (mlp.hip)
+hipError_t launch_features(const SysView& s, const double* b, const double* xo, double* F, hipStream_t st);
+hipError_t launch_mean_rows(const double* X, int64_t k, int64_t len, double* out, hipStream_t st);
+// Strided FP32 GEMM: C(m,n) = sum_k A(m,k) B(k,n) [+bias] [ReLU] [*(mask>0)]
+struct GemmArgs {
+  int M, N, K;
+  const float* A;
+  int64_t sam, sak;
+  const float* B;
+  int64_t sbk, sbn;
+  float* C;
+  int64_t ldc;
+  const float* bias;
+  int relu;
+  float* Zout;
+  const float* mask;
+};
+hipError_t mlp_col_stats(const double* X, int64_t N, int C, double* mu, double* sd, hipStream_t st);
+hipError_t mlp_standardize(const double* X, int64_t N, int C, const double* mu, const double* sd, float* Xs,
+                           hipStream_t st);
+hipError_t mlp_destandardize(const float* Ys, int64_t N, int C, const double* mu, const double* sd, double* Y,
+                             hipStream_t st);
+hipError_t mlp_gemm(const GemmArgs& g, int splits, hipStream_t st);
+hipError_t mlp_mse(const float* Y, const float* T, int64_t total, float* dY, double* loss, hipStream_t st);
+hipError_t mlp_colsum(const float* dZ, int64_t M, int N, float* db, hipStream_t st);
+hipError_t mlp_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
+                    float c1, float c2, hipStream_t st);
+hipError_t mlp_fill(float* p, int64_t n, float val, hipStream_t st);
 
 // number of compute units of the current device (cached)
 int device_cus();

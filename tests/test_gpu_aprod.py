@@ -54,14 +54,14 @@ def dev():
     return gsr
 
 
-@pytest.mark.parametrize("stage", [1, 0])
+@pytest.mark.parametrize("tuning", [(32, 1, 0), (32, 0, 0), (8, 1, 1)])
 @pytest.mark.parametrize("case", list(CASES))
-def test_aprod_fp64(dev, oracle_lib, case, stage):
-    print(f"[aprod fp64] case={case} stage={stage}", flush=True)
+def test_aprod_fp64(dev, oracle_lib, case, tuning):
+    print(f"[aprod fp64] case={case} tuning={tuning}", flush=True)
     g = gsr_synth.make_system(**CASES[case])
     o = oracle_lib.OSystem(g)
     S = dev.System.from_generated(g)
-    S.set_tuning(32, stage)
+    S.set_tuning(*tuning)
     d = g.dims
     rng = np.random.default_rng(1)
     x = rng.standard_normal(d.n)
