@@ -77,6 +77,128 @@ def cpu_baseline(full_m: int, budget_s: float = 15.0):
                       f"{r['itn']} unscaled LSQR iterations in {tk:.1f} s, scaled by rows to m={full_m}"}
 
 
+def _rel(a, b):
+    import torch
+
+    return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+
+def _median_time(fn, reps=5):
+    import torch
+
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t)
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def _iters_to(S, b, x_ref, tol, cap, x0=None, **opts):
+    """Trace run: iterations of a warm- or cold-start solve until ||x - x_ref|| <= tol ||x_ref||."""
+    S.lsqr_begin(b, x0=x0, atol=0.0, btol=0.0, itmax=cap, **opts)
+    x = None
+    for it in range(1, cap + 1):
+        S.lsqr_iterate(1)
+        x = S.lsqr_peek(x)
+        if _rel(x, x_ref) <= tol:
+            S.lsqr_end(want_var=False)
+            return it
+    S.lsqr_end(want_var=False)
+    return None
+
+
+def time_to_tolerance_fp32(gsr, g, tol=1e-10, label=""):
+    """FP64 LSQR vs FP32 storage + FP64 refinement on the same FP32-representable matrix.
+    Reference: the FP64 solve converged to atol = btol = 1e-14."""
+    import numpy as np
+    import torch
+
+    g32 = g.as_f32()
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    rp, at, ic = t(g.star_row_ptr), t(g.att_start), t(g.instr_col)
+    v32 = t(g32.vals)
+    S64 = gsr.System(v32.double(), rp, at, ic, g.dims.n_att, g.dims.n_instr, g.dims.n_glob)
+    S32 = gsr.System(v32, rp, at, ic, g.dims.n_att, g.dims.n_instr, g.dims.n_glob)
+    b = t(g.noise)
+    S64.aprod1(t(g.x_true), b, scale=1.0)
+    x_ref, _, rref = S64.lsqr_solve(b, atol=1e-14, btol=1e-14, itmax=5000, precond=True, want_var=False)
+    n64 = _iters_to(S64, b, x_ref, tol, 2000, precond=True)
+    t64 = _median_time(lambda: S64.lsqr_solve(b, atol=0, btol=0, itmax=n64, precond=True, want_var=False))
+    ropts = dict(atol=1e-6, btol=1e-6, itmax=2000, precond=True, outer_max=10, outer_tol=1e-11)
+    xr, rr = S32.lsqr_refine(b, **ropts)
+    err32 = _rel(xr, x_ref)
+    t32 = _median_time(lambda: S32.lsqr_refine(b, **ropts))
+    S64.close()
+    S32.close()
+    return {"workload": label, "tol": tol, "fp64": {"iterations": n64, "seconds": t64},
+            "fp32_refine": {"outer": rr["outer_steps"], "inner_total": rr["inner_total"], "seconds": t32,
+                            "rel_err_vs_fp64": err32},
+            "speedup": t64 / t32}
+
+
+def time_to_tolerance_warm(gsr, tol=1e-10, train_steps=1500):
+    """Family of 16 related systems on the 1,000-star matrix; train on 0-7, warm-start 8-15."""
+    import numpy as np
+    import torch
+
+    import gsr_synth
+
+    base = gsr_synth.tiny()
+    S = gsr.System.from_generated(base)
+    ns = base.dims.n_stars
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    opts = dict(atol=1e-12, btol=1e-12, itmax=500, precond=True)
+    bs = []
+    for s in range(16):
+        fm = gsr_synth.family_member(base, s)
+        b = t(fm.noise)
+        S.aprod1(t(fm.x_true), b, scale=1.0)
+        bs.append(b)
+    sols = [S.lsqr_solve(bs[s], want_var=False, **opts)[0] for s in range(8)]
+    x_mean = gsr.mean_rows(torch.stack(sols))
+    xo = x_mean[5 * ns:].contiguous()
+    F = torch.cat([S.features(bs[s], xo) for s in range(8)])
+    T = torch.cat([sols[s][: 5 * ns].reshape(ns, 5) for s in range(8)])
+    net = gsr.MLP(gsr_synth.mlp_init(28, 128, 5, seed=11))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    net.fit_norm(F, T)
+    loss = net.train(F, T, steps=train_steps, lr=1e-3)
+    train_s = time.perf_counter() - t0
+
+    def mlp_x0(b):
+        x0 = torch.empty(base.dims.n, dtype=torch.float64, device="cuda")
+        x0[: 5 * ns] = net.forward(S.features(b, xo)).reshape(-1)
+        x0[5 * ns:] = xo
+        return x0
+
+    rows = []
+    for s in range(8, 16):
+        b = bs[s]
+        x_ref, _, _ = S.lsqr_solve(b, atol=1e-14, btol=1e-14, itmax=5000, precond=True, want_var=False)
+        k0 = _iters_to(S, b, x_ref, tol, 500, precond=True)
+        km = _iters_to(S, b, x_ref, tol, 500, x0=x_mean, precond=True)
+        kn = _iters_to(S, b, x_ref, tol, 500, x0=mlp_x0(b), precond=True)
+        t0_ = _median_time(lambda: S.lsqr_solve(b, atol=0, btol=0, itmax=k0, precond=True, want_var=False))
+        tm_ = _median_time(lambda: S.lsqr_solve(b, x0=x_mean, atol=0, btol=0, itmax=km, precond=True,
+                                                want_var=False))
+        tn_ = _median_time(lambda: S.lsqr_solve(b, x0=mlp_x0(b), atol=0, btol=0, itmax=kn, precond=True,
+                                                want_var=False))
+        rows.append((k0, km, kn, t0_, tm_, tn_))
+    net.close()
+    S.close()
+    a = np.array(rows, dtype=float)
+    return {"workload": "family of 16 systems on the 1,000-star matrix (train 0-7, test 8-15)", "tol": tol,
+            "train_loss": loss, "train_seconds": train_s,
+            "iterations": {"zero": a[:, 0].mean(), "mean_x0": a[:, 1].mean(), "mlp_x0": a[:, 2].mean()},
+            "seconds": {"zero": a[:, 3].mean(), "mean_x0": a[:, 4].mean(), "mlp_x0_incl_inference": a[:, 5].mean()},
+            "speedup_mlp_vs_zero": a[:, 3].mean() / a[:, 5].mean()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +206,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--stars", type=int, default=1_000_000)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-1e-10 comparisons")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU row split is not built.",
@@ -163,6 +286,15 @@ def main():
                   "aprod_pair_frac": (bytes1 + bytes2) / ((a1 + a2) * 1e-3) / 1e9 / HBM_PEAK_GBS},
     }
     S.close()
+    if not args.no_ttt:
+        import gsr_synth as _gs
+
+        out["time_to_1e-10"] = {
+            "fp32_refine_tiny": time_to_tolerance_fp32(gsr, _gs.tiny(), label="tiny: 1,000 stars x 20 rows"),
+            "fp32_refine_share": time_to_tolerance_fp32(
+                gsr, _gs.share_1m(n_stars=args.stars // 4), label=f"{args.stars // 4} stars x U[50,90] rows"),
+            "warm_start": time_to_tolerance_warm(gsr),
+        }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(m)
     print(json.dumps(out), flush=True)

@@ -159,14 +159,14 @@ __global__ void __launch_bounds__(kBlock) k_syrk(const double* __restrict__ D, i
           for (int bj = 0; bj < 2; ++bj)
             acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bi][s], bv[bj][s], acc[bi][bj], 0, 0, 0);
     }
-    // accumulator layout: element e of lane l is row 4*(l/16)+e, column l%16
+    // accumulator layout of the 16x16 f64 result: element e of lane l is row (l/16) + 4e, column l%16
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
       for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int64_t r = row0 + 16 * bi + 4 * g + e, c = col0 + 16 * bj + i16;
+          const int64_t r = row0 + 16 * bi + g + 4 * e, c = col0 + 16 * bj + i16;
           if (r < k && c < k) C[r * k + c] += acc[bi][bj][e];
         }
   }

@@ -3,9 +3,11 @@ refinement) with the CPU oracle.
 
 LSQR iterates past the point where the Krylov basis loses orthogonality are
 themselves sensitive to rounding (the oracle perturbed at the last bit of b
-moves them by up to ~1e-8 on the unscaled 1,000-star system).  Converged
-solutions are held to 1e-10; fixed-count runs are held to 1e-12 or, when
-the oracle's own sensitivity is larger, to 20x that sensitivity."""
+or of A moves them by up to ~1e-8 on the unscaled 1,000-star system, and
+moves the variances of a converged run by ~1e-4).  Converged solutions are
+held to 1e-10; unconverged iterates and post-convergence variances are held
+to 1e-12 or, when the oracle's own last-bit sensitivity is larger, to 10x
+that sensitivity."""
 import numpy as np
 import pytest
 import torch
@@ -37,48 +39,67 @@ def tiny(dev, oracle_lib):
     return g, o, b, S
 
 
-def _sensitivity(oracle_lib, o, b, **kw):
+def _sensitivity(oracle_lib, g, o, b, **kw):
+    """The oracle's own response to last-bit perturbations: b and, separately, every
+    coefficient of A scaled by (1 + 2.2e-16 N(0,1)) (the size of the rounding differences
+    between two valid summation orders).  Returns the reference run and the largest
+    relative deviations of x and var over three perturbed runs."""
+    import copy
+
     r1 = oracle_lib.lsqr(o, b, **kw)
-    bp = b * (1 + 2e-16 * np.random.default_rng(5).standard_normal(b.size))
-    r2 = oracle_lib.lsqr(o, bp, **kw)
-    return r1, _rel(r2["x"], r1["x"]), _rel(r2["var"], r1["var"])
+    sx = sv = 0.0
+    for seed in (5, 6):
+        bp = b * (1 + 2e-16 * np.random.default_rng(seed).standard_normal(b.size))
+        r2 = oracle_lib.lsqr(o, bp, **kw)
+        sx, sv = max(sx, _rel(r2["x"], r1["x"])), max(sv, _rel(r2["var"], r1["var"]))
+    gp = copy.copy(g)
+    gp.vals = g.vals * (1 + 2.2e-16 * np.random.default_rng(7).standard_normal(g.vals.shape))
+    r3 = oracle_lib.lsqr(oracle_lib.OSystem(gp), b, **kw)
+    sx, sv = max(sx, _rel(r3["x"], r1["x"])), max(sv, _rel(r3["var"], r1["var"]))
+    return r1, sx, sv
 
 
 def test_lsqr_converged_tiny_precond(dev, oracle_lib, tiny):
+    """Converged solution to 1e-10.  The variances keep accumulating after convergence,
+    where the search directions lose orthogonality; they are held to 10x the oracle's own
+    last-bit sensitivity (about 1e-4 here)."""
     print("[lsqr] tiny, column-scaled, to tolerance", flush=True)
     g, o, b, S = tiny
-    ref = oracle_lib.lsqr(o, b, atol=1e-12, btol=1e-12, itmax=200, precond=True)
+    ref, _, sv = _sensitivity(oracle_lib, g, o, b, atol=1e-12, btol=1e-12, itmax=200, precond=True)
     x, var, r = S.lsqr_solve(torch.from_numpy(b).cuda(), atol=1e-12, btol=1e-12, itmax=200, precond=True)
     x, var = x.cpu().numpy(), var.cpu().numpy()
     print(f"  gpu istop={r['istop']} itn={r['itn']}  oracle istop={ref['istop']} itn={ref['itn']}", flush=True)
     assert r["istop"] == ref["istop"]
     assert abs(r["itn"] - ref["itn"]) <= 1
     assert _rel(x, ref["x"]) <= 1e-10
-    assert _rel(var, ref["var"]) <= 1e-6
-    for k in ("rnorm", "arnorm", "anorm", "acond", "xnorm", "bnorm"):
+    assert _rel(var, ref["var"]) <= max(1e-10, 10 * sv)
+    for k in ("rnorm", "anorm", "acond", "xnorm", "bnorm"):
         assert abs(r[k] - ref[k]) <= 1e-6 * abs(ref[k]) + 1e-300, k
+    # ||A^T r|| at the solution is at rounding level: compare on the scale of the stop test
+    assert abs(r["arnorm"] - ref["arnorm"]) <= 0.05 * ref["arnorm"] + 1e-16 * ref["anorm"] * ref["rnorm"]
 
 
 @pytest.mark.parametrize("precond,itmax", [(True, 5), (True, 30), (False, 20)])
 def test_lsqr_fixed_iterations(dev, oracle_lib, tiny, precond, itmax):
     print(f"[lsqr] tiny fixed count precond={precond} itmax={itmax}", flush=True)
     g, o, b, S = tiny
-    ref, sx, sv = _sensitivity(oracle_lib, o, b, atol=0, btol=0, itmax=itmax, precond=precond)
+    ref, sx, sv = _sensitivity(oracle_lib, g, o, b, atol=0, btol=0, itmax=itmax, precond=precond)
     x, var, r = S.lsqr_solve(torch.from_numpy(b).cuda(), atol=0, btol=0, itmax=itmax, precond=precond)
     assert r["itn"] == itmax and r["istop"] == 7
-    assert _rel(x.cpu().numpy(), ref["x"]) <= max(1e-12, 20 * sx)
-    assert _rel(var.cpu().numpy(), ref["var"]) <= max(1e-12, 20 * sv)
+    print(f"  oracle sensitivity x {sx:.2e} var {sv:.2e}", flush=True)
+    assert _rel(x.cpu().numpy(), ref["x"]) <= max(1e-12, 10 * sx)
+    assert _rel(var.cpu().numpy(), ref["var"]) <= max(1e-12, 10 * sv)
 
 
 def test_lsqr_unscaled_as_written(dev, oracle_lib, tiny):
     """The 1,000-star system without scaling, damp 0, atol = btol = 1e-12, itmax 200."""
     print("[lsqr] tiny unscaled itmax=200", flush=True)
     g, o, b, S = tiny
-    ref, sx, _ = _sensitivity(oracle_lib, o, b, atol=1e-12, btol=1e-12, itmax=200, precond=False)
+    ref, sx, _ = _sensitivity(oracle_lib, g, o, b, atol=1e-12, btol=1e-12, itmax=200, precond=False)
     x, _, r = S.lsqr_solve(torch.from_numpy(b).cuda(), atol=1e-12, btol=1e-12, itmax=200, precond=False)
     print(f"  oracle self-sensitivity {sx:.2e}; gpu istop={r['istop']} itn={r['itn']}", flush=True)
     assert r["istop"] == ref["istop"] == 7
-    assert _rel(x.cpu().numpy(), ref["x"]) <= max(1e-12, 20 * sx)
+    assert _rel(x.cpu().numpy(), ref["x"]) <= max(1e-12, 10 * sx)
 
 
 def test_lsqr_damped_and_warm_start(dev, oracle_lib):
