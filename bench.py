@@ -207,6 +207,8 @@ def main():
     ap.add_argument("--stars", type=int, default=1_000_000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-1e-10 comparisons")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one 2 GiB device copy (known bytes, for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU row split is not built.",
@@ -219,6 +221,14 @@ def main():
     import paper_2503_22863_amd as gsr
 
     torch.cuda.set_device(0)
+    if args.calib_copy:
+        a = torch.empty(1 << 28, dtype=torch.float64, device="cuda")
+        a.fill_(1.0)
+        c = torch.empty_like(a)
+        torch.cuda.synchronize()
+        c.copy_(a)  # reads and writes 2 GiB
+        torch.cuda.synchronize()
+        del a, c
     t = time.time()
     g = gsr_synth.share_1m(n_stars=args.stars)
     m, n, ns = g.dims.m, g.dims.n, g.dims.n_stars

@@ -85,6 +85,11 @@ const char *gsr_version(void);
  */
 int gsr_create(gsr_system **out, const gsr_dims *d, const void *vals, const int64_t *star_row_ptr,
                const int32_t *att_start, const int32_t *instr_col, gsr_stream stream);
+/* When 3*n_att + n_instr + n_glob exceeds 2048 (the attitude block does not fit
+ * in LDS), gsr_create also builds a library-owned copy of the 12 attitude
+ * coefficients of every row grouped by attitude start (12 values + 12 bytes of
+ * index data per row, e.g. 7 GB for 7e7 FP64 rows) so that aprod 2 needs no
+ * global atomics; if that allocation fails the handle falls back to atomics. */
 /* Free the handle's workspaces (synchronises the device first).  NULL is a no-op. */
 int gsr_destroy(gsr_system *sys);
 
@@ -196,12 +201,12 @@ int64_t gsr_cov_bytes(int32_t version, int64_t itn_cov_cp, int64_t count);
  */
 int gsr_syrk(const double *D, int64_t k, int64_t cols, int64_t ldd, double *C, gsr_stream stream);
 
-/* Launch tuning of the row-streaming kernels: waves per CU (1..256), LDS
- * staging of coefficient tiles (stage 0/1), attitude sums of aprod 2 into one
- * private copy per XCD instead of one shared copy (xcd_copies 0/1; only used
- * when the attitude block does not fit in LDS).  Results are unchanged up to
- * the order of the atomic FP64 additions. */
-int gsr_set_tuning(gsr_system *sys, int32_t waves_per_cu, int32_t stage, int32_t xcd_copies);
+/* Launch tuning of the row-streaming kernels: waves per CU (1..256), and,
+ * when the attitude block does not fit in LDS, att_atomics = 1 to sum the
+ * attitude part of aprod 2 with device-scope FP64 atomics instead of the
+ * attitude-bucketed pass (for comparison; much slower).  Results are
+ * unchanged up to the order of FP64 additions. */
+int gsr_set_tuning(gsr_system *sys, int32_t waves_per_cu, int32_t att_atomics);
 
 /* Per-kernel timing with HIP events on the solve's stream (off by default).
  * gsr_timing_get synchronises, returns the totals since the last get and

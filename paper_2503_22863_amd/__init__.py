@@ -79,7 +79,7 @@ _SIGS = {
     "gsr_cov_get": (C.c_int, [C.c_void_p] * 3),
     "gsr_cov_bytes": (C.c_int64, [C.c_int32, C.c_int64, C.c_int64]),
     "gsr_syrk": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p]),
-    "gsr_set_tuning": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]),
+    "gsr_set_tuning": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "gsr_timing_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "gsr_timing_get": (C.c_int, [C.c_void_p, C.c_void_p]),
     "gsr_features": (C.c_int, [C.c_void_p] * 5),
@@ -361,8 +361,8 @@ class System:
         return F
 
     # ---- tuning and timing
-    def set_tuning(self, waves_per_cu, stage, xcd_copies=0):
-        _check(lib().gsr_set_tuning(self._h, int(waves_per_cu), int(stage), int(xcd_copies)))
+    def set_tuning(self, waves_per_cu=32, att_atomics=0):
+        _check(lib().gsr_set_tuning(self._h, int(waves_per_cu), int(att_atomics)))
 
     def timing_enable(self, on=True):
         _check(lib().gsr_timing_enable(self._h, int(bool(on))))

@@ -1,22 +1,26 @@
 // The two products of every LSQR iteration (Sec. 2, Eq. 2 and Eq. 3) over the
 // 24-coefficient row form of the observation matrix, for gfx950.
 //
-// Both kernels stream the coefficient rows once.  Work is split by whole
-// stars: wave w of W owns the stars whose rows start in [w*m/W, (w+1)*m/W),
-// so every astrometric unknown is produced by exactly one wave.  A wave
-// walks its rows in tiles of 64 (one row per lane); each tile's coefficients
-// (64 x 192 B for FP64) are fetched with contiguous 16-byte loads, staged in
-// LDS with one 16-byte pad per row (conflict-free row reads), and then read
-// back row-per-lane.
+// Both kernels stream the coefficient rows once in star order.  Work is split
+// by whole stars: wave w of W owns the stars whose rows start in
+// [w*m/W, (w+1)*m/W), so every astrometric unknown is produced by exactly one
+// wave.  A wave walks its rows in tiles of 64 (one row per lane).  A tile's
+// coefficients (64 x 192 B for FP64) are fetched with contiguous 16-byte
+// nontemporal loads (1 KB per wave instruction), staged in LDS with one
+// 16-byte pad per row (conflict-free row reads) and read back row-per-lane.
+// The star of each row comes from the tile's 64 star boundaries, loaded in
+// one coalesced access and searched in LDS.
 //
 // aprod1: y_r <- scale*y_r + ax * sum_k a_rk x[col(r,k)]; the x gathers hit
-//   L1/L2 (astro x is shared by the ~20-90 rows of a star, the attitude
-//   block is a few MB at most).
-// aprod2: astrometric columns by a segmented scan over the star runs of a
-//   tile (carried across tiles), written once by the owning wave; attitude
-//   columns by FP64 atomics (LDS-private when the whole tail fits, otherwise
-//   device-scope); instrumental and global columns LDS-private per workgroup,
-//   flushed with one atomic per column per workgroup.
+//   L1/L2 (astrometric x is shared by the 20-90 rows of a star, the
+//   attitude block is a few MB at most).
+// aprod2 (this file: astrometric, instrumental, global; and the attitude
+//   block when it fits in LDS): astrometric columns by a segmented scan over
+//   the star runs of a tile, carried across tiles and written once by the
+//   owning wave; instrumental and global columns LDS-private per workgroup,
+//   flushed with one atomic per column per workgroup.  Larger attitude
+//   blocks are summed by the bucketed pass in attitude.hip; this pass then
+//   skips the 64-byte sectors that hold only attitude coefficients.
 #include <algorithm>
 
 #include "device_common.h"
@@ -27,11 +31,13 @@ template <typename VT>
 struct Geo;
 template <>
 struct Geo<double> {
-  static constexpr int CPR = 12;  // 16-byte chunks per row
+  static constexpr int CPR = 12;                // 16-byte chunks per row
+  static constexpr unsigned ATT_ONLY = 0x0F8u;  // chunks 3..7: bytes 48..127, attitude only
 };
 template <>
 struct Geo<float> {
   static constexpr int CPR = 6;
+  static constexpr unsigned ATT_ONLY = 0x00Cu;  // chunks 2..3: bytes 32..63, attitude only
 };
 
 // smallest s in [0, S] with row_ptr[s] >= target
@@ -55,71 +61,54 @@ __device__ inline void wave_stars(const SysView& s, int64_t w, int64_t W, int64_
   *s1 = (w == W - 1) ? s.n_stars : star_lower_bound(s.row_ptr, s.n_stars, t1);
 }
 
-template <typename VT>
-__device__ __forceinline__ double prod(VT a, double x, int pmode) {
-  if (pmode == 1) return (double)((float)a * (float)x);
+template <int PM, typename VT>
+__device__ __forceinline__ double prod(VT a, double x) {
+  if (PM == 1) return (double)((float)a * (float)x);
   return (double)a * x;
 }
 
-// Stage one tile of `nrow` rows starting at row t0 into this wave's LDS slab
-// and return the lane's row as 24 values.
-template <typename VT, int STAGE>
-__device__ __forceinline__ void load_tile_row(const SysView& s, int64_t t0, int nrow, u4* slab, int lane,
-                                              VT* a) {
-  constexpr int CPR = Geo<VT>::CPR;
-  const u4* g = reinterpret_cast<const u4*>(s.vals) + t0 * CPR;
-  if (STAGE == 0) {
-    u4 mine[CPR];
-#pragma unroll
-    for (int j = 0; j < CPR; ++j) mine[j] = (lane < nrow) ? ld_stream(g + lane * CPR + j) : u4{0u, 0u, 0u, 0u};
-    __builtin_memcpy(a, mine, sizeof(VT) * kSlots);
-    return;
-  }
-  const int nch = nrow * CPR;
-  u4 tmp[CPR];
-#pragma unroll
-  for (int j = 0; j < CPR; ++j) {
-    const int c = j * kWave + lane;
-    if (c < nch) tmp[j] = ld_stream(g + c);
-  }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-#pragma unroll
-  for (int j = 0; j < CPR; ++j) {
-    const int c = j * kWave + lane;
-    if (c < nch) {
-      const int r = c / CPR, q = c - r * CPR;
-      slab[r * (CPR + 1) + q] = tmp[j];
-    }
-  }
+// Stars of the tile's rows.  scur is the star of row t0 (wave-uniform); bnd is
+// 64 int64 of this wave's LDS.  Returns the lane's star and advances scur to
+// the star of row t0 + 64.
+__device__ __forceinline__ int64_t tile_stars(const SysView& s, int64_t t0, int lane, int64_t* bnd, int64_t& scur) {
+  const int64_t i = min(scur + 1 + lane, s.n_stars);
+  const int64_t b = s.row_ptr[i];
+  bnd[lane] = b;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  u4 mine[CPR];
-  if (lane < nrow) {
-#pragma unroll
-    for (int j = 0; j < CPR; ++j) mine[j] = slab[lane * (CPR + 1) + j];
-  } else {
-#pragma unroll
-    for (int j = 0; j < CPR; ++j) mine[j] = u4{0u, 0u, 0u, 0u};
+  const int64_t r = t0 + lane;
+  // lo = #{i : bnd[i] <= r}, bnd ascending
+  int lo = 0, hi = kWave;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (bnd[mid] <= r)
+      lo = mid + 1;
+    else
+      hi = mid;
   }
-  __builtin_memcpy(a, mine, sizeof(VT) * kSlots);
-}
-
-// Star of row r, scanning forward from s_hint (rows are sorted by star).
-__device__ __forceinline__ int64_t star_of(const int64_t* rp, int64_t s_hint, int64_t r) {
-  int64_t st = s_hint;
-  while (rp[st + 1] <= r) ++st;
+  int64_t st = scur + lo;
+  if (lo == kWave)  // more than 64 stars end inside this tile (empty or one-row stars)
+    while (st < s.n_stars - 1 && s.row_ptr[st + 1] <= r) ++st;
+  const uint64_t adv = __ballot(b <= t0 + kWave);
+  int64_t nxt = scur + __popcll(adv);
+  if (__popcll(adv) == kWave)
+    while (nxt < s.n_stars - 1 && s.row_ptr[nxt + 1] <= t0 + kWave) ++nxt;
+  nxt = min(nxt, max<int64_t>(s.n_stars - 1, 0));
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  scur = nxt;
   return st;
 }
 
 // ---------------------------------------------------------------- aprod1
-template <typename VT, int STAGE>
+template <typename VT, int PM>
 __global__ void __launch_bounds__(kBlock) k_aprod1(SysView s, int waves, const double* __restrict__ x,
-                                                   double* __restrict__ y, double scale, double ax, int pmode,
-                                                   Scalars* sc, Work wk, int lsqr_stage) {
+                                                   double* __restrict__ y, double scale, double ax, Scalars* sc,
+                                                   Work wk, int lsqr_stage) {
   constexpr int CPR = Geo<VT>::CPR;
-  __shared__ u4 slabs[kWavesPerBlock][STAGE ? kWave * (CPR + 1) : 1];
+  __shared__ u4 slabs[kWavesPerBlock][kWave * (CPR + 1)];
+  __shared__ int64_t bnds[kWavesPerBlock][kWave];
   __shared__ double red[kWavesPerBlock];
   __shared__ int flag;
   if (sc) {
@@ -136,35 +125,38 @@ __global__ void __launch_bounds__(kBlock) k_aprod1(SysView s, int waves, const d
     const int64_t NI = s.n_astro + 3 * s.n_att;
     const double xg = s.n_glob ? x[NI + s.n_instr] : 0.0;
     int64_t scur = s0;
+    while (scur < s1 && s.row_ptr[scur + 1] <= R0) ++scur;  // leading empty stars
     for (int64_t t0 = R0; t0 < R1; t0 += kWave) {
       const int nrow = (int)min((int64_t)kWave, R1 - t0);
-      // the tile's first star
-      while (s.row_ptr[scur + 1] <= t0) ++scur;
+      const bool valid = lane < nrow;
+      const int64_t r = t0 + (valid ? lane : 0);
+      // per-row index data and y, issued with the tile so that they share its latency
+      const int32_t at = __builtin_nontemporal_load(s.att_start + r);
+      const i2* icp = reinterpret_cast<const i2*>(s.instr_col + 6 * r);
+      const i2 i01 = __builtin_nontemporal_load(icp), i23 = __builtin_nontemporal_load(icp + 1),
+               i45 = __builtin_nontemporal_load(icp + 2);
+      const double yo = (scale == 0.0) ? 0.0 : y[r];
+      const int64_t st = tile_stars(s, t0, lane, bnds[wid], scur);
+      u4 mine[CPR];
+      stage_rows<CPR, 0u>(reinterpret_cast<const u4*>(s.vals) + t0 * CPR, nrow, slabs[wid], lane, mine);
       VT a[kSlots];
-      load_tile_row<VT, STAGE>(s, t0, nrow, slabs[wid], lane, a);
-      if (lane < nrow) {
-        const int64_t r = t0 + lane;
-        const int64_t st = star_of(s.row_ptr, scur, r);
-        const int32_t at = __builtin_nontemporal_load(s.att_start + r);
-        const i2* icp = reinterpret_cast<const i2*>(s.instr_col + 6 * r);
-        const i2 i01 = __builtin_nontemporal_load(icp), i23 = __builtin_nontemporal_load(icp + 1),
-                 i45 = __builtin_nontemporal_load(icp + 2);
+      __builtin_memcpy(a, mine, sizeof(a));
+      if (valid) {
         const int ic[6] = {i01.x, i01.y, i23.x, i23.y, i45.x, i45.y};
         double acc = 0.0;
         const double* xa = x + 5 * st;
 #pragma unroll
-        for (int k = 0; k < 5; ++k) acc += prod<VT>(a[k], xa[k], pmode);
+        for (int k = 0; k < 5; ++k) acc += prod<PM>(a[k], xa[k]);
 #pragma unroll
         for (int axs = 0; axs < 3; ++axs) {
           const double* xt = x + s.n_astro + axs * s.n_att + at;
 #pragma unroll
-          for (int j = 0; j < 4; ++j) acc += prod<VT>(a[5 + 4 * axs + j], xt[j], pmode);
+          for (int j = 0; j < 4; ++j) acc += prod<PM>(a[5 + 4 * axs + j], xt[j]);
         }
 #pragma unroll
-        for (int p = 0; p < 6; ++p) acc += prod<VT>(a[17 + p], x[NI + ic[p]], pmode);
-        if (s.n_glob) acc += prod<VT>(a[23], xg, pmode);
-        const double yo = (scale == 0.0) ? 0.0 : scale * y[r];
-        const double yn = yo + ax * acc;
+        for (int q = 0; q < 6; ++q) acc += prod<PM>(a[17 + q], x[NI + ic[q]]);
+        if (s.n_glob) acc += prod<PM>(a[23], xg);
+        const double yn = scale * yo + ax * acc;
         y[r] = yn;
         sumsq += yn * yn;
       }
@@ -183,19 +175,18 @@ __global__ void __launch_bounds__(kBlock) k_aprod1(SysView s, int waves, const d
 }
 
 // ---------------------------------------------------------------- aprod2
-// tail_mode 0: the whole tail (attitude, instrumental, global) in LDS.
-// tail_mode 1: attitude by device-scope atomics, instrumental + global in LDS.
-// tail_mode 2: attitude by atomics into a private copy per XCD (each XCD has
-//   its own L2; the copy of XCD x is only touched by waves running on x, so
-//   the atomics stay in that L2), instrumental + global in LDS.  The tail
-//   pass adds the copies.
-template <typename VT, int STAGE>
+// ATT_MODE 0: the whole tail (attitude, instrumental, global) in LDS.
+// ATT_MODE 1: attitude by device-scope FP64 atomics (fallback), instr + global in LDS.
+// ATT_MODE 3: attitude summed by the bucketed pass; its sectors are not read here.
+template <typename VT, int PM, int SQUARE, int ATT_MODE>
 __global__ void __launch_bounds__(kBlock) k_aprod2(SysView s, int waves, const double* __restrict__ y,
                                                    double* __restrict__ x, double* __restrict__ acc,
                                                    const double* __restrict__ S, double scale, double inv_beta,
-                                                   int pmode, int square, int tail_mode, Scalars* sc, Work wk) {
+                                                   Scalars* sc, Work wk) {
   constexpr int CPR = Geo<VT>::CPR;
-  __shared__ u4 slabs[kWavesPerBlock][STAGE ? kWave * (CPR + 1) : 1];
+  constexpr unsigned SKIP = (ATT_MODE == 3) ? Geo<VT>::ATT_ONLY : 0u;
+  __shared__ u4 slabs[kWavesPerBlock][kWave * (CPR + 1)];
+  __shared__ int64_t bnds[kWavesPerBlock][kWave];
   __shared__ double red[kWavesPerBlock];
   extern __shared__ double hist[];
   if (sc) {
@@ -205,10 +196,8 @@ __global__ void __launch_bounds__(kBlock) k_aprod2(SysView s, int waves, const d
   }
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   // LDS-private tail: [0, 3*n_att) attitude (mode 0 only), then instr, then global
-  const int64_t hoff = (tail_mode == 0) ? 0 : 3 * s.n_att;  // tail index of hist[0]
+  const int64_t hoff = (ATT_MODE == 0) ? 0 : 3 * s.n_att;  // tail index of hist[0]
   const int64_t hlen = s.tail_len - hoff;
-  double* acc_att = acc;
-  if (tail_mode == 2) acc_att = acc + s.tail_len + (int64_t)xcc_id() * 3 * s.n_att;
   for (int64_t j = threadIdx.x; j < hlen; j += kBlock) hist[j] = 0.0;
   __syncthreads();
 
@@ -219,55 +208,57 @@ __global__ void __launch_bounds__(kBlock) k_aprod2(SysView s, int waves, const d
     wave_stars(s, w, waves, &s0, &s1);
     const int64_t R0 = s.row_ptr[s0], R1 = s.row_ptr[s1];
     int64_t scur = s0;
+    while (scur < s1 && s.row_ptr[scur + 1] <= R0) ++scur;
     double carry[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     int carry_valid = 0;
     for (int64_t t0 = R0; t0 < R1; t0 += kWave) {
       const int nrow = (int)min((int64_t)kWave, R1 - t0);
-      while (s.row_ptr[scur + 1] <= t0) ++scur;
-      VT a[kSlots];
-      load_tile_row<VT, STAGE>(s, t0, nrow, slabs[wid], lane, a);
       const bool valid = lane < nrow;
       const int64_t r = t0 + (valid ? lane : 0);
-      const int64_t st = valid ? star_of(s.row_ptr, scur, r) : scur;
-      const int64_t rbeg = s.row_ptr[st], rend = s.row_ptr[st + 1];
-      const int seg0 = valid ? (int)(max(rbeg, t0) - t0) : lane;
+      const double t = SQUARE ? 0.0 : __builtin_nontemporal_load(y + r) * inv_beta;
+      const int32_t at = (ATT_MODE == 3) ? 0 : __builtin_nontemporal_load(s.att_start + r);
+      const i2* icp = reinterpret_cast<const i2*>(s.instr_col + 6 * r);
+      const i2 i01 = __builtin_nontemporal_load(icp), i23 = __builtin_nontemporal_load(icp + 1),
+               i45 = __builtin_nontemporal_load(icp + 2);
+      const int64_t st = tile_stars(s, t0, lane, bnds[wid], scur);
+      u4 mine[CPR];
+      stage_rows<CPR, SKIP>(reinterpret_cast<const u4*>(s.vals) + t0 * CPR, nrow, slabs[wid], lane, mine);
+      VT a[kSlots];
+      __builtin_memcpy(a, mine, sizeof(a));
+      const int64_t rend = s.row_ptr[st + 1];
+      const int seg0 = valid ? (int)(max(s.row_ptr[st], t0) - t0) : lane;
       double p[5];
       if (valid) {
-        const double t = square ? 0.0 : __builtin_nontemporal_load(y + r) * inv_beta;
-        const int32_t at = __builtin_nontemporal_load(s.att_start + r);
-        const i2* icp = reinterpret_cast<const i2*>(s.instr_col + 6 * r);
-        const i2 i01 = __builtin_nontemporal_load(icp), i23 = __builtin_nontemporal_load(icp + 1),
-                 i45 = __builtin_nontemporal_load(icp + 2);
         const int ic[6] = {i01.x, i01.y, i23.x, i23.y, i45.x, i45.y};
 #pragma unroll
-        for (int k = 0; k < 5; ++k) p[k] = square ? (double)a[k] * (double)a[k] : prod<VT>(a[k], t, pmode);
+        for (int k = 0; k < 5; ++k) p[k] = SQUARE ? (double)a[k] * (double)a[k] : prod<PM>(a[k], t);
+        if (ATT_MODE != 3) {
 #pragma unroll
-        for (int axs = 0; axs < 3; ++axs) {
-          const int64_t col = axs * s.n_att + at;  // tail index
+          for (int axs = 0; axs < 3; ++axs) {
+            const int64_t col = axs * s.n_att + at;  // tail index
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const VT av = a[5 + 4 * axs + j];
-            const double c = square ? (double)av * (double)av : prod<VT>(av, t, pmode);
-            if (tail_mode == 0)
-              atomicAdd(hist + col + j, c);
-            else if (tail_mode == 1)
-              atomicAdd(acc_att + col + j, c);
-            else
-              __hip_atomic_fetch_add(acc_att + col + j, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            for (int j = 0; j < 4; ++j) {
+              const VT av = a[5 + 4 * axs + j];
+              const double c = SQUARE ? (double)av * (double)av : prod<PM>(av, t);
+              if (ATT_MODE == 0)
+                atomicAdd(hist + col + j, c);
+              else
+                atomicAdd(acc + col + j, c);
+            }
           }
         }
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
           const VT av = a[17 + q];
-          const double c = square ? (double)av * (double)av : prod<VT>(av, t, pmode);
+          const double c = SQUARE ? (double)av * (double)av : prod<PM>(av, t);
           atomicAdd(hist + (3 * s.n_att - hoff) + ic[q], c);
         }
-        if (s.n_glob) gsum += square ? (double)a[23] * (double)a[23] : prod<VT>(a[23], t, pmode);
+        if (s.n_glob) gsum += SQUARE ? (double)a[23] * (double)a[23] : prod<PM>(a[23], t);
       } else {
 #pragma unroll
         for (int k = 0; k < 5; ++k) p[k] = 0.0;
       }
-      // carried partial sums of a star that began in an earlier tile
+      // partial sums carried from the star that began in an earlier tile
       if (carry_valid && lane == 0) {
 #pragma unroll
         for (int k = 0; k < 5; ++k) p[k] += carry[k];
@@ -331,21 +322,16 @@ __global__ void __launch_bounds__(kBlock) k_aprod2(SysView s, int waves, const d
 }
 
 // ------------------------------------------------------------------ tail
-// x_t <- scale*x_t + S_t * acc_t for the attitude, instrumental and global
-// unknowns; acc is cleared for the next product.  In an LSQR solve the last
-// workgroup forms alpha_{i+1}, applies the rotations of the iteration and
-// buffers d_i[sel] = w_i[sel] / rho_i as one covariance column.
-struct TailLsqr {
-  int lsqr_stage;       // 0 init, 1 iteration
-  int astro_parts;      // partials written by the aprod2 launch
-  const int64_t* sel;   // selected unknowns (nsel = sc->nsel)
-  const double* w;      // search direction w_i
-  double* D;            // [nsel][dblock]
-};
-
-__global__ void __launch_bounds__(kBlock) k_tail(SysView s, double* __restrict__ x, double* __restrict__ acc,
-                                                 const double* __restrict__ S, double scale, Scalars* sc, Work wk,
-                                                 TailLsqr L, int xcd_copies) {
+// x_t <- scale*x_t + S_t * (sum of the tail contributions) for the attitude,
+// instrumental and global unknowns; acc is cleared for the next product.  With
+// the bucketed attitude pass, attitude column c of axis a adds the window
+// partials Q[sub][a][c - b*Wb] of the (at most two) buckets b whose window
+// [b*Wb, b*Wb + Wb + 3) covers c.  In an LSQR solve the last workgroup forms
+// alpha_{i+1}, applies the plane rotations of the iteration and buffers
+// d_i[sel] = w_i[sel] / rho_i as one covariance column.
+__global__ void __launch_bounds__(kBlock) k_tail(SysView s, AttView av, int att_mode, double* __restrict__ x,
+                                                 double* __restrict__ acc, const double* __restrict__ S, double scale,
+                                                 Scalars* sc, Work wk, TailLsqr L) {
   __shared__ double red[kWavesPerBlock];
   __shared__ int flag;
   int work = 1;
@@ -357,16 +343,21 @@ __global__ void __launch_bounds__(kBlock) k_tail(SysView s, double* __restrict__
   double sumsq = 0.0;
   if (work) {
     const int64_t natt = 3 * s.n_att;
+    const int64_t win = av.Wb + 3;
     for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < s.tail_len; j += (int64_t)gridDim.x * kBlock) {
-      double a = acc[j];
-      acc[j] = 0.0;
-      if (xcd_copies && j < natt) {
-#pragma unroll
-        for (int x = 0; x < kXcds; ++x) {
-          double* q = acc + s.tail_len + x * natt + j;
-          a += *q;
-          *q = 0.0;
+      double a;
+      if (att_mode == 3 && j < natt) {
+        const int64_t axs = j / s.n_att, c = j - axs * s.n_att;
+        a = 0.0;
+        const int64_t bhi = min(c / av.Wb, av.nb - 1);
+        for (int64_t b = max<int64_t>(bhi - 1, 0); b <= bhi; ++b) {
+          const int64_t off = c - b * av.Wb;
+          if (off < 0 || off >= win) continue;
+          for (int32_t q = av.bsub[b]; q < av.bsub[b + 1]; ++q) a += av.Q[((int64_t)q * 3 + axs) * win + off];
         }
+      } else {
+        a = acc[j];
+        acc[j] = 0.0;
       }
       const int64_t c = s.n_astro + j;
       const double xo = (scale == 0.0) ? 0.0 : scale * x[c];
@@ -427,7 +418,7 @@ __global__ void k_scale_from_sq(int64_t n, double* S) {
 }
 
 // ------------------------------------------------------------ launchers
-StreamShape stream_shape(const SysView& s, int cus, int waves_per_cu, int stage, int xcd_copies) {
+StreamShape stream_shape(const SysView& s, int cus, int waves_per_cu) {
   // never more waves than stars or row tiles, never more blocks than partial slots
   int64_t waves = (int64_t)cus * waves_per_cu;
   waves = std::min(waves, (int64_t)kMaxPartials * kWavesPerBlock);
@@ -437,68 +428,65 @@ StreamShape stream_shape(const SysView& s, int cus, int waves_per_cu, int stage,
   StreamShape sh;
   sh.waves = (int)waves;
   sh.blocks = (int)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
-  sh.stage = stage;
-  sh.xcd_copies = xcd_copies;
   return sh;
-}
-
-template <int STAGE>
-static void aprod1_go(const SysView& s, StreamShape sh, const double* x, double* y, double scale, double ax,
-                      int pmode, Scalars* sc, Work w, int lsqr_stage, hipStream_t st) {
-  if (s.value_type == GSR_F32)
-    hipLaunchKernelGGL((k_aprod1<float, STAGE>), dim3(sh.blocks), dim3(kBlock), 0, st, s, sh.waves, x, y, scale, ax,
-                       pmode, sc, w, lsqr_stage);
-  else
-    hipLaunchKernelGGL((k_aprod1<double, STAGE>), dim3(sh.blocks), dim3(kBlock), 0, st, s, sh.waves, x, y, scale,
-                       ax, 0, sc, w, lsqr_stage);
 }
 
 hipError_t launch_aprod1(const SysView& s, StreamShape sh, const double* x, double* y, double scale, double ax,
                          int pmode, Scalars* sc, Work w, int lsqr_stage, hipStream_t st) {
-  if (sh.stage)
-    aprod1_go<1>(s, sh, x, y, scale, ax, pmode, sc, w, lsqr_stage, st);
+  const dim3 g(sh.blocks), b(kBlock);
+  if (s.value_type == GSR_F32 && pmode == 1)
+    hipLaunchKernelGGL((k_aprod1<float, 1>), g, b, 0, st, s, sh.waves, x, y, scale, ax, sc, w, lsqr_stage);
+  else if (s.value_type == GSR_F32)
+    hipLaunchKernelGGL((k_aprod1<float, 0>), g, b, 0, st, s, sh.waves, x, y, scale, ax, sc, w, lsqr_stage);
   else
-    aprod1_go<0>(s, sh, x, y, scale, ax, pmode, sc, w, lsqr_stage, st);
+    hipLaunchKernelGGL((k_aprod1<double, 0>), g, b, 0, st, s, sh.waves, x, y, scale, ax, sc, w, lsqr_stage);
   return hipGetLastError();
 }
 
-int tail_mode_of(const SysView& s, int xcd_copies) {
+int att_mode_of(const SysView& s, const AttView& av, int force_atomics) {
   if (s.tail_len <= kLdsTailMax) return 0;
-  return xcd_copies ? 2 : 1;
+  if (force_atomics || !av.ready) return 1;
+  return 3;
 }
 
-template <int STAGE>
-static void aprod2_go(const SysView& s, StreamShape sh, const double* y, double* x, double* acc, const double* S,
-                      double scale, double inv_beta, int pmode, int square, int tm, size_t hbytes, Scalars* sc,
-                      Work w, hipStream_t st) {
-  if (s.value_type == GSR_F32)
-    hipLaunchKernelGGL((k_aprod2<float, STAGE>), dim3(sh.blocks), dim3(kBlock), hbytes, st, s, sh.waves, y, x, acc,
-                       S, scale, inv_beta, pmode, square, tm, sc, w);
+template <typename VT, int PM, int SQ>
+static void aprod2_mode(int mode, const SysView& s, StreamShape sh, const double* y, double* x, double* acc,
+                        const double* S, double scale, double inv_beta, size_t hb, Scalars* sc, Work w,
+                        hipStream_t st) {
+  const dim3 g(sh.blocks), b(kBlock);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_aprod2<VT, PM, SQ, 0>), g, b, hb, st, s, sh.waves, y, x, acc, S, scale, inv_beta, sc, w);
+  else if (mode == 1)
+    hipLaunchKernelGGL((k_aprod2<VT, PM, SQ, 1>), g, b, hb, st, s, sh.waves, y, x, acc, S, scale, inv_beta, sc, w);
   else
-    hipLaunchKernelGGL((k_aprod2<double, STAGE>), dim3(sh.blocks), dim3(kBlock), hbytes, st, s, sh.waves, y, x,
-                       acc, S, scale, inv_beta, 0, square, tm, sc, w);
+    hipLaunchKernelGGL((k_aprod2<VT, PM, SQ, 3>), g, b, hb, st, s, sh.waves, y, x, acc, S, scale, inv_beta, sc, w);
 }
 
-hipError_t launch_aprod2(const SysView& s, StreamShape sh, const double* y, double* x, double* acc, const double* S,
-                         double scale, double inv_beta, int pmode, int square, Scalars* sc, Work w,
+hipError_t launch_aprod2(const SysView& s, StreamShape sh, int att_mode, const double* y, double* x, double* acc,
+                         const double* S, double scale, double inv_beta, int pmode, int square, Scalars* sc, Work w,
                          hipStream_t st) {
-  const int tm = tail_mode_of(s, sh.xcd_copies);
-  const size_t hbytes = sizeof(double) * (size_t)(tm == 0 ? s.tail_len : s.tail_len - 3 * s.n_att);
-  if (sh.stage)
-    aprod2_go<1>(s, sh, y, x, acc, S, scale, inv_beta, pmode, square, tm, hbytes, sc, w, st);
-  else
-    aprod2_go<0>(s, sh, y, x, acc, S, scale, inv_beta, pmode, square, tm, hbytes, sc, w, st);
+  const size_t hb = sizeof(double) * (size_t)(att_mode == 0 ? s.tail_len : s.tail_len - 3 * s.n_att);
+  if (square) {
+    if (s.value_type == GSR_F32)
+      aprod2_mode<float, 0, 1>(att_mode, s, sh, y, x, acc, S, scale, inv_beta, hb, sc, w, st);
+    else
+      aprod2_mode<double, 0, 1>(att_mode, s, sh, y, x, acc, S, scale, inv_beta, hb, sc, w, st);
+  } else if (s.value_type == GSR_F32 && pmode == 1) {
+    aprod2_mode<float, 1, 0>(att_mode, s, sh, y, x, acc, S, scale, inv_beta, hb, sc, w, st);
+  } else if (s.value_type == GSR_F32) {
+    aprod2_mode<float, 0, 0>(att_mode, s, sh, y, x, acc, S, scale, inv_beta, hb, sc, w, st);
+  } else {
+    aprod2_mode<double, 0, 0>(att_mode, s, sh, y, x, acc, S, scale, inv_beta, hb, sc, w, st);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_tail(const SysView& s, double* x, double* acc, const double* S, double scale, int square,
-                       Scalars* sc, Work w, int lsqr_stage, int astro_parts, const int64_t* sel, const double* wv,
-                       double* D, int xcd_copies, hipStream_t st) {
-  (void)square;
-  int blocks = (int)std::min<int64_t>(256, std::max<int64_t>(1, (s.tail_len + kBlock - 1) / kBlock));
+hipError_t launch_tail(const SysView& s, const AttView& av, int att_mode, double* x, double* acc, const double* S,
+                       double scale, Scalars* sc, Work w, int lsqr_stage, int astro_parts, const int64_t* sel,
+                       const double* wv, double* D, hipStream_t st) {
+  int blocks = (int)std::min<int64_t>(512, std::max<int64_t>(1, (s.tail_len + kBlock - 1) / kBlock));
   TailLsqr L{lsqr_stage, astro_parts, sel, wv, D};
-  hipLaunchKernelGGL(k_tail, dim3(blocks), dim3(kBlock), 0, st, s, x, acc, S, scale, sc, w, L,
-                     tail_mode_of(s, xcd_copies) == 2 ? 1 : 0);
+  hipLaunchKernelGGL(k_tail, dim3(blocks), dim3(kBlock), 0, st, s, av, att_mode, x, acc, S, scale, sc, w, L);
   return hipGetLastError();
 }
 

@@ -54,9 +54,9 @@ struct gsr_system {
   int device = 0;
   int cus = 256;
   int waves_per_cu = 32;
-  int stage = 1;
-  int xcd_copies = 0;
+  int att_atomics = 0;  // 1: attitude sums by device atomics instead of the bucketed pass
   StreamShape sh{};
+  AttView av{};
   Scalars* sc = nullptr;
   Scalars* sc_host = nullptr;  // pinned
   Work wk{};
@@ -147,9 +147,9 @@ extern "C" int64_t gsr_num_unknowns(const gsr_dims* d) {
   return 5 * d->n_stars + 3 * d->n_att + d->n_instr + d->n_glob;
 }
 
-static void reshape(gsr_system* s) {
-  s->sh = stream_shape(s->s, s->cus, s->waves_per_cu, s->stage, s->xcd_copies);
-}
+static void reshape(gsr_system* s) { s->sh = stream_shape(s->s, s->cus, s->waves_per_cu); }
+
+static int att_mode(const gsr_system* s) { return att_mode_of(s->s, s->av, s->att_atomics); }
 
 static void release(gsr_system* s) {
   (void)hipDeviceSynchronize();
@@ -174,6 +174,7 @@ static void release(gsr_system* s) {
   dfree(s->sel);
   dfree(s->D);
   dfree(s->Cacc);
+  att_free(&s->av);
   for (auto e : s->pool) (void)hipEventDestroy(e);
   for (auto& p : s->pending) {
     (void)hipEventDestroy(p.a);
@@ -230,14 +231,14 @@ extern "C" int gsr_create(gsr_system** out, const gsr_dims* d, const void* vals,
   };
   if ((rc = dalloc(&s->sc, 1)) || (rc = dalloc(&s->wk.part_a, kMaxPartials)) ||
       (rc = dalloc(&s->wk.part_b, kMaxPartials)) || (rc = dalloc(&s->wk.part_c, kMaxPartials)) ||
-      (rc = dalloc(&s->wk.tickets, 8)) || (rc = dalloc(&s->acc, (size_t)(v.tail_len + kXcds * 3 * v.n_att))))
+      (rc = dalloc(&s->wk.tickets, 8)) || (rc = dalloc(&s->acc, (size_t)v.tail_len)))
     return bail(rc);
   if (hipHostMalloc((void**)&s->sc_host, sizeof(Scalars), hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
     return bail(fail(GSR_ENOMEM, "pinned host allocation failed"));
   }
   if (hipMemsetAsync(s->wk.tickets, 0, 8 * sizeof(unsigned), st) != hipSuccess ||
-      hipMemsetAsync(s->acc, 0, (size_t)(v.tail_len + kXcds * 3 * v.n_att) * sizeof(double), st) != hipSuccess)
+      hipMemsetAsync(s->acc, 0, (size_t)v.tail_len * sizeof(double), st) != hipSuccess)
     return bail(fail(GSR_EHIP, "workspace clear failed"));
 
   // index validation on the device
@@ -261,6 +262,16 @@ extern "C" int gsr_create(gsr_system** out, const gsr_dims* d, const void* vals,
   if (hb[0] != ~0ull) return bail(fail(GSR_EINVAL, "att_start / instr_col out of range at row %llu", hb[0]));
   v.has_empty_stars = hb[2] != 0;
   reshape(s);
+  if (v.tail_len > kLdsTailMax && v.m > 0) {
+    // attitude block too large for LDS: build the attitude-bucketed copy
+    char msg[256] = "";
+    rc = att_build(v, &s->av, s->cus, msg, sizeof msg, st);
+    if (rc == GSR_ENOMEM) {
+      s->att_atomics = 1;  // not enough memory for the copy: device atomics
+    } else if (rc != GSR_OK) {
+      return bail(fail(rc, "attitude view: %s", msg));
+    }
+  }
   {
     std::lock_guard<std::mutex> lk(g_mu);
     g_live.insert(s);
@@ -280,13 +291,12 @@ extern "C" int gsr_destroy(gsr_system* s) {
   return GSR_OK;
 }
 
-extern "C" int gsr_set_tuning(gsr_system* s, int32_t waves_per_cu, int32_t stage, int32_t xcd_copies) {
+extern "C" int gsr_set_tuning(gsr_system* s, int32_t waves_per_cu, int32_t att_atomics) {
   CHK(check_handle(s));
-  if (waves_per_cu < 1 || waves_per_cu > 256 || (stage != 0 && stage != 1) || (xcd_copies != 0 && xcd_copies != 1))
-    return fail(GSR_EINVAL, "waves_per_cu in [1,256], stage and xcd_copies in {0,1}");
+  if (waves_per_cu < 1 || waves_per_cu > 256 || (att_atomics != 0 && att_atomics != 1))
+    return fail(GSR_EINVAL, "waves_per_cu in [1,256], att_atomics in {0,1}");
   s->waves_per_cu = waves_per_cu;
-  s->stage = stage;
-  s->xcd_copies = xcd_copies;
+  s->att_atomics = att_atomics || !s->av.ready;
   reshape(s);
   return GSR_OK;
 }
@@ -373,16 +383,29 @@ extern "C" int gsr_aprod1(gsr_system* s, const double* x, double* y, double scal
   return GSR_OK;
 }
 
-static int aprod2_raw(gsr_system* s, const double* y, double* x, double scale_x, int32_t product, int square,
-                      hipStream_t st) {
+// aprod 2 in LSQR form (sc != nullptr: scale / 1/beta from the device scalars) or standalone.
+static int aprod2_launches(gsr_system* s, const double* y, double* x, const double* S, double scale, int32_t product,
+                           int square, Scalars* sc, int lsqr_stage, hipStream_t st) {
+  const int mode = att_mode(s);
   {
     TimeScope ts(s, 1, st);
-    HIPCHK(launch_aprod2(s->s, s->sh, y, x, s->acc, nullptr, scale_x, 1.0, product, square, nullptr, s->wk, st));
+    if (mode == 3 && !square) HIPCHK(launch_partition(s->s, s->av, y, sc, st));
+    HIPCHK(launch_aprod2(s->s, s->sh, mode, y, x, s->acc, S, scale, 1.0, product, square, sc, s->wk, st));
+    if (mode == 3) HIPCHK(launch_att_pass(s->s, s->av, 1.0, product, square, sc, st));
   }
   TimeScope ts(s, 2, st);
-  HIPCHK(launch_tail(s->s, x, s->acc, nullptr, scale_x, square, nullptr, s->wk, 0, 0, nullptr, nullptr, nullptr,
-                     s->sh.xcd_copies, st));
+  if (sc)
+    HIPCHK(launch_tail(s->s, s->av, mode, x, s->acc, S, 0.0, sc, s->wk, lsqr_stage, s->sh.blocks, s->sel, s->w, s->D,
+                       st));
+  else
+    HIPCHK(launch_tail(s->s, s->av, mode, x, s->acc, nullptr, scale, nullptr, s->wk, 0, 0, nullptr, nullptr, nullptr,
+                       st));
   return GSR_OK;
+}
+
+static int aprod2_raw(gsr_system* s, const double* y, double* x, double scale_x, int32_t product, int square,
+                      hipStream_t st) {
+  return aprod2_launches(s, y, x, nullptr, scale_x, product, square, nullptr, 0, st);
 }
 
 extern "C" int gsr_aprod2(gsr_system* s, const double* y, double* x, double scale_x, int32_t product,
@@ -471,9 +494,7 @@ static int lsqr_begin(gsr_system* s, const double* b, const double* x0, const gs
     HIPCHK(launch_aprod1(s->s, s->sh, x0, s->u, 1.0, -1.0, 0, nullptr, s->wk, 0, st));
   HIPCHK(launch_norm_init(s->u, s->s.m, s->sc, s->wk, st));
   // alpha_1 v_1 = S A^T u_1
-  HIPCHK(launch_aprod2(s->s, s->sh, s->u, s->v, s->acc, S, 0.0, 1.0, product, 0, s->sc, s->wk, st));
-  HIPCHK(launch_tail(s->s, s->v, s->acc, S, 0.0, 0, s->sc, s->wk, 0, s->sh.blocks, s->sel, s->w, s->D,
-                     s->sh.xcd_copies, st));
+  CHK(aprod2_launches(s, s->u, s->v, S, 0.0, product, 0, s->sc, 0, st));
   HIPCHK(launch_init_vectors(s->s.n, s->v, s->vg, s->w, s->y, s->var, S, s->sc, st));
   s->in_session = 1;
   return GSR_OK;
@@ -494,15 +515,7 @@ static int lsqr_iterate(gsr_system* s, int64_t nit, hipStream_t st) {
       TimeScope ts(s, 0, st);
       HIPCHK(launch_aprod1(s->s, s->sh, vg, s->u, 0.0, 1.0, s->pmode, s->sc, s->wk, 1, st));
     }
-    {
-      TimeScope ts(s, 1, st);
-      HIPCHK(launch_aprod2(s->s, s->sh, s->u, s->v, s->acc, S, 0.0, 1.0, s->pmode, 0, s->sc, s->wk, st));
-    }
-    {
-      TimeScope ts(s, 2, st);
-      HIPCHK(launch_tail(s->s, s->v, s->acc, S, 0.0, 0, s->sc, s->wk, 1, s->sh.blocks, s->sel, s->w, s->D,
-                         s->sh.xcd_copies, st));
-    }
+    CHK(aprod2_launches(s, s->u, s->v, S, 0.0, s->pmode, 0, s->sc, 1, st));
     {
       TimeScope ts(s, 3, st);
       HIPCHK(launch_update(s->s.n, s->v, vg, s->w, s->y, s->var, S, s->sc, s->wk, st));

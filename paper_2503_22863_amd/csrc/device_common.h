@@ -12,10 +12,37 @@ typedef int i2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ u4 ld_stream(const u4* p) { return __builtin_nontemporal_load(p); }
 
-// Index of the XCD (accelerator complex die) the wave runs on: hardware
-// register XCC_ID (20), bits 3:0 on gfx942 / gfx950; kept in [0, kXcds).
-__device__ __forceinline__ unsigned xcc_id() {
-  return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & (kXcds - 1);
+
+// Stage one tile of `nrow` rows of CPR 16-byte chunks each (starting at chunk
+// pointer g) through this wave's LDS slab (row stride CPR + 1 chunks, so that
+// row-per-lane reads are free of bank conflicts) and return the lane's row.
+// Chunks whose bit is set in SKIP are neither loaded nor returned (zero).
+template <int CPR, unsigned SKIP>
+__device__ __forceinline__ void stage_rows(const u4* __restrict__ g, int nrow, u4* slab, int lane, u4* mine) {
+  const int nch = nrow * CPR;
+  u4 tmp[CPR];
+#pragma unroll
+  for (int j = 0; j < CPR; ++j) {
+    const int c = j * kWave + lane;
+    const int q = c % CPR;
+    if (c < nch && !((SKIP >> q) & 1u)) tmp[j] = ld_stream(g + c);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int j = 0; j < CPR; ++j) {
+    const int c = j * kWave + lane;
+    const int r = c / CPR, q = c - r * CPR;
+    if (c < nch && !((SKIP >> q) & 1u)) slab[r * (CPR + 1) + q] = tmp[j];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+  for (int j = 0; j < CPR; ++j)
+    mine[j] = (lane < nrow && !((SKIP >> j) & 1u)) ? slab[lane * (CPR + 1) + j] : u4{0u, 0u, 0u, 0u};
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
 }
 
 __device__ __forceinline__ double wave_sum(double v) {

@@ -14,7 +14,6 @@ constexpr int kBlock = 256;        // threads per workgroup (4 waves)
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kSlots = 24;         // coefficients per row: 5 astro, 12 attitude, 6 instr, 1 global
 constexpr int kMaxPartials = 4096; // upper bound on workgroups of a reducing launch
-constexpr int kXcds = 8;           // XCDs of an MI355X, each with its own L2
 constexpr int kLdsTailMax = 2048;  // tail columns accumulated in LDS when they fit (16 KB)
 
 // Device-resident LSQR state.  Written only by the single "last" workgroup of
@@ -70,24 +69,64 @@ struct SysView {
 struct StreamShape {
   int blocks;
   int waves;
-  int stage;       // 1: coefficient tiles staged through LDS, 0: direct row loads
-  int xcd_copies;  // 1: attitude atomics into one private copy per XCD
 };
-StreamShape stream_shape(const SysView& s, int cus, int waves_per_cu, int stage, int xcd_copies);
+StreamShape stream_shape(const SysView& s, int cus, int waves_per_cu);
+
+// Attitude-bucketed view of the system, built once per handle when the
+// attitude block does not fit in LDS.  Rows are grouped by bucket
+// b = att_start / Wb (Wb consecutive attitude starts per bucket); inside a
+// bucket they keep star order, chunk by chunk (chunks of K consecutive rows).
+// The attitude part of aprod 2 then reads the 12 attitude coefficients of
+// each row in bucket order (batt) together with u permuted into the same
+// order (ub, written each product by the partition pass) and accumulates the
+// bucket's window of Wb + 3 columns per axis in LDS.
+struct AttView {
+  int ready;            // 1 once built
+  int64_t Wb, nb;       // bucket width, buckets
+  int64_t K, nchunks;   // partition chunk rows, chunks
+  int32_t* count;       // [nchunks][nb] rows of chunk c in bucket b
+  int32_t* cbase;       // [nchunks][nb] bucket-order position of the first such row
+  uint16_t* lpos;       // [m] position of row r in its chunk's bucket-grouped order
+  void* batt;           // [m][12] attitude coefficients in bucket order (value type)
+  uint16_t* bst;        // [m] att_start - b*Wb in bucket order
+  int32_t nsub;         // workgroup ranges of the attitude pass
+  int64_t* sub_lo;      // [nsub+1] bucket-order row ranges
+  int32_t* sub_b;       // [nsub] bucket of each range
+  int32_t* bsub;        // [nb+1] first range of each bucket
+  double* Q;            // [nsub][3][Wb+3] window partial sums
+  double* ub;           // [m] u in bucket order
+};
+
+// LSQR epilogue arguments of the tail pass.
+struct TailLsqr {
+  int lsqr_stage;       // 0 init, 1 iteration
+  int astro_parts;      // partials written by the aprod2 launch
+  const int64_t* sel;   // selected unknowns (nsel = sc->nsel)
+  const double* w;      // search direction w_i
+  double* D;            // [nsel][dblock]
+};
 
 // ---- launchers (all asynchronous on `st`) ---------------------------------
 // y <- scale*y + ax * A x (or with the LSQR scalars: scale = sc->u_scale, ax = 1,
 // and the last workgroup forms beta_{i+1}); mode: 0 FP64 products, 1 FP32 products.
 hipError_t launch_aprod1(const SysView& s, StreamShape sh, const double* x, double* y, double scale,
                          double ax, int pmode, Scalars* sc, Work w, int lsqr_stage, hipStream_t st);
-// astro part of x <- scale*x + S*(A^T (inv_beta*y)); tail part accumulated in acc.
-hipError_t launch_aprod2(const SysView& s, StreamShape sh, const double* y, double* x, double* acc,
-                         const double* S, double scale, double inv_beta, int pmode, int square,
+// astro part of x <- scale*x + S*(A^T (inv_beta*y)); tail part accumulated in acc
+// (attitude part by the bucketed pass when att_mode == 3).
+hipError_t launch_aprod2(const SysView& s, StreamShape sh, int att_mode, const double* y, double* x,
+                         double* acc, const double* S, double scale, double inv_beta, int pmode, int square,
                          Scalars* sc, Work w, hipStream_t st);
-// tail part: x_t <- scale*x_t + S_t * acc_t, acc cleared; LSQR epilogue when sc != nullptr.
-hipError_t launch_tail(const SysView& s, double* x, double* acc, const double* S, double scale,
-                       int square, Scalars* sc, Work w, int lsqr_stage, int astro_parts,
-                       const int64_t* sel, const double* wv, double* D, int xcd_copies, hipStream_t st);
+// tail part: x_t <- scale*x_t + S_t * (acc_t or window sums), acc cleared; LSQR epilogue when sc != nullptr.
+hipError_t launch_tail(const SysView& s, const AttView& av, int att_mode, double* x, double* acc, const double* S,
+                       double scale, Scalars* sc, Work w, int lsqr_stage, int astro_parts, const int64_t* sel,
+                       const double* wv, double* D, hipStream_t st);
+int att_mode_of(const SysView& s, const AttView& av, int force_atomics);
+// bucketed attitude pass (attitude.hip)
+int att_build(const SysView& s, AttView* av, int cus, char* err, size_t errlen, hipStream_t st);
+void att_free(AttView* av);
+hipError_t launch_partition(const SysView& s, const AttView& av, const double* u, Scalars* sc, hipStream_t st);
+hipError_t launch_att_pass(const SysView& s, const AttView& av, double inv_beta, int pmode, int square,
+                           Scalars* sc, hipStream_t st);
 // bad[0] <- first row with an out-of-range index, bad[1] <- first bad star, bad[2] <- 1 if a star is empty
 hipError_t launch_validate(const SysView& s, unsigned long long* bad, hipStream_t st);
 hipError_t launch_scale_from_sq(int64_t n, double* S, hipStream_t st);
@@ -107,7 +146,6 @@ hipError_t launch_cov_out(const double* C, int64_t k, const double* S, const int
                           hipStream_t st);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
 hipError_t launch_axpy_norms(int64_t n, const double* dx, double* x, double* out2, Work w, hipStream_t st);
-int tail_mode_of(const SysView& s, int xcd_copies);
 
 // learned warm start (mlp.hip)
 hipError_t launch_features(const SysView& s, const double* b, const double* xo, double* F, hipStream_t st);

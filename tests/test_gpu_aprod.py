@@ -19,6 +19,8 @@ CASES = {
     "tiny_1000x20": dict(n_stars=1000, obs=20, n_att=64, n_instr=32, n_glob=1, seed=2503),
     "wide_attitude": dict(n_stars=3000, obs=(50, 90), n_att=2500, n_instr=200, n_glob=1, seed=10),
     "one_star": dict(n_stars=1, obs=300, n_att=4, n_instr=6, n_glob=1, seed=11),
+    "att_buckets_small": dict(n_stars=20, obs=(0, 50), n_att=1000, n_instr=6, n_glob=0, seed=12),
+    "att_buckets_many_chunks": dict(n_stars=700, obs=(40, 100), n_att=800, n_instr=40, n_glob=1, seed=13),
 }
 
 
@@ -54,7 +56,7 @@ def dev():
     return gsr
 
 
-@pytest.mark.parametrize("tuning", [(32, 1, 0), (32, 0, 0), (8, 1, 1)])
+@pytest.mark.parametrize("tuning", [(32, 0), (8, 0), (32, 1)])
 @pytest.mark.parametrize("case", list(CASES))
 def test_aprod_fp64(dev, oracle_lib, case, tuning):
     print(f"[aprod fp64] case={case} tuning={tuning}", flush=True)

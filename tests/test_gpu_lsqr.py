@@ -131,10 +131,11 @@ def test_lsqr_edge_cases(dev, oracle_lib):
     b = oracle_lib.known_terms(o, g.x_true, g.noise)
     x, _, r = S.lsqr_solve(torch.from_numpy(b).cuda(), itmax=0)
     assert r["itn"] == 0 and torch.all(x == 0)
-    b0 = oracle_lib.known_terms(o, g.x_true, np.zeros(g.dims.m))
+    # x0 solving the system exactly: b0 = A x0 formed by the same product, so b0 - A x0 = 0 bit for bit
     x0 = torch.from_numpy(g.x_true).cuda()
-    x, _, r = S.lsqr_solve(torch.from_numpy(b0).cuda(), x0=x0, itmax=50)
-    assert r["itn"] == 0 and torch.equal(x, x0)
+    b0 = S.aprod1(x0)
+    x, _, r = S.lsqr_solve(b0, x0=x0, itmax=50)
+    assert r["itn"] == 0 and r["istop"] == 0 and torch.equal(x, x0)
     S.close()
 
 
