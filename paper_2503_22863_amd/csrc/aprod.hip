@@ -67,12 +67,17 @@ __device__ __forceinline__ double prod(VT a, double x) {
   return (double)a * x;
 }
 
-// Stars of the tile's rows.  scur is the star of row t0 (wave-uniform); bnd is
-// 64 int64 of this wave's LDS.  Returns the lane's star and advances scur to
-// the star of row t0 + 64.
-__device__ __forceinline__ int64_t tile_stars(const SysView& s, int64_t t0, int lane, int64_t* bnd, int64_t& scur) {
-  const int64_t i = min(scur + 1 + lane, s.n_stars);
-  const int64_t b = s.row_ptr[i];
+// Star boundaries for a tile whose first row is in star scur: lane i holds
+// row_ptr[scur + 1 + i] (the end row of star scur + i), clamped at n_stars.
+__device__ __forceinline__ int64_t bnd_load(const SysView& s, int64_t scur, int lane) {
+  return s.row_ptr[min(scur + 1 + lane, s.n_stars)];
+}
+
+// Stars of the tile's rows from the loaded boundaries b (searched in this
+// wave's LDS bnd[64]).  Returns the lane's star and advances scur to the star
+// of row t0 + 64.
+__device__ __forceinline__ int64_t tile_stars(const SysView& s, int64_t b, int64_t t0, int lane, int64_t* bnd,
+                                              int64_t& scur, int64_t* rbeg = nullptr, int64_t* rend = nullptr) {
   bnd[lane] = b;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -88,8 +93,16 @@ __device__ __forceinline__ int64_t tile_stars(const SysView& s, int64_t t0, int 
       hi = mid;
   }
   int64_t st = scur + lo;
-  if (lo == kWave)  // more than 64 stars end inside this tile (empty or one-row stars)
+  if (lo == kWave) {  // more than 64 stars end inside this tile (empty or one-row stars)
     while (st < s.n_stars - 1 && s.row_ptr[st + 1] <= r) ++st;
+    if (rbeg) *rbeg = s.row_ptr[st];
+    if (rend) *rend = s.row_ptr[st + 1];
+  } else {
+    // star st = scur + lo spans rows [row_ptr[st], row_ptr[st+1]) = [bnd[lo-1], bnd[lo]);
+    // for lo = 0 it began at or before t0
+    if (rbeg) *rbeg = lo > 0 ? bnd[lo - 1] : t0;
+    if (rend) *rend = bnd[lo];
+  }
   const uint64_t adv = __ballot(b <= t0 + kWave);
   int64_t nxt = scur + __popcll(adv);
   if (__popcll(adv) == kWave)
@@ -126,37 +139,61 @@ __global__ void __launch_bounds__(kBlock) k_aprod1(SysView s, int waves, const d
     const double xg = s.n_glob ? x[NI + s.n_instr] : 0.0;
     int64_t scur = s0;
     while (scur < s1 && s.row_ptr[scur + 1] <= R0) ++scur;  // leading empty stars
+    const u4* vbase = reinterpret_cast<const u4*>(s.vals);
+    // registers of the prefetched tile
+    u4 tmp[CPR];
+    int32_t at;
+    i2 i01, i23, i45;
+    double yo;
+    int64_t bv;
+    auto fetch = [&](int64_t tt) {
+      const int nr = (int)max<int64_t>(0, min((int64_t)kWave, R1 - tt));
+      const int64_t rr = (lane < nr) ? tt + lane : R1 - 1;  // always a valid row
+      issue_chunks<CPR, 0u>(vbase + tt * CPR, nr, lane, tmp);
+      at = __builtin_nontemporal_load(s.att_start + rr);
+      const i2* icp = reinterpret_cast<const i2*>(s.instr_col + 6 * rr);
+      i01 = __builtin_nontemporal_load(icp);
+      i23 = __builtin_nontemporal_load(icp + 1);
+      i45 = __builtin_nontemporal_load(icp + 2);
+      yo = (scale == 0.0) ? 0.0 : y[rr];
+      bv = bnd_load(s, scur, lane);
+    };
+    if (R0 < R1) fetch(R0);
+#pragma unroll 1
     for (int64_t t0 = R0; t0 < R1; t0 += kWave) {
       const int nrow = (int)min((int64_t)kWave, R1 - t0);
       const bool valid = lane < nrow;
       const int64_t r = t0 + (valid ? lane : 0);
-      // per-row index data and y, issued with the tile so that they share its latency
-      const int32_t at = __builtin_nontemporal_load(s.att_start + r);
-      const i2* icp = reinterpret_cast<const i2*>(s.instr_col + 6 * r);
-      const i2 i01 = __builtin_nontemporal_load(icp), i23 = __builtin_nontemporal_load(icp + 1),
-               i45 = __builtin_nontemporal_load(icp + 2);
-      const double yo = (scale == 0.0) ? 0.0 : y[r];
-      const int64_t st = tile_stars(s, t0, lane, bnds[wid], scur);
+      const int32_t at_c = at;
+      const int ic[6] = {i01.x, i01.y, i23.x, i23.y, i45.x, i45.y};
+      const double yo_c = yo;
       u4 mine[CPR];
-      stage_rows<CPR, 0u>(reinterpret_cast<const u4*>(s.vals) + t0 * CPR, nrow, slabs[wid], lane, mine);
+      lds_rows<CPR, 0u>(tmp, nrow, slabs[wid], lane, mine);
+      const int64_t st = tile_stars(s, bv, t0, lane, bnds[wid], scur);
       VT a[kSlots];
       __builtin_memcpy(a, mine, sizeof(a));
+      // gathers of x for this tile, then the next tile's loads
+      double gx[kSlots];
+      const double* xa = x + 5 * st;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) gx[k] = xa[k];
+#pragma unroll
+      for (int axs = 0; axs < 3; ++axs) {
+        const double* xt = x + s.n_astro + axs * s.n_att + at_c;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) gx[5 + 4 * axs + j] = xt[j];
+      }
+#pragma unroll
+      for (int q = 0; q < 6; ++q) gx[17 + q] = x[NI + ic[q]];
+      order_point();
+      fetch(t0 + kWave);  // past the end: chunk loads off, index loads from a valid row
+      order_point();
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < 23; ++k) acc += prod<PM>(a[k], gx[k]);
+      if (s.n_glob) acc += prod<PM>(a[23], xg);
       if (valid) {
-        const int ic[6] = {i01.x, i01.y, i23.x, i23.y, i45.x, i45.y};
-        double acc = 0.0;
-        const double* xa = x + 5 * st;
-#pragma unroll
-        for (int k = 0; k < 5; ++k) acc += prod<PM>(a[k], xa[k]);
-#pragma unroll
-        for (int axs = 0; axs < 3; ++axs) {
-          const double* xt = x + s.n_astro + axs * s.n_att + at;
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc += prod<PM>(a[5 + 4 * axs + j], xt[j]);
-        }
-#pragma unroll
-        for (int q = 0; q < 6; ++q) acc += prod<PM>(a[17 + q], x[NI + ic[q]]);
-        if (s.n_glob) acc += prod<PM>(a[23], xg);
-        const double yn = scale * yo + ax * acc;
+        const double yn = scale * yo_c + ax * acc;
         y[r] = yn;
         sumsq += yn * yn;
       }
@@ -211,31 +248,51 @@ __global__ void __launch_bounds__(kBlock) k_aprod2(SysView s, int waves, const d
     while (scur < s1 && s.row_ptr[scur + 1] <= R0) ++scur;
     double carry[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     int carry_valid = 0;
+    const u4* vbase = reinterpret_cast<const u4*>(s.vals);
+    u4 tmp[CPR];
+    double tv;
+    int32_t at;
+    i2 i01, i23, i45;
+    int64_t bv;
+    auto fetch = [&](int64_t tt) {
+      const int nr = (int)max<int64_t>(0, min((int64_t)kWave, R1 - tt));
+      const int64_t rr = (lane < nr) ? tt + lane : R1 - 1;  // always a valid row
+      issue_chunks<CPR, SKIP>(vbase + tt * CPR, nr, lane, tmp);
+      tv = SQUARE ? 0.0 : __builtin_nontemporal_load(y + rr);
+      at = (ATT_MODE == 3) ? 0 : __builtin_nontemporal_load(s.att_start + rr);
+      const i2* icp = reinterpret_cast<const i2*>(s.instr_col + 6 * rr);
+      i01 = __builtin_nontemporal_load(icp);
+      i23 = __builtin_nontemporal_load(icp + 1);
+      i45 = __builtin_nontemporal_load(icp + 2);
+      bv = bnd_load(s, scur, lane);
+    };
+    if (R0 < R1) fetch(R0);
+#pragma unroll 1
     for (int64_t t0 = R0; t0 < R1; t0 += kWave) {
       const int nrow = (int)min((int64_t)kWave, R1 - t0);
       const bool valid = lane < nrow;
       const int64_t r = t0 + (valid ? lane : 0);
-      const double t = SQUARE ? 0.0 : __builtin_nontemporal_load(y + r) * inv_beta;
-      const int32_t at = (ATT_MODE == 3) ? 0 : __builtin_nontemporal_load(s.att_start + r);
-      const i2* icp = reinterpret_cast<const i2*>(s.instr_col + 6 * r);
-      const i2 i01 = __builtin_nontemporal_load(icp), i23 = __builtin_nontemporal_load(icp + 1),
-               i45 = __builtin_nontemporal_load(icp + 2);
-      const int64_t st = tile_stars(s, t0, lane, bnds[wid], scur);
+      const double t = tv * inv_beta;
+      const int32_t at_c = at;
+      const int ic[6] = {i01.x, i01.y, i23.x, i23.y, i45.x, i45.y};
       u4 mine[CPR];
-      stage_rows<CPR, SKIP>(reinterpret_cast<const u4*>(s.vals) + t0 * CPR, nrow, slabs[wid], lane, mine);
+      lds_rows<CPR, SKIP>(tmp, nrow, slabs[wid], lane, mine);
+      int64_t rbeg, rend;
+      const int64_t st = tile_stars(s, bv, t0, lane, bnds[wid], scur, &rbeg, &rend);
+      order_point();
+      fetch(t0 + kWave);  // past the end: chunk loads off, index loads from a valid row
+      order_point();
       VT a[kSlots];
       __builtin_memcpy(a, mine, sizeof(a));
-      const int64_t rend = s.row_ptr[st + 1];
-      const int seg0 = valid ? (int)(max(s.row_ptr[st], t0) - t0) : lane;
+      const int seg0 = valid ? (int)(max(rbeg, t0) - t0) : lane;
       double p[5];
       if (valid) {
-        const int ic[6] = {i01.x, i01.y, i23.x, i23.y, i45.x, i45.y};
 #pragma unroll
         for (int k = 0; k < 5; ++k) p[k] = SQUARE ? (double)a[k] * (double)a[k] : prod<PM>(a[k], t);
         if (ATT_MODE != 3) {
 #pragma unroll
           for (int axs = 0; axs < 3; ++axs) {
-            const int64_t col = axs * s.n_att + at;  // tail index
+            const int64_t col = axs * s.n_att + at_c;  // tail index
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
               const VT av = a[5 + 4 * axs + j];

@@ -42,6 +42,18 @@ __global__ void k_bk_count(SysView s, AttView av) {
   for (int64_t b = threadIdx.x; b < av.nb; b += blockDim.x) av.count[c * av.nb + b] = hist_i[b];
 }
 
+// lst[c][b] = rows of chunk c in buckets before b (local start of bucket b's run)
+__global__ void k_bk_lstart(AttView av) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= av.nchunks) return;
+  int32_t run = 0;
+  for (int64_t b = 0; b < av.nb; ++b) {
+    av.lst[c * (av.nb + 1) + b] = run;
+    run += av.count[c * av.nb + b];
+  }
+  av.lst[c * (av.nb + 1) + av.nb] = run;
+}
+
 // cbase[c][b] = rows of bucket b in chunks before c; btot[b] = rows of bucket b
 __global__ void k_bk_colscan(AttView av, int32_t* btot) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -67,13 +79,9 @@ __global__ void __launch_bounds__(kWave) k_bk_rank(SysView s, AttView av, int32_
   int* cur = lds_i + av.nb;    // [nb] rows of each bucket placed so far
   const int64_t c = blockIdx.x;
   const int lane = threadIdx.x;
-  if (lane == 0) {
-    int run = 0;
-    for (int64_t b = 0; b < av.nb; ++b) {
-      lstart[b] = run;
-      run += av.count[c * av.nb + b];
-      cur[b] = 0;
-    }
+  for (int64_t b = lane; b < av.nb; b += kWave) {
+    lstart[b] = av.lst[c * (av.nb + 1) + b];
+    cur[b] = 0;
   }
   __syncthreads();
   const int64_t r0 = c * av.K, r1 = min(s.m, r0 + av.K);
@@ -112,7 +120,7 @@ __global__ void k_bk_scatter(SysView s, AttView av, const int32_t* dest) {
 }
 
 void att_free(AttView* av) {
-  for (void* p : {(void*)av->count, (void*)av->cbase, (void*)av->lpos, av->batt, (void*)av->bst, (void*)av->sub_lo,
+  for (void* p : {(void*)av->count, (void*)av->cbase, (void*)av->lst, (void*)av->lpos, av->batt, (void*)av->bst, (void*)av->sub_lo,
                   (void*)av->sub_b, (void*)av->bsub, (void*)av->Q, (void*)av->ub})
     if (p) (void)hipFree(p);
   *av = AttView{};
@@ -150,6 +158,7 @@ int att_build(const SysView& s, AttView* av, int cus, char* err, size_t errlen, 
   const size_t vsz = s.value_type == GSR_F32 ? sizeof(float) : sizeof(double);
   ATT_CHK(hipMalloc((void**)&av->count, sizeof(int32_t) * av->nchunks * av->nb));
   ATT_CHK(hipMalloc((void**)&av->cbase, sizeof(int32_t) * av->nchunks * av->nb));
+  ATT_CHK(hipMalloc((void**)&av->lst, sizeof(int32_t) * av->nchunks * (av->nb + 1)));
   ATT_CHK(hipMalloc((void**)&av->lpos, sizeof(uint16_t) * m));
   ATT_CHK(hipMalloc((void**)&av->batt, vsz * 12 * m));
   ATT_CHK(hipMalloc((void**)&av->bst, sizeof(uint16_t) * m));
@@ -161,6 +170,8 @@ int att_build(const SysView& s, AttView* av, int cus, char* err, size_t errlen, 
   hipLaunchKernelGGL(k_bk_count, dim3((unsigned)av->nchunks), dim3(256), sizeof(int) * av->nb, st, s, *av);
   ATT_CHK(hipGetLastError());
   hipLaunchKernelGGL(k_bk_colscan, dim3((unsigned)((av->nb + 63) / 64)), dim3(64), 0, st, *av, btot);
+  ATT_CHK(hipGetLastError());
+  hipLaunchKernelGGL(k_bk_lstart, dim3((unsigned)((av->nchunks + 255) / 256)), dim3(256), 0, st, *av);
   ATT_CHK(hipGetLastError());
   std::vector<int32_t> tot(av->nb);
   ATT_CHK(hipMemcpyAsync(tot.data(), btot, sizeof(int32_t) * av->nb, hipMemcpyDeviceToHost, st));
@@ -217,14 +228,7 @@ __global__ void __launch_bounds__(kBlock) k_partition(SysView s, AttView av, con
   const int64_t c = blockIdx.x;
   const int64_t r0 = c * av.K;
   const int n = (int)min(av.K, s.m - r0);
-  if (threadIdx.x == 0) {
-    int run = 0;
-    for (int64_t b = 0; b < av.nb; ++b) {
-      ls[b] = run;
-      run += av.count[c * av.nb + b];
-    }
-    ls[av.nb] = run;
-  }
+  for (int64_t b = threadIdx.x; b <= av.nb; b += kBlock) ls[b] = av.lst[c * (av.nb + 1) + b];
   for (int i = threadIdx.x; i < n; i += kBlock) buf[av.lpos[r0 + i]] = __builtin_nontemporal_load(u + r0 + i);
   __syncthreads();
   for (int p = threadIdx.x; p < n; p += kBlock) {
@@ -258,14 +262,30 @@ __global__ void __launch_bounds__(kBlock) k_att_pass(SysView s, AttView av, doub
   const int64_t sub = blockIdx.x;
   const int64_t lo = av.sub_lo[sub], hi = av.sub_lo[sub + 1];
   const u4* base = reinterpret_cast<const u4*>(av.batt);
-  for (int64_t t0 = lo + (int64_t)wid * kWave; t0 < hi; t0 += (int64_t)kWavesPerBlock * kWave) {
+  u4 tmp[CPR];
+  double tv;
+  int sov;
+  auto fetch = [&](int64_t tt) {
+    const int nr = (int)max<int64_t>(0, min((int64_t)kWave, hi - tt));
+    const int64_t ii = (lane < nr) ? tt + lane : hi - 1;  // always a valid row of the range
+    issue_chunks<CPR, 0u>(base + tt * CPR, nr, lane, tmp);
+    tv = SQUARE ? 0.0 : __builtin_nontemporal_load(av.ub + ii);
+    sov = av.bst[ii];
+  };
+  const int64_t step = (int64_t)kWavesPerBlock * kWave;
+  int64_t t0 = lo + (int64_t)wid * kWave;
+  if (t0 < hi) fetch(t0);
+#pragma unroll 1
+  for (; t0 < hi; t0 += step) {
     const int nrow = (int)min((int64_t)kWave, hi - t0);
     const bool valid = lane < nrow;
-    const int64_t i = t0 + (valid ? lane : 0);
-    const double t = SQUARE ? 0.0 : __builtin_nontemporal_load(av.ub + i) * inv_beta;
-    const int so = av.bst[i];
+    const double t = tv * inv_beta;
+    const int so = sov;
     u4 mine[CPR];
-    stage_rows<CPR, 0u>(base + t0 * CPR, nrow, slabs[wid], lane, mine);
+    lds_rows<CPR, 0u>(tmp, nrow, slabs[wid], lane, mine);
+    order_point();
+    fetch(t0 + step);
+    order_point();
     VT a[12];
     __builtin_memcpy(a, mine, sizeof(a));
     if (valid) {

@@ -13,20 +13,28 @@ typedef int i2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ u4 ld_stream(const u4* p) { return __builtin_nontemporal_load(p); }
 
 
-// Stage one tile of `nrow` rows of CPR 16-byte chunks each (starting at chunk
-// pointer g) through this wave's LDS slab (row stride CPR + 1 chunks, so that
-// row-per-lane reads are free of bank conflicts) and return the lane's row.
-// Chunks whose bit is set in SKIP are neither loaded nor returned (zero).
+// Row tiles are moved in two steps so that the next tile's loads can be in
+// flight while the current tile is processed:
+//   issue_chunks: the tile's nrow rows of CPR 16-byte chunks (starting at chunk
+//     pointer g) as contiguous 16-byte nontemporal loads, chunk j*64+lane in
+//     register j (chunks whose bit is set in SKIP are not loaded);
+//   lds_rows: writes those registers to this wave's LDS slab (row stride CPR+1
+//     chunks, so that row-per-lane reads are free of bank conflicts) and reads
+//     back the lane's own row (skipped chunks read as zero).
 template <int CPR, unsigned SKIP>
-__device__ __forceinline__ void stage_rows(const u4* __restrict__ g, int nrow, u4* slab, int lane, u4* mine) {
+__device__ __forceinline__ void issue_chunks(const u4* __restrict__ g, int nrow, int lane, u4* tmp) {
   const int nch = nrow * CPR;
-  u4 tmp[CPR];
 #pragma unroll
   for (int j = 0; j < CPR; ++j) {
     const int c = j * kWave + lane;
     const int q = c % CPR;
     if (c < nch && !((SKIP >> q) & 1u)) tmp[j] = ld_stream(g + c);
   }
+}
+
+template <int CPR, unsigned SKIP>
+__device__ __forceinline__ void lds_rows(const u4* tmp, int nrow, u4* slab, int lane, u4* mine) {
+  const int nch = nrow * CPR;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
 #pragma unroll
@@ -44,6 +52,12 @@ __device__ __forceinline__ void stage_rows(const u4* __restrict__ g, int nrow, u
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
 }
+
+// Keeps the compiler from moving memory operations across this point (used to
+// issue the current tile's gathers before the next tile's prefetch: vector
+// loads complete in order, so a later wait on the gathers must not also wait
+// on the prefetch).
+__device__ __forceinline__ void order_point() { __builtin_amdgcn_sched_barrier(0); }
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

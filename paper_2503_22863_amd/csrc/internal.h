@@ -86,6 +86,7 @@ struct AttView {
   int64_t K, nchunks;   // partition chunk rows, chunks
   int32_t* count;       // [nchunks][nb] rows of chunk c in bucket b
   int32_t* cbase;       // [nchunks][nb] bucket-order position of the first such row
+  int32_t* lst;         // [nchunks][nb+1] rows of chunk c in buckets before b
   uint16_t* lpos;       // [m] position of row r in its chunk's bucket-grouped order
   void* batt;           // [m][12] attitude coefficients in bucket order (value type)
   uint16_t* bst;        // [m] att_start - b*Wb in bucket order
