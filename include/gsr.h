@@ -208,6 +208,12 @@ int gsr_syrk(const double *D, int64_t k, int64_t cols, int64_t ldd, double *C, g
  * unchanged up to the order of FP64 additions. */
 int gsr_set_tuning(gsr_system *sys, int32_t waves_per_cu, int32_t att_atomics);
 
+/* Replay of captured HIP graphs for blocks of LSQR iterations (16, or the
+ * covariance block), on by default; per-kernel timing disables it.  The
+ * graphs run on a stream of the handle, ordered with the caller's stream by
+ * events. */
+int gsr_set_graphs(gsr_system *sys, int32_t on);
+
 /* Per-kernel timing with HIP events on the solve's stream (off by default).
  * gsr_timing_get synchronises, returns the totals since the last get and
  * resets them. */

@@ -81,6 +81,13 @@ struct gsr_system {
   const double* x0 = nullptr;
   int64_t itmax = 0;
   int64_t enq = 0;
+  // graph replay of blocks of iterations (launch-bound small systems)
+  int use_graphs = 1;
+  hipStream_t gstream = nullptr;  // non-blocking stream the graphs are captured and replayed on
+  hipGraphExec_t gexec = nullptr;
+  hipEvent_t gev[2] = {nullptr, nullptr};
+  int64_t gsize = 0;
+  uint64_t gkey = 0;
   // timing
   int timing = 0;
   std::vector<hipEvent_t> pool;
@@ -175,6 +182,10 @@ static void release(gsr_system* s) {
   dfree(s->D);
   dfree(s->Cacc);
   att_free(&s->av);
+  if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+  for (auto e : s->gev)
+    if (e) (void)hipEventDestroy(e);
+  if (s->gstream) (void)hipStreamDestroy(s->gstream);
   for (auto e : s->pool) (void)hipEventDestroy(e);
   for (auto& p : s->pending) {
     (void)hipEventDestroy(p.a);
@@ -298,6 +309,12 @@ extern "C" int gsr_set_tuning(gsr_system* s, int32_t waves_per_cu, int32_t att_a
   s->waves_per_cu = waves_per_cu;
   s->att_atomics = att_atomics || !s->av.ready;
   reshape(s);
+  return GSR_OK;
+}
+
+extern "C" int gsr_set_graphs(gsr_system* s, int32_t on) {
+  CHK(check_handle(s));
+  s->use_graphs = on != 0;
   return GSR_OK;
 }
 
@@ -507,25 +524,91 @@ extern "C" int gsr_lsqr_begin(gsr_system* s, const double* b, const double* x0, 
   return lsqr_begin(s, b, x0, o, o->product, (hipStream_t)stream);
 }
 
-static int lsqr_iterate(gsr_system* s, int64_t nit, hipStream_t st) {
+// One LSQR iteration: aprod 1, aprod 2 (+ tail), update, and the covariance
+// SYRK when a block of `dblock` columns is complete.
+static int enqueue_iteration(gsr_system* s, hipStream_t st) {
   const double* S = s->precond ? s->S : nullptr;
   double* vg = s->precond ? s->vg : s->v;
-  for (int64_t i = 0; i < nit && s->enq < s->itmax; ++i) {
-    {
-      TimeScope ts(s, 0, st);
-      HIPCHK(launch_aprod1(s->s, s->sh, vg, s->u, 0.0, 1.0, s->pmode, s->sc, s->wk, 1, st));
+  {
+    TimeScope ts(s, 0, st);
+    HIPCHK(launch_aprod1(s->s, s->sh, vg, s->u, 0.0, 1.0, s->pmode, s->sc, s->wk, 1, st));
+  }
+  CHK(aprod2_launches(s, s->u, s->v, S, 0.0, s->pmode, 0, s->sc, 1, st));
+  {
+    TimeScope ts(s, 3, st);
+    HIPCHK(launch_update(s->s.n, s->v, vg, s->w, s->y, s->var, S, s->sc, s->wk, st));
+  }
+  s->enq += 1;
+  if (s->nsel > 0 && s->enq % s->dblock == 0) {
+    TimeScope ts(s, 4, st);
+    HIPCHK(launch_syrk(s->D, s->nsel, s->dblock, s->Cacc, s->sc, s->wk, -1, st));
+  }
+  return GSR_OK;
+}
+
+static void drop_graph(gsr_system* s) {
+  if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+  s->gexec = nullptr;
+  s->gsize = 0;
+}
+
+// Replays of a captured block of iterations.  The kernels of an iteration are
+// identical from one iteration to the next (all per-iteration values live in
+// the device scalar struct), so a block captured once is replayed for the
+// rest of the solve and for later solves with the same configuration.  The
+// graph runs on the handle's own stream, ordered after and before the
+// caller's stream by events (the null stream cannot be captured).
+static int graph_block(gsr_system* s, int64_t G, hipStream_t st) {
+  const uint64_t key = ((uint64_t)s->precond << 0) | ((uint64_t)s->pmode << 1) | ((uint64_t)(s->nsel > 0) << 2) |
+                       ((uint64_t)G << 3) | ((uint64_t)s->att_atomics << 40) | ((uint64_t)s->waves_per_cu << 41);
+  if (!s->gstream) {
+    HIPCHK(hipStreamCreateWithFlags(&s->gstream, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&s->gev[0], hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&s->gev[1], hipEventDisableTiming));
+  }
+  HIPCHK(hipEventRecord(s->gev[0], st));
+  HIPCHK(hipStreamWaitEvent(s->gstream, s->gev[0], 0));
+  if (!s->gexec || s->gkey != key) {
+    drop_graph(s);
+    const int64_t enq0 = s->enq;
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(s->gstream, hipStreamCaptureModeThreadLocal));
+    int rc = GSR_OK;
+    for (int64_t i = 0; i < G && rc == GSR_OK; ++i) rc = enqueue_iteration(s, s->gstream);
+    hipError_t e = hipStreamEndCapture(s->gstream, &g);
+    s->enq = enq0;
+    if (rc != GSR_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
     }
-    CHK(aprod2_launches(s, s->u, s->v, S, 0.0, s->pmode, 0, s->sc, 1, st));
-    {
-      TimeScope ts(s, 3, st);
-      HIPCHK(launch_update(s->s.n, s->v, vg, s->w, s->y, s->var, S, s->sc, s->wk, st));
+    if (e != hipSuccess) return fail(GSR_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      s->gexec = nullptr;
+      return fail(GSR_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
     }
-    s->enq += 1;
-    if (s->nsel > 0 && s->enq % s->dblock == 0) {
-      TimeScope ts(s, 4, st);
-      HIPCHK(launch_syrk(s->D, s->nsel, s->dblock, s->Cacc, s->sc, s->wk, -1, st));
+    s->gkey = key;
+    s->gsize = G;
+  }
+  HIPCHK(hipGraphLaunch(s->gexec, s->gstream));
+  HIPCHK(hipEventRecord(s->gev[1], s->gstream));
+  HIPCHK(hipStreamWaitEvent(st, s->gev[1], 0));
+  s->enq += G;
+  return GSR_OK;
+}
+
+static int lsqr_iterate(gsr_system* s, int64_t nit, hipStream_t st) {
+  // blocks of G iterations by graph replay when no per-kernel timing is requested;
+  // with covariances a block is the covariance block, aligned to it
+  const int64_t G = s->nsel > 0 ? s->dblock : 16;
+  if (s->use_graphs && !s->timing) {
+    while (nit >= G && s->itmax - s->enq >= G && (s->nsel == 0 || s->enq % G == 0)) {
+      CHK(graph_block(s, G, st));
+      nit -= G;
     }
   }
+  for (int64_t i = 0; i < nit && s->enq < s->itmax; ++i) CHK(enqueue_iteration(s, st));
   return GSR_OK;
 }
 
@@ -688,6 +771,7 @@ extern "C" int gsr_cov_request(gsr_system* s, const int64_t* sel, int64_t k, int
     if (sel[p] < 0 || sel[p] >= s->s.n) return fail(GSR_EINVAL, "sel[%lld] = %lld out of range", (long long)p,
                                                      (long long)sel[p]);
   (void)hipDeviceSynchronize();
+  drop_graph(s);
   dfree(s->sel);
   dfree(s->D);
   dfree(s->Cacc);
