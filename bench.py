@@ -263,10 +263,10 @@ def main():
     a2 = tm["aprod2_ms"] / max(1, tm["aprod2_n"])
     bytes1 = APROD1_B_ROW * m
     bytes2 = APROD2_B_ROW * m + APROD2_B_STAR * ns
-    if a2 >= a1:
-        kname, ms, by = "k_aprod2", a2, bytes2
-    else:
-        kname, ms, by = "k_aprod1", a1, bytes1
+    # k_aprod1 is the longest single kernel of the step: aprod 2 runs as a partition, a
+    # star pass, an attitude pass and a tail, each shorter (the kernel-trace summary
+    # lists them); its four-kernel total is reported under "aprod".
+    kname, ms, by = "k_aprod1", a1, bytes1
     achieved = by / (ms * 1e-3) / 1e9
     workload = "share_1m"
     traffic = load_traffic(kname, workload)

@@ -4,7 +4,8 @@ refinement) with the CPU oracle.
 LSQR iterates past the point where the Krylov basis loses orthogonality are
 themselves sensitive to rounding (the oracle perturbed at the last bit of b
 or of A moves them by up to ~1e-8 on the unscaled 1,000-star system, and
-moves the variances of a converged run by ~1e-4).  Converged solutions are
+moves the variances of a converged run by ~1e-4, its anorm estimate by ~1e-5).
+Converged solutions are
 held to 1e-10; unconverged iterates and post-convergence variances are held
 to 1e-12 or, when the oracle's own last-bit sensitivity is larger, to 10x
 that sensitivity."""
@@ -43,19 +44,22 @@ def _sensitivity(oracle_lib, g, o, b, **kw):
     """The oracle's own response to last-bit perturbations: b and, separately, every
     coefficient of A scaled by (1 + 2.2e-16 N(0,1)) (the size of the rounding differences
     between two valid summation orders).  Returns the reference run and the largest
-    relative deviations of x and var over three perturbed runs."""
+    relative deviations of x and var over three perturbed runs; the deviations of the
+    scalar estimates (rnorm, anorm, ...) are kept in r1["sens"]."""
     import copy
 
     r1 = oracle_lib.lsqr(o, b, **kw)
-    sx = sv = 0.0
+    runs = []
     for seed in (5, 6):
         bp = b * (1 + 2e-16 * np.random.default_rng(seed).standard_normal(b.size))
-        r2 = oracle_lib.lsqr(o, bp, **kw)
-        sx, sv = max(sx, _rel(r2["x"], r1["x"])), max(sv, _rel(r2["var"], r1["var"]))
+        runs.append(oracle_lib.lsqr(o, bp, **kw))
     gp = copy.copy(g)
     gp.vals = g.vals * (1 + 2.2e-16 * np.random.default_rng(7).standard_normal(g.vals.shape))
-    r3 = oracle_lib.lsqr(oracle_lib.OSystem(gp), b, **kw)
-    sx, sv = max(sx, _rel(r3["x"], r1["x"])), max(sv, _rel(r3["var"], r1["var"]))
+    runs.append(oracle_lib.lsqr(oracle_lib.OSystem(gp), b, **kw))
+    sx = max(_rel(r["x"], r1["x"]) for r in runs)
+    sv = max(_rel(r["var"], r1["var"]) for r in runs)
+    r1["sens"] = {k: max(abs(r[k] - r1[k]) / max(abs(r1[k]), 1e-300) for r in runs)
+                  for k in ("rnorm", "anorm", "acond", "xnorm", "bnorm")}
     return r1, sx, sv
 
 
@@ -73,8 +77,9 @@ def test_lsqr_converged_tiny_precond(dev, oracle_lib, tiny):
     assert abs(r["itn"] - ref["itn"]) <= 1
     assert _rel(x, ref["x"]) <= 1e-10
     assert _rel(var, ref["var"]) <= max(1e-10, 10 * sv)
+    # anorm and acond keep accumulating alpha and beta after convergence, as var does
     for k in ("rnorm", "anorm", "acond", "xnorm", "bnorm"):
-        assert abs(r[k] - ref[k]) <= 1e-6 * abs(ref[k]) + 1e-300, k
+        assert abs(r[k] - ref[k]) <= max(1e-6, 10 * ref["sens"][k]) * abs(ref[k]) + 1e-300, k
     # ||A^T r|| at the solution is at rounding level: compare on the scale of the stop test
     assert abs(r["arnorm"] - ref["arnorm"]) <= 0.05 * ref["arnorm"] + 1e-16 * ref["anorm"] * ref["rnorm"]
 
