@@ -1,14 +1,15 @@
 """Throughput of the AVU-GSR LSQR hot path on one MI355X.
 
-A step is one LSQR iteration (aprod 1, aprod 2 with its tail pass, the
-x / w / variance update and the scalar recurrences) on the one-GPU share:
+A step is one LSQR iteration (both products A v and A^T u -- one fused pass
+over the rows plus the bucketed attitude pass -- the tail pass, the x / w /
+variance update and the scalar recurrences) on the one-GPU share:
 1,000,000 stars with U[50,90] observations each (m ~ 7.0e7 rows,
 ~1.7e9 nonzeros), 3 x 40,000 attitude, 200 instrumental and 1 global
 unknown, FP64 coefficients N(0,1), plain (unscaled) FP64 LSQR with damp 0.
 
-Prints one JSON line: iterations/s, the roofline of the dominant product
-kernel (HIP-event timing inside the timed region), and the CPU oracle timed
-on a bounded sample of the same workload.
+Prints one JSON line: iterations/s, the roofline of the dominant kernel (the
+fused row pass; HIP-event timing inside the timed region), and the CPU oracle
+timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -23,15 +24,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per row / per star (FP64 values, int32 indices)
-APROD1_B_ROW = 192 + 4 + 24 + 16  # coefficients, attitude start, 6 instr columns, y read+write
-APROD2_B_ROW = 192 + 4 + 24 + 8  # coefficients, attitude start, 6 instr columns, u read
-APROD2_B_STAR = 80  # astrometric x read+write
+# Algorithmic bytes of the fused row pass (one per LSQR iteration), FP64 values and
+# int32 indices: per row the 24 coefficients, the attitude start, the 6 instrumental
+# columns, u read and u written; per star the 5 astrometric v read and the 5 raw
+# column sums written.
+FUSED_B_ROW = 192 + 4 + 24 + 8 + 8
+FUSED_B_STAR = 40 + 40
 
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("aprod.hip", "device_common.h", "internal.h"):
+    for f in ("fused.hip", "row_tiles.h", "device_common.h", "internal.h"):
         with open(os.path.join(ROOT, "paper_2503_22863_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -259,15 +262,12 @@ def main():
         raise RuntimeError(f"solve stopped early (itn={st['itn']}, istop={st['istop']}): timed steps not all real")
     S.lsqr_end(want_var=False)
 
-    a1 = tm["aprod1_ms"] / max(1, tm["aprod1_n"])
-    a2 = tm["aprod2_ms"] / max(1, tm["aprod2_n"])
-    bytes1 = APROD1_B_ROW * m
-    bytes2 = APROD2_B_ROW * m + APROD2_B_STAR * ns
-    # k_aprod1 is the longest single kernel of the step: aprod 2 runs as a partition, a
-    # star pass, an attitude pass and a tail, each shorter (the kernel-trace summary
-    # lists them); its four-kernel total is reported under "aprod".
-    kname, ms, by = "k_aprod1", a1, bytes1
-    achieved = by / (ms * 1e-3) / 1e9
+    # timing scopes of an iteration: the fused row pass, the attitude passes
+    # (partition of u and the bucketed sums), the tail, the x / w / var update
+    f_ms = tm["aprod1_ms"] / max(1, tm["aprod1_n"])
+    att_ms = tm["aprod2_ms"] / max(1, tm["aprod2_n"])
+    kname, by = "k_fused", FUSED_B_ROW * m + FUSED_B_STAR * ns
+    achieved = by / (f_ms * 1e-3) / 1e9
     workload = "share_1m"
     traffic = load_traffic(kname, workload)
     out = {
@@ -288,12 +288,10 @@ def main():
                    "global_batch": m, "seq_len": None, "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "bytes_per_launch": by, "avg_ms": ms},
-        "aprod": {"aprod1_ms": a1, "aprod1_gbs": bytes1 / (a1 * 1e-3) / 1e9,
-                  "aprod2_ms": a2, "aprod2_gbs": bytes2 / (a2 * 1e-3) / 1e9,
-                  "tail_ms": tm["tail_ms"] / max(1, tm["tail_n"]),
-                  "update_ms": tm["update_ms"] / max(1, tm["update_n"]),
-                  "aprod_pair_frac": (bytes1 + bytes2) / ((a1 + a2) * 1e-3) / 1e9 / HBM_PEAK_GBS},
+                     "bytes_per_launch": by, "avg_ms": f_ms},
+        "iteration_ms": {"fused_row_pass": f_ms, "attitude_passes": att_ms,
+                         "tail": tm["tail_ms"] / max(1, tm["tail_n"]),
+                         "update": tm["update_ms"] / max(1, tm["update_n"])},
     }
     S.close()
     if not args.no_ttt:

@@ -214,6 +214,16 @@ int gsr_set_tuning(gsr_system *sys, int32_t waves_per_cu, int32_t att_atomics);
  * events. */
 int gsr_set_graphs(gsr_system *sys, int32_t on);
 
+/* One pass over the rows per LSQR iteration (on by default).  An iteration
+ * needs A v_i - alpha_i u_i and then A^T u_{i+1} (Sec. 2, Eq. 2 and Eq. 3);
+ * with u kept unnormalised, A^T u_{i+1} = A^T(beta_{i+1} u_{i+1}) / beta_{i+1},
+ * so both products read each row once and 1/beta_{i+1} is applied
+ * afterwards.  Used with FP64 products when the attitude columns are summed
+ * in LDS or by the bucketed pass; off, or otherwise, an iteration runs
+ * gsr_aprod1 and gsr_aprod2 as separate passes.  Results agree up to the
+ * rounding of the 1/beta scaling. */
+int gsr_set_fused(gsr_system *sys, int32_t on);
+
 /* Per-kernel timing with HIP events on the solve's stream (off by default).
  * gsr_timing_get synchronises, returns the totals since the last get and
  * resets them. */

@@ -82,6 +82,7 @@ _SIGS = {
     "gsr_set_tuning": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "gsr_timing_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "gsr_set_graphs": (C.c_int, [C.c_void_p, C.c_int32]),
+    "gsr_set_fused": (C.c_int, [C.c_void_p, C.c_int32]),
     "gsr_timing_get": (C.c_int, [C.c_void_p, C.c_void_p]),
     "gsr_features": (C.c_int, [C.c_void_p] * 5),
     "gsr_mean_rows": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p]),
@@ -367,6 +368,9 @@ class System:
 
     def set_graphs(self, on=True):
         _check(lib().gsr_set_graphs(self._h, int(bool(on))))
+
+    def set_fused(self, on=True):
+        _check(lib().gsr_set_fused(self._h, int(bool(on))))
 
     def timing_enable(self, on=True):
         _check(lib().gsr_timing_enable(self._h, int(bool(on))))

@@ -1,121 +1,48 @@
 // The two products of every LSQR iteration (Sec. 2, Eq. 2 and Eq. 3) over the
 // 24-coefficient row form of the observation matrix, for gfx950.
 //
-// Both kernels stream the coefficient rows once in star order.  Work is split
-// by whole stars: wave w of W owns the stars whose rows start in
-// [w*m/W, (w+1)*m/W), so every astrometric unknown is produced by exactly one
-// wave.  A wave walks its rows in tiles of 64 (one row per lane).  A tile's
-// coefficients (64 x 192 B for FP64) are fetched with contiguous 16-byte
-// nontemporal loads (1 KB per wave instruction), staged in LDS with one
-// 16-byte pad per row (conflict-free row reads) and read back row-per-lane.
-// The star of each row comes from the tile's 64 star boundaries, loaded in
-// one coalesced access and searched in LDS.
+// Both kernels stream the coefficient rows once in row (star) order; a wave
+// walks a contiguous range of rows in tiles of 64 (one row per lane).  A
+// tile's coefficients (64 x 192 B for FP64) are fetched with contiguous
+// 16-byte nontemporal loads (1 KB per wave instruction), staged in LDS with
+// one 16-byte pad per row (conflict-free row reads) and read back
+// row-per-lane; the next tile's loads are issued as soon as the current one
+// sits in LDS.  The star of each row comes from the tile's 64 star
+// boundaries, loaded in one coalesced access and searched in LDS.
 //
-// aprod1: y_r <- scale*y_r + ax * sum_k a_rk x[col(r,k)]; the x gathers hit
-//   L1/L2 (astrometric x is shared by the 20-90 rows of a star, the
-//   attitude block is a few MB at most).
+// aprod1: y_r <- scale*y_r + ax * sum_k a_rk x[col(r,k)].  Wave ranges are
+//   whole 64-row tiles, so each tile's 512-byte store of y covers whole
+//   64-byte sectors (a partly written sector costs the memory a
+//   read-modify-write; with unaligned tiles those stores took a quarter of
+//   the kernel's time).  x is gathered per tile: the astrometric x of the
+//   tile's stars in one contiguous load, spread to the rows by lane shuffles;
+//   the attitude windows with 16-byte loads; the instrumental x from LDS.
 // aprod2 (this file: astrometric, instrumental, global; and the attitude
-//   block when it fits in LDS): astrometric columns by a segmented scan over
-//   the star runs of a tile, carried across tiles and written once by the
-//   owning wave; instrumental and global columns LDS-private per workgroup,
-//   flushed with one atomic per column per workgroup.  Larger attitude
-//   blocks are summed by the bucketed pass in attitude.hip; this pass then
-//   skips the 64-byte sectors that hold only attitude coefficients.
+//   block when it fits in LDS): work is split by whole stars (wave w owns
+//   the stars whose rows start in [w*m/W, (w+1)*m/W)), so every astrometric
+//   unknown is produced by exactly one wave.  Astrometric columns by a
+//   segmented scan over the star runs of a tile, carried across tiles;
+//   instrumental and global columns LDS-private per workgroup, flushed with
+//   one atomic per column per workgroup.  Larger attitude blocks are summed
+//   by the bucketed pass in attitude.hip; this pass then reads the row-order
+//   copy that holds only the other twelve coefficients (half the bytes).
 #include <algorithm>
 
-#include "device_common.h"
+#include "row_tiles.h"
 
 namespace gsr {
 
-template <typename VT>
-struct Geo;
-template <>
-struct Geo<double> {
-  static constexpr int CPR = 12;                // 16-byte chunks per row
-  static constexpr unsigned ATT_ONLY = 0x0F8u;  // chunks 3..7: bytes 48..127, attitude only
-};
-template <>
-struct Geo<float> {
-  static constexpr int CPR = 6;
-  static constexpr unsigned ATT_ONLY = 0x00Cu;  // chunks 2..3: bytes 32..63, attitude only
-};
-
-// smallest s in [0, S] with row_ptr[s] >= target
-__device__ inline int64_t star_lower_bound(const int64_t* rp, int64_t S, int64_t target) {
-  int64_t lo = 0, hi = S;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (rp[mid] < target)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  return lo;
-}
-
-// Star range [s0, s1) of wave w out of W.
-__device__ inline void wave_stars(const SysView& s, int64_t w, int64_t W, int64_t* s0, int64_t* s1) {
-  const int64_t t0 = (s.m * w + W - 1) / W;
-  const int64_t t1 = (s.m * (w + 1) + W - 1) / W;
-  *s0 = (w == 0) ? 0 : star_lower_bound(s.row_ptr, s.n_stars, t0);
-  *s1 = (w == W - 1) ? s.n_stars : star_lower_bound(s.row_ptr, s.n_stars, t1);
-}
-
-template <int PM, typename VT>
-__device__ __forceinline__ double prod(VT a, double x) {
-  if (PM == 1) return (double)((float)a * (float)x);
-  return (double)a * x;
-}
-
-// Star boundaries for a tile whose first row is in star scur: lane i holds
-// row_ptr[scur + 1 + i] (the end row of star scur + i), clamped at n_stars.
-__device__ __forceinline__ int64_t bnd_load(const SysView& s, int64_t scur, int lane) {
-  return s.row_ptr[min(scur + 1 + lane, s.n_stars)];
-}
-
-// Stars of the tile's rows from the loaded boundaries b (searched in this
-// wave's LDS bnd[64]).  Returns the lane's star and advances scur to the star
-// of row t0 + 64.
-__device__ __forceinline__ int64_t tile_stars(const SysView& s, int64_t b, int64_t t0, int lane, int64_t* bnd,
-                                              int64_t& scur, int64_t* rbeg = nullptr, int64_t* rend = nullptr) {
-  bnd[lane] = b;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  const int64_t r = t0 + lane;
-  // lo = #{i : bnd[i] <= r}, bnd ascending
-  int lo = 0, hi = kWave;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (bnd[mid] <= r)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  int64_t st = scur + lo;
-  if (lo == kWave) {  // more than 64 stars end inside this tile (empty or one-row stars)
-    while (st < s.n_stars - 1 && s.row_ptr[st + 1] <= r) ++st;
-    if (rbeg) *rbeg = s.row_ptr[st];
-    if (rend) *rend = s.row_ptr[st + 1];
-  } else {
-    // star st = scur + lo spans rows [row_ptr[st], row_ptr[st+1]) = [bnd[lo-1], bnd[lo]);
-    // for lo = 0 it began at or before t0
-    if (rbeg) *rbeg = lo > 0 ? bnd[lo - 1] : t0;
-    if (rend) *rend = bnd[lo];
-  }
-  const uint64_t adv = __ballot(b <= t0 + kWave);
-  int64_t nxt = scur + __popcll(adv);
-  if (__popcll(adv) == kWave)
-    while (nxt < s.n_stars - 1 && s.row_ptr[nxt + 1] <= t0 + kWave) ++nxt;
-  nxt = min(nxt, max<int64_t>(s.n_stars - 1, 0));
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  scur = nxt;
-  return st;
-}
-
 // ---------------------------------------------------------------- aprod1
-template <typename VT, int PM>
+//
+// Gathers of x per tile: the astrometric x of the tile's stars with one
+// contiguous load and lane shuffles (when the tile spans at most 12 stars),
+// the three 4-column attitude windows with two 16-byte loads each, and the
+// instrumental x from an LDS copy (IL = 1, up to kLdsInstrMax entries).
+// Every global load and store of the steady-state loop is unconditional or
+// issued before the next tile's prefetch (y of a tile is stored at the start
+// of the next one), so the waits before the compute cover only this tile's
+// gathers.
+template <typename VT, int PM, int IL>
 __global__ void __launch_bounds__(kBlock) k_aprod1(SysView s, int waves, const double* __restrict__ x,
                                                    double* __restrict__ y, double scale, double ax, Scalars* sc,
                                                    Work wk, int lsqr_stage) {
@@ -124,21 +51,28 @@ __global__ void __launch_bounds__(kBlock) k_aprod1(SysView s, int waves, const d
   __shared__ int64_t bnds[kWavesPerBlock][kWave];
   __shared__ double red[kWavesPerBlock];
   __shared__ int flag;
+  extern __shared__ double xil[];  // instrumental x when IL
   if (sc) {
     if (sc->done) return;
     scale = sc->u_scale;
+  }
+  const int64_t NI = s.n_astro + 3 * s.n_att;
+  if (IL) {
+    for (int64_t j = threadIdx.x; j < s.n_instr; j += kBlock) xil[j] = x[NI + j];
+    __syncthreads();
   }
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   const int64_t w = (int64_t)blockIdx.x * kWavesPerBlock + wid;
   double sumsq = 0.0;
   if (w < waves) {
-    int64_t s0, s1;
-    wave_stars(s, w, waves, &s0, &s1);
-    const int64_t R0 = s.row_ptr[s0], R1 = s.row_ptr[s1];
-    const int64_t NI = s.n_astro + 3 * s.n_att;
+    // rows [R0, R1): a contiguous range of whole 64-row tiles, so that every
+    // tile (and its 512-byte store of y) is aligned
+    const int64_t T = (s.m + kWave - 1) / kWave;
+    const int64_t R0 = kWave * (T * w / waves), R1 = min(s.m, kWave * (T * (w + 1) / waves));
     const double xg = s.n_glob ? x[NI + s.n_instr] : 0.0;
-    int64_t scur = s0;
-    while (scur < s1 && s.row_ptr[scur + 1] <= R0) ++scur;  // leading empty stars
+    // star of row R0: the last star starting at or before it
+    int64_t scur = R0 < R1 ? star_lower_bound(s.row_ptr, s.n_stars, R0 + 1) - 1 : 0;
+    const int64_t xa_last = 5 * s.n_stars - 1;
     const u4* vbase = reinterpret_cast<const u4*>(s.vals);
     // registers of the prefetched tile
     u4 tmp[CPR];
@@ -147,66 +81,94 @@ __global__ void __launch_bounds__(kBlock) k_aprod1(SysView s, int waves, const d
     double yo;
     int64_t bv;
     auto fetch = [&](int64_t tt) {
-      const int nr = (int)max<int64_t>(0, min((int64_t)kWave, R1 - tt));
-      const int64_t rr = (lane < nr) ? tt + lane : R1 - 1;  // always a valid row
-      issue_chunks<CPR, 0u>(vbase + tt * CPR, nr, lane, tmp);
+      // past the end of the range: re-read its last row (the registers are not used)
+      const int64_t te = min(tt, R1 - 1);
+      const int nr = (int)min((int64_t)kWave, R1 - te);
+      const int64_t rr = (lane < nr) ? te + lane : R1 - 1;
+      issue_chunks<CPR>(vbase + te * CPR, nr, lane, tmp);
       at = __builtin_nontemporal_load(s.att_start + rr);
       const i2* icp = reinterpret_cast<const i2*>(s.instr_col + 6 * rr);
       i01 = __builtin_nontemporal_load(icp);
       i23 = __builtin_nontemporal_load(icp + 1);
       i45 = __builtin_nontemporal_load(icp + 2);
-      yo = (scale == 0.0) ? 0.0 : y[rr];
+      yo = y[rr];
       bv = bnd_load(s, scur, lane);
     };
+    // y of the previous tile, stored at the start of the next one
+    double y_out = 0.0;
+    int64_t r_out = -1;
     if (R0 < R1) fetch(R0);
 #pragma unroll 1
     for (int64_t t0 = R0; t0 < R1; t0 += kWave) {
       const int nrow = (int)min((int64_t)kWave, R1 - t0);
       const bool valid = lane < nrow;
-      const int64_t r = t0 + (valid ? lane : 0);
       const int32_t at_c = at;
       const int ic[6] = {i01.x, i01.y, i23.x, i23.y, i45.x, i45.y};
-      const double yo_c = yo;
-      u4 mine[CPR];
-      lds_rows<CPR, 0u>(tmp, nrow, slabs[wid], lane, mine);
-      const int64_t st = tile_stars(s, bv, t0, lane, bnds[wid], scur);
-      VT a[kSlots];
-      __builtin_memcpy(a, mine, sizeof(a));
-      // gathers of x for this tile, then the next tile's loads
+      const double yo_c = (scale == 0.0) ? 0.0 : scale * yo;
+      const int64_t bv_c = bv;
+      const int64_t sf = scur;  // star of row t0
+      // stars of the tile (valid when the last row's star is among the 64 boundaries)
+      const int64_t span = __popcll(__ballot(bv_c <= t0 + nrow - 1)) + 1;
+      scur = tile_next(s, bv_c, t0, sf);
+      if (r_out >= 0) y[r_out] = y_out;
+      // gathers of x for this tile, issued before the next tile's loads
+      const double xs = x[min(5 * sf + lane, xa_last)];
       double gx[kSlots];
-      const double* xa = x + 5 * st;
-#pragma unroll
-      for (int k = 0; k < 5; ++k) gx[k] = xa[k];
 #pragma unroll
       for (int axs = 0; axs < 3; ++axs) {
-        const double* xt = x + s.n_astro + axs * s.n_att + at_c;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) gx[5 + 4 * axs + j] = xt[j];
+        const dd2u* xt = reinterpret_cast<const dd2u*>(x + s.n_astro + axs * s.n_att + at_c);
+        const dd2u p0 = xt[0], p1 = xt[1];
+        gx[5 + 4 * axs] = p0.x;
+        gx[6 + 4 * axs] = p0.y;
+        gx[7 + 4 * axs] = p1.x;
+        gx[8 + 4 * axs] = p1.y;
       }
+      if (!IL) {
 #pragma unroll
-      for (int q = 0; q < 6; ++q) gx[17 + q] = x[NI + ic[q]];
+        for (int q = 0; q < 6; ++q) gx[17 + q] = x[NI + ic[q]];
+      }
+      bnds[wid][lane] = bv_c;
+      lds_put<CPR>(tmp, nrow, slabs[wid], lane);
       order_point();
-      fetch(t0 + kWave);  // past the end: chunk loads off, index loads from a valid row
+      fetch(t0 + kWave);
       order_point();
+      u4 mine[CPR];
+      lds_get<CPR>(nrow, slabs[wid], lane, mine);
+      const int64_t st = tile_star(s, t0, lane, bnds[wid], sf);
+      VT a[kSlots];
+      __builtin_memcpy(a, mine, sizeof(a));
+      if (IL) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) gx[17 + q] = xil[ic[q]];
+      }
+      {
+        const int base = valid ? 5 * (int)min<int64_t>(st - sf, 12) : 0;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) gx[k] = __shfl(xs, base + k, kWave);
+      }
+      if (span > 12) {  // many short stars in this tile: per-lane gathers
+#pragma unroll
+        for (int k = 0; k < 5; ++k) gx[k] = x[5 * st + k];
+      }
       double acc = 0.0;
 #pragma unroll
       for (int k = 0; k < 23; ++k) acc += prod<PM>(a[k], gx[k]);
       if (s.n_glob) acc += prod<PM>(a[23], xg);
-      if (valid) {
-        const double yn = scale * yo_c + ax * acc;
-        y[r] = yn;
-        sumsq += yn * yn;
-      }
+      const double yn = yo_c + ax * acc;
+      r_out = valid ? t0 + lane : -1;
+      y_out = yn;
+      if (valid) sumsq += yn * yn;
     }
+    if (r_out >= 0) y[r_out] = y_out;
   }
   if (!sc) return;
   const double bs = block_sum(sumsq, red);
-  if (threadIdx.x == 0) wk.part_a[blockIdx.x] = bs;
+  if (threadIdx.x == 0) publish(wk.part_a + blockIdx.x, bs);
   if (last_block(wk.tickets + T_APROD1, &flag)) {
     const double tot = sum_partials(wk.part_a, gridDim.x, red);
     if (threadIdx.x == 0) {
       epi_beta(sc, tot, lsqr_stage == 0);
-      wk.tickets[T_APROD1] = 0;
+      ticket_reset(wk.tickets + T_APROD1);
     }
   }
 }
@@ -215,13 +177,17 @@ __global__ void __launch_bounds__(kBlock) k_aprod1(SysView s, int waves, const d
 // ATT_MODE 0: the whole tail (attitude, instrumental, global) in LDS.
 // ATT_MODE 1: attitude by device-scope FP64 atomics (fallback), instr + global in LDS.
 // ATT_MODE 3: attitude summed by the bucketed pass; its sectors are not read here.
+// In mode 3 the rows are read from the star-pass copy sv (astrometric,
+// instrumental and global coefficients only, half the row).
 template <typename VT, int PM, int SQUARE, int ATT_MODE>
-__global__ void __launch_bounds__(kBlock) k_aprod2(SysView s, int waves, const double* __restrict__ y,
-                                                   double* __restrict__ x, double* __restrict__ acc,
-                                                   const double* __restrict__ S, double scale, double inv_beta,
-                                                   Scalars* sc, Work wk) {
-  constexpr int CPR = Geo<VT>::CPR;
-  constexpr unsigned SKIP = (ATT_MODE == 3) ? Geo<VT>::ATT_ONLY : 0u;
+__global__ void __launch_bounds__(kBlock) k_aprod2(SysView s, int waves, const void* __restrict__ sv,
+                                                   const double* __restrict__ y, double* __restrict__ x,
+                                                   double* __restrict__ acc, const double* __restrict__ S,
+                                                   double scale, double inv_beta, Scalars* sc, Work wk) {
+  constexpr int CPR = (ATT_MODE == 3) ? Geo<VT>::CPR / 2 : Geo<VT>::CPR;
+  constexpr int NS = (ATT_MODE == 3) ? 12 : kSlots;  // coefficients per row read here
+  constexpr int IN0 = (ATT_MODE == 3) ? 5 : 17;      // first instrumental coefficient
+  constexpr int GL = NS - 1;                         // global coefficient
   __shared__ u4 slabs[kWavesPerBlock][kWave * (CPR + 1)];
   __shared__ int64_t bnds[kWavesPerBlock][kWave];
   __shared__ double red[kWavesPerBlock];
@@ -248,16 +214,20 @@ __global__ void __launch_bounds__(kBlock) k_aprod2(SysView s, int waves, const d
     while (scur < s1 && s.row_ptr[scur + 1] <= R0) ++scur;
     double carry[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     int carry_valid = 0;
-    const u4* vbase = reinterpret_cast<const u4*>(s.vals);
+    const u4* vbase = reinterpret_cast<const u4*>(ATT_MODE == 3 ? sv : s.vals);
+    const int64_t xa_last = 5 * s.n_stars - 1;
+    const double* Sx = S ? S : x;  // read unconditionally, ignored when S is null
     u4 tmp[CPR];
     double tv;
     int32_t at;
     i2 i01, i23, i45;
     int64_t bv;
     auto fetch = [&](int64_t tt) {
-      const int nr = (int)max<int64_t>(0, min((int64_t)kWave, R1 - tt));
-      const int64_t rr = (lane < nr) ? tt + lane : R1 - 1;  // always a valid row
-      issue_chunks<CPR, SKIP>(vbase + tt * CPR, nr, lane, tmp);
+      // past the end of the range: re-read its last row (the registers are not used)
+      const int64_t te = min(tt, R1 - 1);
+      const int nr = (int)min((int64_t)kWave, R1 - te);
+      const int64_t rr = (lane < nr) ? te + lane : R1 - 1;
+      issue_chunks<CPR>(vbase + te * CPR, nr, lane, tmp);
       tv = SQUARE ? 0.0 : __builtin_nontemporal_load(y + rr);
       at = (ATT_MODE == 3) ? 0 : __builtin_nontemporal_load(s.att_start + rr);
       const i2* icp = reinterpret_cast<const i2*>(s.instr_col + 6 * rr);
@@ -266,6 +236,9 @@ __global__ void __launch_bounds__(kBlock) k_aprod2(SysView s, int waves, const d
       i45 = __builtin_nontemporal_load(icp + 2);
       bv = bnd_load(s, scur, lane);
     };
+    // stars finished in the previous tile, stored at the start of the next one
+    int64_t c_out = -1;
+    double x_out[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (R0 < R1) fetch(R0);
 #pragma unroll 1
     for (int64_t t0 = R0; t0 < R1; t0 += kWave) {
@@ -275,14 +248,29 @@ __global__ void __launch_bounds__(kBlock) k_aprod2(SysView s, int waves, const d
       const double t = tv * inv_beta;
       const int32_t at_c = at;
       const int ic[6] = {i01.x, i01.y, i23.x, i23.y, i45.x, i45.y};
+      const int64_t bv_c = bv;
+      const int64_t sf = scur;  // star of row t0
+      // stars of the tile (valid when the last row's star is among the 64 boundaries)
+      const int64_t span = __popcll(__ballot(bv_c <= t0 + nrow - 1)) + 1;
+      scur = tile_next(s, bv_c, t0, sf);
+      if (c_out >= 0) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) x[c_out + k] = x_out[k];
+      }
+      // old x and column scales of the tile's stars, one contiguous load each
+      const int64_t ia = min(5 * sf + lane, xa_last);
+      const double xo_l = x[ia];
+      const double so_l = Sx[ia];
+      bnds[wid][lane] = bv_c;
+      lds_put<CPR>(tmp, nrow, slabs[wid], lane);
+      order_point();
+      fetch(t0 + kWave);
+      order_point();
       u4 mine[CPR];
-      lds_rows<CPR, SKIP>(tmp, nrow, slabs[wid], lane, mine);
+      lds_get<CPR>(nrow, slabs[wid], lane, mine);
       int64_t rbeg, rend;
-      const int64_t st = tile_stars(s, bv, t0, lane, bnds[wid], scur, &rbeg, &rend);
-      order_point();
-      fetch(t0 + kWave);  // past the end: chunk loads off, index loads from a valid row
-      order_point();
-      VT a[kSlots];
+      const int64_t st = tile_star(s, t0, lane, bnds[wid], sf, &rbeg, &rend);
+      VT a[NS];
       __builtin_memcpy(a, mine, sizeof(a));
       const int seg0 = valid ? (int)(max(rbeg, t0) - t0) : lane;
       double p[5];
@@ -306,11 +294,11 @@ __global__ void __launch_bounds__(kBlock) k_aprod2(SysView s, int waves, const d
         }
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
-          const VT av = a[17 + q];
+          const VT av = a[IN0 + q];
           const double c = SQUARE ? (double)av * (double)av : prod<PM>(av, t);
           atomicAdd(hist + (3 * s.n_att - hoff) + ic[q], c);
         }
-        if (s.n_glob) gsum += SQUARE ? (double)a[23] * (double)a[23] : prod<PM>(a[23], t);
+        if (s.n_glob) gsum += SQUARE ? (double)a[GL] * (double)a[GL] : prod<PM>(a[GL], t);
       } else {
 #pragma unroll
         for (int k = 0; k < 5; ++k) p[k] = 0.0;
@@ -330,13 +318,29 @@ __global__ void __launch_bounds__(kBlock) k_aprod2(SysView s, int waves, const d
         }
       }
       const bool ends_here = valid && (r == rend - 1);
+      // old x and scale of the lane's star
+      double xo[5], so[5];
+      {
+        const int base = valid ? 5 * (int)min<int64_t>(st - sf, 12) : 0;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+          xo[k] = __shfl(xo_l, base + k, kWave);
+          so[k] = __shfl(so_l, base + k, kWave);
+        }
+      }
+      if (span > 12) {  // many short stars in this tile: per-lane loads
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+          xo[k] = x[5 * st + k];
+          so[k] = Sx[5 * st + k];
+        }
+      }
+      c_out = ends_here ? 5 * st : -1;
       if (ends_here) {
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
-          const int64_t c = 5 * st + k;
-          const double xo = (scale == 0.0) ? 0.0 : scale * x[c];
-          const double xn = xo + (S ? S[c] : 1.0) * p[k];
-          x[c] = xn;
+          const double xn = ((scale == 0.0) ? 0.0 : scale * xo[k]) + (S ? so[k] : 1.0) * p[k];
+          x_out[k] = xn;
           sumsq += xn * xn;
         }
       }
@@ -346,6 +350,10 @@ __global__ void __launch_bounds__(kBlock) k_aprod2(SysView s, int waves, const d
 #pragma unroll
       for (int k = 0; k < 5; ++k) carry[k] = __shfl(p[k], last, kWave);
       carry_valid = !lend;
+    }
+    if (c_out >= 0) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) x[c_out + k] = x_out[k];
     }
     // stars without rows: x <- scale*x
     if (s.has_empty_stars) {
@@ -374,7 +382,7 @@ __global__ void __launch_bounds__(kBlock) k_aprod2(SysView s, int waves, const d
   }
   if (sc) {
     const double bs = block_sum(sumsq, red);
-    if (threadIdx.x == 0) wk.part_b[blockIdx.x] = bs;
+    if (threadIdx.x == 0) publish(wk.part_b + blockIdx.x, bs);
   }
 }
 
@@ -401,9 +409,15 @@ __global__ void __launch_bounds__(kBlock) k_tail(SysView s, AttView av, int att_
   if (work) {
     const int64_t natt = 3 * s.n_att;
     const int64_t win = av.Wb + 3;
-    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < s.tail_len; j += (int64_t)gridDim.x * kBlock) {
+    // fused iteration: the astrometric columns too, and every raw sum times 1/beta
+    const int64_t j0 = L.gA ? -s.n_astro : 0;
+    const double f = L.gA ? sc->inv_beta : 1.0;
+    for (int64_t j = j0 + (int64_t)blockIdx.x * kBlock + threadIdx.x; j < s.tail_len;
+         j += (int64_t)gridDim.x * kBlock) {
       double a;
-      if (att_mode == 3 && j < natt) {
+      if (j < 0) {
+        a = L.gA[s.n_astro + j];
+      } else if (att_mode == 3 && j < natt) {
         const int64_t axs = j / s.n_att, c = j - axs * s.n_att;
         a = 0.0;
         const int64_t bhi = min(c / av.Wb, av.nb - 1);
@@ -418,14 +432,14 @@ __global__ void __launch_bounds__(kBlock) k_tail(SysView s, AttView av, int att_
       }
       const int64_t c = s.n_astro + j;
       const double xo = (scale == 0.0) ? 0.0 : scale * x[c];
-      const double xn = xo + (S ? S[c] : 1.0) * a;
+      const double xn = xo + (S ? S[c] : 1.0) * (f * a);
       x[c] = xn;
       sumsq += xn * xn;
     }
   }
   if (!sc) return;
   const double bs = block_sum(sumsq, red);
-  if (threadIdx.x == 0) wk.part_a[blockIdx.x] = bs;
+  if (threadIdx.x == 0) publish(wk.part_a + blockIdx.x, bs);
   if (last_block(wk.tickets + T_TAIL, &flag)) {
     double tot = sum_partials(wk.part_b, L.astro_parts, red);
     tot += sum_partials(wk.part_a, gridDim.x, red);
@@ -435,7 +449,7 @@ __global__ void __launch_bounds__(kBlock) k_tail(SysView s, AttView av, int att_
       epi_alpha(sc, tot, L.lsqr_stage == 0);
       t3s = sc->t3;
       cols = sc->dcount;
-      wk.tickets[T_TAIL] = 0;
+      ticket_reset(wk.tickets + T_TAIL);
     }
     __syncthreads();
     if (L.lsqr_stage != 0 && sc->nsel > 0) {
@@ -488,15 +502,26 @@ StreamShape stream_shape(const SysView& s, int cus, int waves_per_cu) {
   return sh;
 }
 
+template <typename VT, int PM>
+static void aprod1_il(int il, dim3 g, dim3 b, size_t lb, hipStream_t st, const SysView& s, int waves,
+                      const double* x, double* y, double scale, double ax, Scalars* sc, Work w, int lsqr_stage) {
+  if (il)
+    hipLaunchKernelGGL((k_aprod1<VT, PM, 1>), g, b, lb, st, s, waves, x, y, scale, ax, sc, w, lsqr_stage);
+  else
+    hipLaunchKernelGGL((k_aprod1<VT, PM, 0>), g, b, 0, st, s, waves, x, y, scale, ax, sc, w, lsqr_stage);
+}
+
 hipError_t launch_aprod1(const SysView& s, StreamShape sh, const double* x, double* y, double scale, double ax,
                          int pmode, Scalars* sc, Work w, int lsqr_stage, hipStream_t st) {
   const dim3 g(sh.blocks), b(kBlock);
+  const int il = s.n_instr <= kLdsInstrMax ? 1 : 0;
+  const size_t lb = sizeof(double) * (size_t)std::max<int64_t>(s.n_instr, 1);
   if (s.value_type == GSR_F32 && pmode == 1)
-    hipLaunchKernelGGL((k_aprod1<float, 1>), g, b, 0, st, s, sh.waves, x, y, scale, ax, sc, w, lsqr_stage);
+    aprod1_il<float, 1>(il, g, b, lb, st, s, sh.waves, x, y, scale, ax, sc, w, lsqr_stage);
   else if (s.value_type == GSR_F32)
-    hipLaunchKernelGGL((k_aprod1<float, 0>), g, b, 0, st, s, sh.waves, x, y, scale, ax, sc, w, lsqr_stage);
+    aprod1_il<float, 0>(il, g, b, lb, st, s, sh.waves, x, y, scale, ax, sc, w, lsqr_stage);
   else
-    hipLaunchKernelGGL((k_aprod1<double, 0>), g, b, 0, st, s, sh.waves, x, y, scale, ax, sc, w, lsqr_stage);
+    aprod1_il<double, 0>(il, g, b, lb, st, s, sh.waves, x, y, scale, ax, sc, w, lsqr_stage);
   return hipGetLastError();
 }
 
@@ -507,33 +532,35 @@ int att_mode_of(const SysView& s, const AttView& av, int force_atomics) {
 }
 
 template <typename VT, int PM, int SQ>
-static void aprod2_mode(int mode, const SysView& s, StreamShape sh, const double* y, double* x, double* acc,
+static void aprod2_mode(int mode, const SysView& s, StreamShape sh, const void* sv, const double* y, double* x,
+                        double* acc,
                         const double* S, double scale, double inv_beta, size_t hb, Scalars* sc, Work w,
                         hipStream_t st) {
   const dim3 g(sh.blocks), b(kBlock);
   if (mode == 0)
-    hipLaunchKernelGGL((k_aprod2<VT, PM, SQ, 0>), g, b, hb, st, s, sh.waves, y, x, acc, S, scale, inv_beta, sc, w);
+    hipLaunchKernelGGL((k_aprod2<VT, PM, SQ, 0>), g, b, hb, st, s, sh.waves, sv, y, x, acc, S, scale, inv_beta, sc, w);
   else if (mode == 1)
-    hipLaunchKernelGGL((k_aprod2<VT, PM, SQ, 1>), g, b, hb, st, s, sh.waves, y, x, acc, S, scale, inv_beta, sc, w);
+    hipLaunchKernelGGL((k_aprod2<VT, PM, SQ, 1>), g, b, hb, st, s, sh.waves, sv, y, x, acc, S, scale, inv_beta, sc, w);
   else
-    hipLaunchKernelGGL((k_aprod2<VT, PM, SQ, 3>), g, b, hb, st, s, sh.waves, y, x, acc, S, scale, inv_beta, sc, w);
+    hipLaunchKernelGGL((k_aprod2<VT, PM, SQ, 3>), g, b, hb, st, s, sh.waves, sv, y, x, acc, S, scale, inv_beta, sc, w);
 }
 
-hipError_t launch_aprod2(const SysView& s, StreamShape sh, int att_mode, const double* y, double* x, double* acc,
+hipError_t launch_aprod2(const SysView& s, StreamShape sh, int att_mode, const void* sv, const double* y, double* x,
+                         double* acc,
                          const double* S, double scale, double inv_beta, int pmode, int square, Scalars* sc, Work w,
                          hipStream_t st) {
   const size_t hb = sizeof(double) * (size_t)(att_mode == 0 ? s.tail_len : s.tail_len - 3 * s.n_att);
   if (square) {
     if (s.value_type == GSR_F32)
-      aprod2_mode<float, 0, 1>(att_mode, s, sh, y, x, acc, S, scale, inv_beta, hb, sc, w, st);
+      aprod2_mode<float, 0, 1>(att_mode, s, sh, sv, y, x, acc, S, scale, inv_beta, hb, sc, w, st);
     else
-      aprod2_mode<double, 0, 1>(att_mode, s, sh, y, x, acc, S, scale, inv_beta, hb, sc, w, st);
+      aprod2_mode<double, 0, 1>(att_mode, s, sh, sv, y, x, acc, S, scale, inv_beta, hb, sc, w, st);
   } else if (s.value_type == GSR_F32 && pmode == 1) {
-    aprod2_mode<float, 1, 0>(att_mode, s, sh, y, x, acc, S, scale, inv_beta, hb, sc, w, st);
+    aprod2_mode<float, 1, 0>(att_mode, s, sh, sv, y, x, acc, S, scale, inv_beta, hb, sc, w, st);
   } else if (s.value_type == GSR_F32) {
-    aprod2_mode<float, 0, 0>(att_mode, s, sh, y, x, acc, S, scale, inv_beta, hb, sc, w, st);
+    aprod2_mode<float, 0, 0>(att_mode, s, sh, sv, y, x, acc, S, scale, inv_beta, hb, sc, w, st);
   } else {
-    aprod2_mode<double, 0, 0>(att_mode, s, sh, y, x, acc, S, scale, inv_beta, hb, sc, w, st);
+    aprod2_mode<double, 0, 0>(att_mode, s, sh, sv, y, x, acc, S, scale, inv_beta, hb, sc, w, st);
   }
   return hipGetLastError();
 }
@@ -542,8 +569,18 @@ hipError_t launch_tail(const SysView& s, const AttView& av, int att_mode, double
                        double scale, Scalars* sc, Work w, int lsqr_stage, int astro_parts, const int64_t* sel,
                        const double* wv, double* D, hipStream_t st) {
   int blocks = (int)std::min<int64_t>(512, std::max<int64_t>(1, (s.tail_len + kBlock - 1) / kBlock));
-  TailLsqr L{lsqr_stage, astro_parts, sel, wv, D};
+  TailLsqr L{lsqr_stage, astro_parts, sel, wv, D, nullptr};
   hipLaunchKernelGGL(k_tail, dim3(blocks), dim3(kBlock), 0, st, s, av, att_mode, x, acc, S, scale, sc, w, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_tail_fused(const SysView& s, const AttView& av, int att_mode, double* x, double* acc,
+                             const double* S, const double* gA, Scalars* sc, Work w, const int64_t* sel,
+                             const double* wv, double* D, hipStream_t st) {
+  const int64_t cols = s.n_astro + s.tail_len;
+  int blocks = (int)std::min<int64_t>(kMaxPartials, std::max<int64_t>(1, (cols + kBlock - 1) / kBlock));
+  TailLsqr L{1, 0, sel, wv, D, gA};
+  hipLaunchKernelGGL(k_tail, dim3(blocks), dim3(kBlock), 0, st, s, av, att_mode, x, acc, S, 0.0, sc, w, L);
   return hipGetLastError();
 }
 

@@ -5,7 +5,9 @@
 // star-ordered pass would need 12 scattered FP64 atomics per row (measured on
 // MI355X at ~2e10 atomics/s, far below the HBM stream).  Instead the handle
 // keeps, once per system, a copy of the attitude coefficients grouped by
-// attitude bucket b = att_start / Wb.  Each product then
+// attitude bucket b = att_start / Wb, and a row-order copy of the other twelve
+// coefficients for the star pass of aprod 2 (which then streams half a row).
+// Each product then
 //   1. permutes u into the same order (partition pass: one workgroup per
 //      chunk of K rows stages the chunk's u in LDS by bucket and writes one
 //      contiguous run per bucket), and
@@ -106,22 +108,54 @@ __global__ void __launch_bounds__(kWave) k_bk_rank(SysView s, AttView av, int32_
   }
 }
 
+// One pass over the rows (64-row tiles per wave, staged through LDS): the
+// attitude coefficients go to their bucket-order slot dest[r] in batt, the
+// other twelve (astrometric, instrumental, global) to row r of sv.
 template <typename VT>
-__global__ void k_bk_scatter(SysView s, AttView av, const int32_t* dest) {
-  const VT* V = reinterpret_cast<const VT*>(s.vals);
-  VT* B = reinterpret_cast<VT*>(av.batt);
-  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < s.m; r += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t d = dest[r];
+__global__ void __launch_bounds__(kBlock) k_bk_split(SysView s, AttView av, const int32_t* __restrict__ dest) {
+  constexpr int HC = AttGeo<VT>::CPR;  // chunks per half row
+  constexpr int RC = 2 * HC;           // chunks per row
+  __shared__ u4 slabs[kWavesPerBlock][kWave * (RC + 1)];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int64_t W = (int64_t)gridDim.x * kWavesPerBlock;
+  const int64_t ntiles = (s.m + kWave - 1) / kWave;
+  const u4* vb = reinterpret_cast<const u4*>(s.vals);
+  u4* svp = reinterpret_cast<u4*>(av.sv);
+  u4* bap = reinterpret_cast<u4*>(av.batt);
+  for (int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + wid; t < ntiles; t += W) {
+    const int64_t t0 = t * kWave;
+    const int nrow = (int)min<int64_t>(kWave, s.m - t0);
+    u4 tmp[RC], mine[RC];
+    issue_chunks<RC>(vb + t0 * RC, nrow, lane, tmp);
+    lds_rows<RC>(tmp, nrow, slabs[wid], lane, mine);
+    if (lane < nrow) {
+      const int64_t r = t0 + lane;
+      VT a[kSlots], sp[12], ap[12];
+      __builtin_memcpy(a, mine, sizeof(a));
 #pragma unroll
-    for (int k = 0; k < 12; ++k) B[d * 12 + k] = V[r * kSlots + 5 + k];
-    const int32_t at = s.att_start[r];
-    av.bst[d] = (uint16_t)(at - (at / av.Wb) * av.Wb);
+      for (int k = 0; k < 5; ++k) sp[k] = a[k];
+#pragma unroll
+      for (int k = 0; k < 7; ++k) sp[5 + k] = a[17 + k];
+#pragma unroll
+      for (int k = 0; k < 12; ++k) ap[k] = a[5 + k];
+      u4 so[HC], ao[HC];
+      __builtin_memcpy(so, sp, sizeof(so));
+      __builtin_memcpy(ao, ap, sizeof(ao));
+      const int64_t d = dest[r];
+#pragma unroll
+      for (int j = 0; j < HC; ++j) {
+        svp[r * HC + j] = so[j];
+        bap[d * HC + j] = ao[j];
+      }
+      const int32_t at = s.att_start[r];
+      av.bst[d] = (uint16_t)(at - (at / av.Wb) * av.Wb);
+    }
   }
 }
 
 void att_free(AttView* av) {
-  for (void* p : {(void*)av->count, (void*)av->cbase, (void*)av->lst, (void*)av->lpos, av->batt, (void*)av->bst, (void*)av->sub_lo,
-                  (void*)av->sub_b, (void*)av->bsub, (void*)av->Q, (void*)av->ub})
+  for (void* p : {(void*)av->count, (void*)av->cbase, (void*)av->lst, (void*)av->lpos, av->batt, (void*)av->bst,
+                  (void*)av->sub_lo, (void*)av->sub_b, (void*)av->bsub, (void*)av->Q, (void*)av->ub, av->sv})
     if (p) (void)hipFree(p);
   *av = AttView{};
 }
@@ -161,6 +195,7 @@ int att_build(const SysView& s, AttView* av, int cus, char* err, size_t errlen, 
   ATT_CHK(hipMalloc((void**)&av->lst, sizeof(int32_t) * av->nchunks * (av->nb + 1)));
   ATT_CHK(hipMalloc((void**)&av->lpos, sizeof(uint16_t) * m));
   ATT_CHK(hipMalloc((void**)&av->batt, vsz * 12 * m));
+  ATT_CHK(hipMalloc((void**)&av->sv, vsz * 12 * m));
   ATT_CHK(hipMalloc((void**)&av->bst, sizeof(uint16_t) * m));
   ATT_CHK(hipMalloc((void**)&av->ub, sizeof(double) * m));
   ATT_CHK(hipMalloc((void**)&dest, sizeof(int32_t) * m));
@@ -205,10 +240,11 @@ int att_build(const SysView& s, AttView* av, int cus, char* err, size_t errlen, 
   ATT_CHK(hipGetLastError());
   hipLaunchKernelGGL(k_bk_rank, dim3((unsigned)av->nchunks), dim3(kWave), 2 * sizeof(int) * av->nb, st, s, *av, dest);
   ATT_CHK(hipGetLastError());
+  const int gs = (int)std::min<int64_t>(8 * (int64_t)cus, (s.m + 4 * kWave - 1) / (4 * kWave));
   if (s.value_type == GSR_F32)
-    hipLaunchKernelGGL(k_bk_scatter<float>, dim3(g), dim3(256), 0, st, s, *av, dest);
+    hipLaunchKernelGGL(k_bk_split<float>, dim3(std::max(gs, 1)), dim3(kBlock), 0, st, s, *av, dest);
   else
-    hipLaunchKernelGGL(k_bk_scatter<double>, dim3(g), dim3(256), 0, st, s, *av, dest);
+    hipLaunchKernelGGL(k_bk_split<double>, dim3(std::max(gs, 1)), dim3(kBlock), 0, st, s, *av, dest);
   ATT_CHK(hipGetLastError());
   ATT_CHK(hipStreamSynchronize(st));
   (void)hipFree(dest);
@@ -247,13 +283,13 @@ __global__ void __launch_bounds__(kBlock) k_partition(SysView s, AttView av, con
 
 // Attitude sums of one bucket range per workgroup into its LDS window, then Q.
 template <typename VT, int PM, int SQUARE>
-__global__ void __launch_bounds__(kBlock) k_att_pass(SysView s, AttView av, double inv_beta, Scalars* sc) {
+__global__ void __launch_bounds__(kBlock) k_att_pass(SysView s, AttView av, double inv_beta, Scalars* sc, int raw) {
   constexpr int CPR = AttGeo<VT>::CPR;
   __shared__ u4 slabs[kWavesPerBlock][kWave * (CPR + 1)];
   extern __shared__ double win[];
   if (sc) {
     if (sc->done || !sc->do_v) return;
-    inv_beta = sc->inv_beta;
+    if (!raw) inv_beta = sc->inv_beta;
   }
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   const int64_t W3 = av.Wb + 3;
@@ -266,9 +302,11 @@ __global__ void __launch_bounds__(kBlock) k_att_pass(SysView s, AttView av, doub
   double tv;
   int sov;
   auto fetch = [&](int64_t tt) {
-    const int nr = (int)max<int64_t>(0, min((int64_t)kWave, hi - tt));
-    const int64_t ii = (lane < nr) ? tt + lane : hi - 1;  // always a valid row of the range
-    issue_chunks<CPR, 0u>(base + tt * CPR, nr, lane, tmp);
+    // past the end of the range: re-read its last row (the registers are not used)
+    const int64_t te = min(tt, hi - 1);
+    const int nr = (int)min((int64_t)kWave, hi - te);
+    const int64_t ii = (lane < nr) ? te + lane : hi - 1;
+    issue_chunks<CPR>(base + te * CPR, nr, lane, tmp);
     tv = SQUARE ? 0.0 : __builtin_nontemporal_load(av.ub + ii);
     sov = av.bst[ii];
   };
@@ -281,11 +319,12 @@ __global__ void __launch_bounds__(kBlock) k_att_pass(SysView s, AttView av, doub
     const bool valid = lane < nrow;
     const double t = tv * inv_beta;
     const int so = sov;
-    u4 mine[CPR];
-    lds_rows<CPR, 0u>(tmp, nrow, slabs[wid], lane, mine);
+    lds_put<CPR>(tmp, nrow, slabs[wid], lane);
     order_point();
     fetch(t0 + step);
     order_point();
+    u4 mine[CPR];
+    lds_get<CPR>(nrow, slabs[wid], lane, mine);
     VT a[12];
     __builtin_memcpy(a, mine, sizeof(a));
     if (valid) {
@@ -313,22 +352,22 @@ hipError_t launch_partition(const SysView& s, const AttView& av, const double* u
 }
 
 hipError_t launch_att_pass(const SysView& s, const AttView& av, double inv_beta, int pmode, int square, Scalars* sc,
-                           hipStream_t st) {
+                           hipStream_t st, int raw) {
   if (av.nsub == 0) return hipSuccess;
   const size_t lds = sizeof(double) * 3 * (av.Wb + 3);
   const dim3 g((unsigned)av.nsub), b(kBlock);
   if (s.value_type == GSR_F32) {
     if (square)
-      hipLaunchKernelGGL((k_att_pass<float, 0, 1>), g, b, lds, st, s, av, inv_beta, sc);
+      hipLaunchKernelGGL((k_att_pass<float, 0, 1>), g, b, lds, st, s, av, inv_beta, sc, raw);
     else if (pmode == 1)
-      hipLaunchKernelGGL((k_att_pass<float, 1, 0>), g, b, lds, st, s, av, inv_beta, sc);
+      hipLaunchKernelGGL((k_att_pass<float, 1, 0>), g, b, lds, st, s, av, inv_beta, sc, raw);
     else
-      hipLaunchKernelGGL((k_att_pass<float, 0, 0>), g, b, lds, st, s, av, inv_beta, sc);
+      hipLaunchKernelGGL((k_att_pass<float, 0, 0>), g, b, lds, st, s, av, inv_beta, sc, raw);
   } else {
     if (square)
-      hipLaunchKernelGGL((k_att_pass<double, 0, 1>), g, b, lds, st, s, av, inv_beta, sc);
+      hipLaunchKernelGGL((k_att_pass<double, 0, 1>), g, b, lds, st, s, av, inv_beta, sc, raw);
     else
-      hipLaunchKernelGGL((k_att_pass<double, 0, 0>), g, b, lds, st, s, av, inv_beta, sc);
+      hipLaunchKernelGGL((k_att_pass<double, 0, 0>), g, b, lds, st, s, av, inv_beta, sc, raw);
   }
   return hipGetLastError();
 }

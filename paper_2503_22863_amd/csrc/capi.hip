@@ -65,6 +65,8 @@ struct gsr_system {
   int S_valid = 0;
   // LSQR vectors
   double *u = nullptr, *v = nullptr, *vg = nullptr, *w = nullptr, *y = nullptr, *var = nullptr;
+  double* gA = nullptr;  // raw astrometric sums of the fused iteration pass
+  int fused = 1;         // one pass over the rows per iteration (FP64 products, attitude mode 0 or 3)
   // refinement buffers
   double *r = nullptr, *xr = nullptr, *dx = nullptr, *nrm2 = nullptr;
   // covariances
@@ -174,6 +176,7 @@ static void release(gsr_system* s) {
   dfree(s->w);
   dfree(s->y);
   dfree(s->var);
+  dfree(s->gA);
   dfree(s->r);
   dfree(s->xr);
   dfree(s->dx);
@@ -318,6 +321,13 @@ extern "C" int gsr_set_graphs(gsr_system* s, int32_t on) {
   return GSR_OK;
 }
 
+extern "C" int gsr_set_fused(gsr_system* s, int32_t on) {
+  CHK(check_handle(s));
+  if (s->in_session) return fail(GSR_ESTATE, "gsr_set_fused: a solve is in progress");
+  s->fused = on != 0;
+  return GSR_OK;
+}
+
 // ------------------------------------------------------------------ timing
 static int ev_get(gsr_system* s, hipEvent_t* e) {
   if (!s->pool.empty()) {
@@ -407,7 +417,7 @@ static int aprod2_launches(gsr_system* s, const double* y, double* x, const doub
   {
     TimeScope ts(s, 1, st);
     if (mode == 3 && !square) HIPCHK(launch_partition(s->s, s->av, y, sc, st));
-    HIPCHK(launch_aprod2(s->s, s->sh, mode, y, x, s->acc, S, scale, 1.0, product, square, sc, s->wk, st));
+    HIPCHK(launch_aprod2(s->s, s->sh, mode, mode == 3 ? s->av.sv : nullptr, y, x, s->acc, S, scale, 1.0, product, square, sc, s->wk, st));
     if (mode == 3) HIPCHK(launch_att_pass(s->s, s->av, 1.0, product, square, sc, st));
   }
   TimeScope ts(s, 2, st);
@@ -472,6 +482,7 @@ static int ensure_vectors(gsr_system* s) {
   if (!s->w) CHK(dalloc(&s->w, n));
   if (!s->y) CHK(dalloc(&s->y, n));
   if (!s->var) CHK(dalloc(&s->var, n));
+  if (!s->gA) CHK(dalloc(&s->gA, (size_t)std::max<int64_t>(s->s.n_astro, 1)));
   return GSR_OK;
 }
 
@@ -526,14 +537,38 @@ extern "C" int gsr_lsqr_begin(gsr_system* s, const double* b, const double* x0, 
 
 // One LSQR iteration: aprod 1, aprod 2 (+ tail), update, and the covariance
 // SYRK when a block of `dblock` columns is complete.
+// Whether an iteration runs as one pass over the rows (plus the attitude and
+// tail passes) instead of separate aprod 1 and aprod 2 passes.
+static int iteration_fused(const gsr_system* s) {
+  const int mode = att_mode(s);
+  return s->fused && s->pmode == 0 && (mode == 0 || mode == 3);
+}
+
 static int enqueue_iteration(gsr_system* s, hipStream_t st) {
   const double* S = s->precond ? s->S : nullptr;
   double* vg = s->precond ? s->vg : s->v;
-  {
-    TimeScope ts(s, 0, st);
-    HIPCHK(launch_aprod1(s->s, s->sh, vg, s->u, 0.0, 1.0, s->pmode, s->sc, s->wk, 1, st));
+  if (iteration_fused(s)) {
+    const int mode = att_mode(s);
+    {
+      TimeScope ts(s, 0, st);
+      HIPCHK(launch_fused(s->s, s->sh, mode, vg, s->u, s->gA, s->acc, s->sc, s->wk, st));
+    }
+    if (mode == 3) {
+      TimeScope ts(s, 1, st);
+      HIPCHK(launch_partition(s->s, s->av, s->u, s->sc, st));
+      HIPCHK(launch_att_pass(s->s, s->av, 1.0, 0, 0, s->sc, st, 1));
+    }
+    {
+      TimeScope ts(s, 2, st);
+      HIPCHK(launch_tail_fused(s->s, s->av, mode, s->v, s->acc, S, s->gA, s->sc, s->wk, s->sel, s->w, s->D, st));
+    }
+  } else {
+    {
+      TimeScope ts(s, 0, st);
+      HIPCHK(launch_aprod1(s->s, s->sh, vg, s->u, 0.0, 1.0, s->pmode, s->sc, s->wk, 1, st));
+    }
+    CHK(aprod2_launches(s, s->u, s->v, S, 0.0, s->pmode, 0, s->sc, 1, st));
   }
-  CHK(aprod2_launches(s, s->u, s->v, S, 0.0, s->pmode, 0, s->sc, 1, st));
   {
     TimeScope ts(s, 3, st);
     HIPCHK(launch_update(s->s.n, s->v, vg, s->w, s->y, s->var, S, s->sc, s->wk, st));
@@ -560,7 +595,8 @@ static void drop_graph(gsr_system* s) {
 // caller's stream by events (the null stream cannot be captured).
 static int graph_block(gsr_system* s, int64_t G, hipStream_t st) {
   const uint64_t key = ((uint64_t)s->precond << 0) | ((uint64_t)s->pmode << 1) | ((uint64_t)(s->nsel > 0) << 2) |
-                       ((uint64_t)G << 3) | ((uint64_t)s->att_atomics << 40) | ((uint64_t)s->waves_per_cu << 41);
+                       ((uint64_t)G << 3) | ((uint64_t)s->att_atomics << 40) | ((uint64_t)s->waves_per_cu << 41) |
+                       ((uint64_t)s->fused << 56);
   if (!s->gstream) {
     HIPCHK(hipStreamCreateWithFlags(&s->gstream, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&s->gev[0], hipEventDisableTiming));

@@ -13,27 +13,27 @@ typedef int i2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ u4 ld_stream(const u4* p) { return __builtin_nontemporal_load(p); }
 
 
-// Row tiles are moved in two steps so that the next tile's loads can be in
+// Row tiles are moved in three steps so that the next tile's loads are in
 // flight while the current tile is processed:
-//   issue_chunks: the tile's nrow rows of CPR 16-byte chunks (starting at chunk
-//     pointer g) as contiguous 16-byte nontemporal loads, chunk j*64+lane in
-//     register j (chunks whose bit is set in SKIP are not loaded);
-//   lds_rows: writes those registers to this wave's LDS slab (row stride CPR+1
-//     chunks, so that row-per-lane reads are free of bank conflicts) and reads
-//     back the lane's own row (skipped chunks read as zero).
-template <int CPR, unsigned SKIP>
+//   issue_chunks: the tile's nrow (>= 1) rows of CPR 16-byte chunks (starting
+//     at chunk pointer g) as contiguous 16-byte nontemporal loads, chunk
+//     j*64+lane in register j.  Lanes past the tile's last chunk re-read that
+//     chunk, so every load is issued unconditionally: with no branches around
+//     them the compiler can count outstanding loads exactly and wait for just
+//     the ones it needs (a data-dependent branch makes it wait for all);
+//   lds_put: writes those registers to this wave's LDS slab (row stride CPR+1
+//     chunks, so that row-per-lane reads are free of bank conflicts); the
+//     registers may then take the next tile's loads;
+//   lds_get: reads back the lane's own row (zeros past the tile's rows).
+template <int CPR>
 __device__ __forceinline__ void issue_chunks(const u4* __restrict__ g, int nrow, int lane, u4* tmp) {
-  const int nch = nrow * CPR;
+  const int last = nrow * CPR - 1;
 #pragma unroll
-  for (int j = 0; j < CPR; ++j) {
-    const int c = j * kWave + lane;
-    const int q = c % CPR;
-    if (c < nch && !((SKIP >> q) & 1u)) tmp[j] = ld_stream(g + c);
-  }
+  for (int j = 0; j < CPR; ++j) tmp[j] = ld_stream(g + min(j * kWave + lane, last));
 }
 
-template <int CPR, unsigned SKIP>
-__device__ __forceinline__ void lds_rows(const u4* tmp, int nrow, u4* slab, int lane, u4* mine) {
+template <int CPR>
+__device__ __forceinline__ void lds_put(const u4* tmp, int nrow, u4* slab, int lane) {
   const int nch = nrow * CPR;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -41,16 +41,25 @@ __device__ __forceinline__ void lds_rows(const u4* tmp, int nrow, u4* slab, int 
   for (int j = 0; j < CPR; ++j) {
     const int c = j * kWave + lane;
     const int r = c / CPR, q = c - r * CPR;
-    if (c < nch && !((SKIP >> q) & 1u)) slab[r * (CPR + 1) + q] = tmp[j];
+    if (c < nch) slab[r * (CPR + 1) + q] = tmp[j];
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
+}
+
+template <int CPR>
+__device__ __forceinline__ void lds_get(int nrow, const u4* slab, int lane, u4* mine) {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-  for (int j = 0; j < CPR; ++j)
-    mine[j] = (lane < nrow && !((SKIP >> j) & 1u)) ? slab[lane * (CPR + 1) + j] : u4{0u, 0u, 0u, 0u};
+  for (int j = 0; j < CPR; ++j) mine[j] = lane < nrow ? slab[lane * (CPR + 1) + j] : u4{0u, 0u, 0u, 0u};
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
+}
+
+template <int CPR>
+__device__ __forceinline__ void lds_rows(const u4* tmp, int nrow, u4* slab, int lane, u4* mine) {
+  lds_put<CPR>(tmp, nrow, slab, lane);
+  lds_get<CPR>(nrow, slab, lane, mine);
 }
 
 // Keeps the compiler from moving memory operations across this point (used to
@@ -79,25 +88,37 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return t;
 }
 
-// Publishes this workgroup's partial and returns true in the single workgroup
-// that finishes last; that workgroup then sees every other partial.
+// Cross-workgroup reductions without cache maintenance.  Thread 0 of each
+// workgroup publishes its partials with write-through stores (coherent at
+// device scope), waits until they are acknowledged, and then draws a ticket;
+// the workgroup drawing the last ticket reads all partials with device-coherent
+// loads.  Nothing else written in the launch is read by that workgroup, so no
+// device-scope fence is needed: on this chip such a fence writes back and
+// invalidates the XCD's whole L2, and one per workgroup stalls every wave on it.
+__device__ __forceinline__ void publish(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void ticket_reset(unsigned* ticket) {
+  __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Returns true in the single workgroup that finishes last.  Only thread 0 may
+// have published partials before the call.
 __device__ __forceinline__ bool last_block(unsigned* ticket, int* flag_lds) {
-  __threadfence();
-  __syncthreads();
   if (threadIdx.x == 0) {
-    unsigned t = atomicAdd(ticket, 1u);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's stores are acknowledged
+    const unsigned t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     *flag_lds = (t == gridDim.x - 1);
   }
   __syncthreads();
-  bool last = *flag_lds != 0;
-  if (last) __threadfence();
-  return last;
+  return *flag_lds != 0;
 }
 
 // Fixed-order sum of `n` partials by the whole workgroup.
 __device__ __forceinline__ double sum_partials(const double* p, int n, double* red) {
   double v = 0.0;
-  for (int i = threadIdx.x; i < n; i += kBlock) v += __builtin_nontemporal_load(p + i);
+  for (int i = threadIdx.x; i < n; i += kBlock) v += __hip_atomic_load(p + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return block_sum(v, red);
 }
 

@@ -1,0 +1,255 @@
+// One pass over the rows per LSQR iteration (Sec. 2, Eq. 2 and Eq. 3 on the
+// bidiagonalisation of Paige & Saunders).
+//
+// The iteration needs u_{i+1} = (A v_i - alpha_i u_i) / beta_{i+1} and then
+// A^T u_{i+1}.  Both are linear in the unnormalised u' = A v_i - alpha_i u_i,
+// so A^T u_{i+1} = (A^T u') / beta_{i+1}: one streaming pass forms u'_r for
+// each row and, from the same registers, adds a_r * u'_r to the
+// astrometric, instrumental and global columns; beta_{i+1} is known at the end
+// of the pass and the tail pass applies 1/beta_{i+1} when it forms v_{i+1}.
+// The coefficients are read once per iteration instead of twice.  (Mixing
+// even a few percent of stores into a read stream lowers the HBM rate
+// markedly on this chip, so a separate aprod 1 pass, which writes u, and
+// star pass, which reads the rows again, cost far more than their bytes.)
+// The attitude columns are summed afterwards by the bucketed pass on u'
+// (or, when the tail fits in LDS, in the same pass).
+//
+// Work split and tile mechanics as in aprod.hip: wave w owns whole stars,
+// 64-row tiles staged through LDS, the next tile's loads issued as soon as
+// the current one is in LDS, stores of a tile issued at the start of the next.
+#include <algorithm>
+
+#include "row_tiles.h"
+
+namespace gsr {
+
+template <typename VT, int IL, int ATT_MODE>
+__global__ void __launch_bounds__(kBlock) k_fused(SysView s, int waves, const double* __restrict__ x,
+                                                  double* __restrict__ u, double* __restrict__ gA,
+                                                  double* __restrict__ acc, Scalars* sc, Work wk) {
+  constexpr int CPR = Geo<VT>::CPR;
+  __shared__ u4 slabs[kWavesPerBlock][kWave * (CPR + 1)];
+  __shared__ int64_t bnds[kWavesPerBlock][kWave];
+  __shared__ double red[kWavesPerBlock];
+  __shared__ int flag;
+  extern __shared__ double dyn[];  // tail histogram, then the instrumental x when IL
+  if (sc->done) return;
+  const double scale = sc->u_scale;
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int64_t hoff = (ATT_MODE == 0) ? 0 : 3 * s.n_att;  // tail index of hist[0]
+  const int64_t hlen = s.tail_len - hoff;
+  double* hist = dyn;
+  double* xil = dyn + hlen;
+  const int64_t NI = s.n_astro + 3 * s.n_att;
+  for (int64_t j = threadIdx.x; j < hlen; j += kBlock) hist[j] = 0.0;
+  if (IL)
+    for (int64_t j = threadIdx.x; j < s.n_instr; j += kBlock) xil[j] = x[NI + j];
+  __syncthreads();
+
+  const int64_t w = (int64_t)blockIdx.x * kWavesPerBlock + wid;
+  double sumsq = 0.0, gsum = 0.0;
+  if (w < waves) {
+    int64_t s0, s1;
+    wave_stars(s, w, waves, &s0, &s1);
+    const int64_t R0 = s.row_ptr[s0], R1 = s.row_ptr[s1];
+    int64_t scur = s0;
+    while (scur < s1 && s.row_ptr[scur + 1] <= R0) ++scur;  // leading empty stars
+    const double xg = s.n_glob ? x[NI + s.n_instr] : 0.0;
+    const int64_t xa_last = 5 * s.n_stars - 1;
+    const u4* vbase = reinterpret_cast<const u4*>(s.vals);
+    u4 tmp[CPR];
+    int32_t at;
+    i2 i01, i23, i45;
+    double uo;
+    int64_t bv;
+    auto fetch = [&](int64_t tt) {
+      // past the end of the range: re-read its last row (the registers are not used)
+      const int64_t te = min(tt, R1 - 1);
+      const int nr = (int)min((int64_t)kWave, R1 - te);
+      const int64_t rr = (lane < nr) ? te + lane : R1 - 1;
+      issue_chunks<CPR>(vbase + te * CPR, nr, lane, tmp);
+      at = __builtin_nontemporal_load(s.att_start + rr);
+      const i2* icp = reinterpret_cast<const i2*>(s.instr_col + 6 * rr);
+      i01 = __builtin_nontemporal_load(icp);
+      i23 = __builtin_nontemporal_load(icp + 1);
+      i45 = __builtin_nontemporal_load(icp + 2);
+      uo = u[rr];
+      bv = bnd_load(s, scur, lane);
+    };
+    double carry[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    int carry_valid = 0;
+    // results of the previous tile, stored at the start of the next one
+    int64_t r_out = -1, c_out = -1;
+    double u_out = 0.0;
+    double g_out[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (R0 < R1) fetch(R0);
+#pragma unroll 1
+    for (int64_t t0 = R0; t0 < R1; t0 += kWave) {
+      const int nrow = (int)min((int64_t)kWave, R1 - t0);
+      const bool valid = lane < nrow;
+      const int64_t r = t0 + (valid ? lane : 0);
+      const int32_t at_c = at;
+      const int ic[6] = {i01.x, i01.y, i23.x, i23.y, i45.x, i45.y};
+      const double uo_c = (scale == 0.0) ? 0.0 : scale * uo;
+      const int64_t bv_c = bv;
+      const int64_t sf = scur;  // star of row t0
+      const int64_t span = __popcll(__ballot(bv_c <= t0 + nrow - 1)) + 1;
+      scur = tile_next(s, bv_c, t0, sf);
+      if (r_out >= 0) u[r_out] = u_out;
+      if (c_out >= 0) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) gA[c_out + k] = g_out[k];
+      }
+      // gathers of x for this tile, issued before the next tile's loads
+      const double xs = x[min(5 * sf + lane, xa_last)];
+      double gx[kSlots];
+#pragma unroll
+      for (int axs = 0; axs < 3; ++axs) {
+        const dd2u* xt = reinterpret_cast<const dd2u*>(x + s.n_astro + axs * s.n_att + at_c);
+        const dd2u p0 = xt[0], p1 = xt[1];
+        gx[5 + 4 * axs] = p0.x;
+        gx[6 + 4 * axs] = p0.y;
+        gx[7 + 4 * axs] = p1.x;
+        gx[8 + 4 * axs] = p1.y;
+      }
+      if (!IL) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) gx[17 + q] = x[NI + ic[q]];
+      }
+      bnds[wid][lane] = bv_c;
+      lds_put<CPR>(tmp, nrow, slabs[wid], lane);
+      order_point();
+      fetch(t0 + kWave);
+      order_point();
+      u4 mine[CPR];
+      lds_get<CPR>(nrow, slabs[wid], lane, mine);
+      int64_t rbeg, rend;
+      const int64_t st = tile_star(s, t0, lane, bnds[wid], sf, &rbeg, &rend);
+      VT a[kSlots];
+      __builtin_memcpy(a, mine, sizeof(a));
+      if (IL) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) gx[17 + q] = xil[ic[q]];
+      }
+      {
+        const int base = valid ? 5 * (int)min<int64_t>(st - sf, 12) : 0;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) gx[k] = __shfl(xs, base + k, kWave);
+      }
+      if (span > 12) {  // many short stars in this tile: per-lane gathers
+#pragma unroll
+        for (int k = 0; k < 5; ++k) gx[k] = x[5 * st + k];
+      }
+      // u'_r = u_scale * u_r + (A x)_r
+      double ax = 0.0;
+#pragma unroll
+      for (int k = 0; k < 23; ++k) ax += (double)a[k] * gx[k];
+      if (s.n_glob) ax += (double)a[23] * xg;
+      const double un = uo_c + ax;
+      r_out = valid ? r : -1;
+      u_out = un;
+      // a_r * u'_r into the star's, the instrumental and the global columns
+      const double t = valid ? un : 0.0;
+      sumsq += t * t;
+      double p[5];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) p[k] = (double)a[k] * t;
+      if (valid) {
+        if (ATT_MODE == 0) {
+#pragma unroll
+          for (int axs = 0; axs < 3; ++axs)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) atomicAdd(hist + axs * s.n_att + at_c + j, (double)a[5 + 4 * axs + j] * t);
+        }
+#pragma unroll
+        for (int q = 0; q < 6; ++q) atomicAdd(hist + (3 * s.n_att - hoff) + ic[q], (double)a[17 + q] * t);
+        if (s.n_glob) gsum += (double)a[23] * t;
+      }
+      if (carry_valid && lane == 0) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) p[k] += carry[k];
+      }
+      const int seg0 = valid ? (int)(max(rbeg, t0) - t0) : lane;
+#pragma unroll
+      for (int off = 1; off < kWave; off <<= 1) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+          const double o = __shfl_up(p[k], off, kWave);
+          if (lane - off >= seg0) p[k] += o;
+        }
+      }
+      const bool ends_here = valid && (r == rend - 1);
+      c_out = ends_here ? 5 * st : -1;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) g_out[k] = p[k];
+      const int last = nrow - 1;
+      const int lend = __shfl(ends_here ? 1 : 0, last, kWave);
+#pragma unroll
+      for (int k = 0; k < 5; ++k) carry[k] = __shfl(p[k], last, kWave);
+      carry_valid = !lend;
+    }
+    if (r_out >= 0) u[r_out] = u_out;
+    if (c_out >= 0) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) gA[c_out + k] = g_out[k];
+    }
+    // stars without rows contribute nothing to A^T u
+    if (s.has_empty_stars) {
+      for (int64_t e = s0 + lane; e < s1; e += kWave)
+        if (s.row_ptr[e] == s.row_ptr[e + 1]) {
+#pragma unroll
+          for (int k = 0; k < 5; ++k) gA[5 * e + k] = 0.0;
+        }
+    }
+  }
+  if (s.n_glob) {
+    const double g = wave_sum(gsum);
+    if (lane == 0) atomicAdd(hist + (hlen - 1), g);
+  }
+  __syncthreads();
+  for (int64_t j = threadIdx.x; j < hlen; j += kBlock) {
+    const double v = hist[j];
+    if (v != 0.0) atomicAdd(acc + hoff + j, v);
+  }
+  const double bs = block_sum(sumsq, red);
+  if (threadIdx.x == 0) publish(wk.part_a + blockIdx.x, bs);
+  if (last_block(wk.tickets + T_APROD1, &flag)) {
+    const double tot = sum_partials(wk.part_a, gridDim.x, red);
+    if (threadIdx.x == 0) {
+      epi_beta(sc, tot, 0);
+      ticket_reset(wk.tickets + T_APROD1);
+    }
+  }
+}
+
+template <typename VT>
+static void fused_launch(int il, int mode, dim3 g, dim3 b, size_t lds, hipStream_t st, const SysView& s, int waves,
+                         const double* vg, double* u, double* gA, double* acc, Scalars* sc, Work w) {
+  if (mode == 0) {
+    if (il)
+      hipLaunchKernelGGL((k_fused<VT, 1, 0>), g, b, lds, st, s, waves, vg, u, gA, acc, sc, w);
+    else
+      hipLaunchKernelGGL((k_fused<VT, 0, 0>), g, b, lds, st, s, waves, vg, u, gA, acc, sc, w);
+  } else {
+    if (il)
+      hipLaunchKernelGGL((k_fused<VT, 1, 3>), g, b, lds, st, s, waves, vg, u, gA, acc, sc, w);
+    else
+      hipLaunchKernelGGL((k_fused<VT, 0, 3>), g, b, lds, st, s, waves, vg, u, gA, acc, sc, w);
+  }
+}
+
+hipError_t launch_fused(const SysView& s, StreamShape sh, int att_mode, const double* vg, double* u, double* gA,
+                        double* acc, Scalars* sc, Work w, hipStream_t st) {
+  if (att_mode != 0 && att_mode != 3) return hipErrorInvalidValue;
+  const int il = s.n_instr <= kLdsInstrMax ? 1 : 0;
+  const int64_t hlen = att_mode == 0 ? s.tail_len : s.tail_len - 3 * s.n_att;
+  const size_t lds = sizeof(double) * (size_t)(hlen + (il ? s.n_instr : 0));
+  const dim3 g(sh.blocks), b(kBlock);
+  if (s.value_type == GSR_F32)
+    fused_launch<float>(il, att_mode, g, b, lds, st, s, sh.waves, vg, u, gA, acc, sc, w);
+  else
+    fused_launch<double>(il, att_mode, g, b, lds, st, s, sh.waves, vg, u, gA, acc, sc, w);
+  return hipGetLastError();
+}
+
+}  // namespace gsr

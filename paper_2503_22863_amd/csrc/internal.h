@@ -14,7 +14,8 @@ constexpr int kBlock = 256;        // threads per workgroup (4 waves)
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kSlots = 24;         // coefficients per row: 5 astro, 12 attitude, 6 instr, 1 global
 constexpr int kMaxPartials = 4096; // upper bound on workgroups of a reducing launch
-constexpr int kLdsTailMax = 2048;  // tail columns accumulated in LDS when they fit (16 KB)
+constexpr int kLdsTailMax = 2048;   // tail columns accumulated in LDS when they fit (16 KB)
+constexpr int kLdsInstrMax = 2048;  // instrumental x staged in LDS by aprod 1 up to this size
 
 // Device-resident LSQR state.  Written only by the single "last" workgroup of
 // a launch (ticket pattern) or by the host before a solve; every other
@@ -96,6 +97,7 @@ struct AttView {
   int32_t* bsub;        // [nb+1] first range of each bucket
   double* Q;            // [nsub][3][Wb+3] window partial sums
   double* ub;           // [m] u in bucket order
+  void* sv;             // [m][12] astrometric, instrumental, global coefficients in row order (value type)
 };
 
 // LSQR epilogue arguments of the tail pass.
@@ -105,6 +107,7 @@ struct TailLsqr {
   const int64_t* sel;   // selected unknowns (nsel = sc->nsel)
   const double* w;      // search direction w_i
   double* D;            // [nsel][dblock]
+  const double* gA;     // fused iteration: raw astrometric column sums (scaled here by 1/beta); else null
 };
 
 // ---- launchers (all asynchronous on `st`) ---------------------------------
@@ -114,8 +117,8 @@ hipError_t launch_aprod1(const SysView& s, StreamShape sh, const double* x, doub
                          double ax, int pmode, Scalars* sc, Work w, int lsqr_stage, hipStream_t st);
 // astro part of x <- scale*x + S*(A^T (inv_beta*y)); tail part accumulated in acc
 // (attitude part by the bucketed pass when att_mode == 3).
-hipError_t launch_aprod2(const SysView& s, StreamShape sh, int att_mode, const double* y, double* x,
-                         double* acc, const double* S, double scale, double inv_beta, int pmode, int square,
+hipError_t launch_aprod2(const SysView& s, StreamShape sh, int att_mode, const void* sv, const double* y,
+                         double* x, double* acc, const double* S, double scale, double inv_beta, int pmode, int square,
                          Scalars* sc, Work w, hipStream_t st);
 // tail part: x_t <- scale*x_t + S_t * (acc_t or window sums), acc cleared; LSQR epilogue when sc != nullptr.
 hipError_t launch_tail(const SysView& s, const AttView& av, int att_mode, double* x, double* acc, const double* S,
@@ -126,8 +129,21 @@ int att_mode_of(const SysView& s, const AttView& av, int force_atomics);
 int att_build(const SysView& s, AttView* av, int cus, char* err, size_t errlen, hipStream_t st);
 void att_free(AttView* av);
 hipError_t launch_partition(const SysView& s, const AttView& av, const double* u, Scalars* sc, hipStream_t st);
+// raw = 1: sums of the stored u as they are (the fused iteration's tail divides by beta)
 hipError_t launch_att_pass(const SysView& s, const AttView& av, double inv_beta, int pmode, int square,
-                           Scalars* sc, hipStream_t st);
+                           Scalars* sc, hipStream_t st, int raw = 0);
+// One LSQR iteration's pass over the rows (FP64 products, attitude mode 0 or 3):
+// u <- u_scale*u + A vg (beta_{i+1} by the last workgroup) and, from the same
+// rows, the astrometric, instrumental and global parts of A^T u on the
+// unnormalised u (astrometric sums to gA, the others into acc; mode 0 also
+// the attitude part).
+hipError_t launch_fused(const SysView& s, StreamShape sh, int att_mode, const double* vg, double* u, double* gA,
+                        double* acc, Scalars* sc, Work w, hipStream_t st);
+// Tail of the fused iteration: every column x_j <- v_scale*x_j + S_j * raw_j / beta (raw_j from gA, acc
+// or the attitude windows), then alpha_{i+1}, the rotations and the covariance column, as launch_tail.
+hipError_t launch_tail_fused(const SysView& s, const AttView& av, int att_mode, double* x, double* acc,
+                             const double* S, const double* gA, Scalars* sc, Work w, const int64_t* sel,
+                             const double* wv, double* D, hipStream_t st);
 // bad[0] <- first row with an out-of-range index, bad[1] <- first bad star, bad[2] <- 1 if a star is empty
 hipError_t launch_validate(const SysView& s, unsigned long long* bad, hipStream_t st);
 hipError_t launch_scale_from_sq(int64_t n, double* S, hipStream_t st);

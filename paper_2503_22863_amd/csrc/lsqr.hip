@@ -30,12 +30,12 @@ __global__ void __launch_bounds__(kBlock) k_norm_init(const double* __restrict__
     s += v * v;
   }
   const double bs = block_sum(s, red);
-  if (threadIdx.x == 0) wk.part_a[blockIdx.x] = bs;
+  if (threadIdx.x == 0) publish(wk.part_a + blockIdx.x, bs);
   if (last_block(wk.tickets + T_INIT, &flag)) {
     const double tot = sum_partials(wk.part_a, gridDim.x, red);
     if (threadIdx.x == 0) {
       epi_beta(sc, tot, 1);
-      wk.tickets[T_INIT] = 0;
+      ticket_reset(wk.tickets + T_INIT);
     }
   }
 }
@@ -85,15 +85,15 @@ __global__ void __launch_bounds__(kBlock) k_update(int64_t n, double* __restrict
   const double bx = block_sum(xs, red);
   const double bd = block_sum(ds, red);
   if (threadIdx.x == 0) {
-    wk.part_a[blockIdx.x] = bx;
-    wk.part_c[blockIdx.x] = bd;
+    publish(wk.part_a + blockIdx.x, bx);
+    publish(wk.part_c + blockIdx.x, bd);
   }
   if (last_block(wk.tickets + T_UPDATE, &flag)) {
     const double tx = sum_partials(wk.part_a, gridDim.x, red);
     const double td = sum_partials(wk.part_c, gridDim.x, red);
     if (threadIdx.x == 0) {
       epi_update(sc, tx, td);
-      wk.tickets[T_UPDATE] = 0;
+      ticket_reset(wk.tickets + T_UPDATE);
     }
   }
 }
@@ -173,7 +173,7 @@ __global__ void __launch_bounds__(kBlock) k_syrk(const double* __restrict__ D, i
   if (fixed_cols < 0) {
     if (last_block(wk.tickets + T_SYRK, &flag) && threadIdx.x == 0) {
       sc->dcount = 0;
-      wk.tickets[T_SYRK] = 0;
+      ticket_reset(wk.tickets + T_SYRK);
     }
   }
 }
@@ -206,8 +206,8 @@ __global__ void __launch_bounds__(kBlock) k_axpy_norms(int64_t n, const double* 
   const double ba = block_sum(a, red);
   const double bb = block_sum(b, red);
   if (threadIdx.x == 0) {
-    wk.part_a[blockIdx.x] = ba;
-    wk.part_c[blockIdx.x] = bb;
+    publish(wk.part_a + blockIdx.x, ba);
+    publish(wk.part_c + blockIdx.x, bb);
   }
   if (last_block(wk.tickets + T_VALID, &flag)) {
     const double ta = sum_partials(wk.part_a, gridDim.x, red);
@@ -215,7 +215,7 @@ __global__ void __launch_bounds__(kBlock) k_axpy_norms(int64_t n, const double* 
     if (threadIdx.x == 0) {
       out2[0] = ta;
       out2[1] = tb;
-      wk.tickets[T_VALID] = 0;
+      ticket_reset(wk.tickets + T_VALID);
     }
   }
 }
