@@ -255,13 +255,19 @@ int att_build(const SysView& s, AttView* av, int cus, char* err, size_t errlen, 
 }
 
 // ------------------------------------------------------------- per product
-// ub <- u in bucket order.  One workgroup per chunk of K rows.
+// ub <- u in bucket order.  One workgroup per chunk of K rows.  Consecutive
+// chunks run on the same XCD (workgroup b runs on XCD b mod 8): the run of a
+// bucket from chunk c ends where the run from chunk c+1 begins, so the 64-byte
+// sector they share is completed in one L2 instead of reaching memory as two
+// partial writes.
 __global__ void __launch_bounds__(kBlock) k_partition(SysView s, AttView av, const double* __restrict__ u,
                                                       Scalars* sc) {
   if (sc && (sc->done || !sc->do_v)) return;
   extern __shared__ double buf[];
   int* ls = reinterpret_cast<int*>(buf + av.K);  // [nb+1]
-  const int64_t c = blockIdx.x;
+  const int64_t per = (av.nchunks + kXcds - 1) / kXcds;
+  const int64_t c = (int64_t)(blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+  if (c >= av.nchunks) return;
   const int64_t r0 = c * av.K;
   const int n = (int)min(av.K, s.m - r0);
   for (int64_t b = threadIdx.x; b <= av.nb; b += kBlock) ls[b] = av.lst[c * (av.nb + 1) + b];
@@ -347,7 +353,8 @@ __global__ void __launch_bounds__(kBlock) k_att_pass(SysView s, AttView av, doub
 hipError_t launch_partition(const SysView& s, const AttView& av, const double* u, Scalars* sc, hipStream_t st) {
   if (s.m == 0) return hipSuccess;
   const size_t lds = sizeof(double) * av.K + sizeof(int) * (av.nb + 1);
-  hipLaunchKernelGGL(k_partition, dim3((unsigned)av.nchunks), dim3(kBlock), lds, st, s, av, u, sc);
+  const int64_t per = (av.nchunks + kXcds - 1) / kXcds;
+  hipLaunchKernelGGL(k_partition, dim3((unsigned)(per * kXcds)), dim3(kBlock), lds, st, s, av, u, sc);
   return hipGetLastError();
 }
 

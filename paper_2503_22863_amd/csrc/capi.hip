@@ -66,6 +66,7 @@ struct gsr_system {
   // LSQR vectors
   double *u = nullptr, *v = nullptr, *vg = nullptr, *w = nullptr, *y = nullptr, *var = nullptr;
   double* gA = nullptr;  // raw astrometric sums of the fused iteration pass
+  double* x3 = nullptr;  // attitude part of vg, axes interleaved, for the fused pass
   int fused = 1;         // one pass over the rows per iteration (FP64 products, attitude mode 0 or 3)
   // refinement buffers
   double *r = nullptr, *xr = nullptr, *dx = nullptr, *nrm2 = nullptr;
@@ -177,6 +178,7 @@ static void release(gsr_system* s) {
   dfree(s->y);
   dfree(s->var);
   dfree(s->gA);
+  dfree(s->x3);
   dfree(s->r);
   dfree(s->xr);
   dfree(s->dx);
@@ -483,7 +485,15 @@ static int ensure_vectors(gsr_system* s) {
   if (!s->y) CHK(dalloc(&s->y, n));
   if (!s->var) CHK(dalloc(&s->var, n));
   if (!s->gA) CHK(dalloc(&s->gA, (size_t)std::max<int64_t>(s->s.n_astro, 1)));
+  if (!s->x3) CHK(dalloc(&s->x3, (size_t)std::max<int64_t>(3 * s->s.n_att, 1)));
   return GSR_OK;
+}
+
+// Whether an iteration runs as one pass over the rows (plus the attitude and
+// tail passes) instead of separate aprod 1 and aprod 2 passes.
+static int iteration_fused(const gsr_system* s) {
+  const int mode = att_mode(s);
+  return s->fused && s->pmode == 0 && (mode == 0 || mode == 3);
 }
 
 static int lsqr_begin(gsr_system* s, const double* b, const double* x0, const gsr_lsqr_opts* o, int32_t product,
@@ -524,6 +534,7 @@ static int lsqr_begin(gsr_system* s, const double* b, const double* x0, const gs
   // alpha_1 v_1 = S A^T u_1
   CHK(aprod2_launches(s, s->u, s->v, S, 0.0, product, 0, s->sc, 0, st));
   HIPCHK(launch_init_vectors(s->s.n, s->v, s->vg, s->w, s->y, s->var, S, s->sc, st));
+  if (iteration_fused(s)) HIPCHK(launch_att_interleave(s->s, o->precond ? s->vg : s->v, s->x3, st));
   s->in_session = 1;
   return GSR_OK;
 }
@@ -537,13 +548,6 @@ extern "C" int gsr_lsqr_begin(gsr_system* s, const double* b, const double* x0, 
 
 // One LSQR iteration: aprod 1, aprod 2 (+ tail), update, and the covariance
 // SYRK when a block of `dblock` columns is complete.
-// Whether an iteration runs as one pass over the rows (plus the attitude and
-// tail passes) instead of separate aprod 1 and aprod 2 passes.
-static int iteration_fused(const gsr_system* s) {
-  const int mode = att_mode(s);
-  return s->fused && s->pmode == 0 && (mode == 0 || mode == 3);
-}
-
 static int enqueue_iteration(gsr_system* s, hipStream_t st) {
   const double* S = s->precond ? s->S : nullptr;
   double* vg = s->precond ? s->vg : s->v;
@@ -551,7 +555,7 @@ static int enqueue_iteration(gsr_system* s, hipStream_t st) {
     const int mode = att_mode(s);
     {
       TimeScope ts(s, 0, st);
-      HIPCHK(launch_fused(s->s, s->sh, mode, vg, s->u, s->gA, s->acc, s->sc, s->wk, st));
+      HIPCHK(launch_fused(s->s, s->sh, mode, vg, s->x3, s->u, s->gA, s->acc, s->sc, s->wk, st));
     }
     if (mode == 3) {
       TimeScope ts(s, 1, st);
@@ -572,6 +576,7 @@ static int enqueue_iteration(gsr_system* s, hipStream_t st) {
   {
     TimeScope ts(s, 3, st);
     HIPCHK(launch_update(s->s.n, s->v, vg, s->w, s->y, s->var, S, s->sc, s->wk, st));
+    if (iteration_fused(s)) HIPCHK(launch_att_interleave(s->s, vg, s->x3, st));
   }
   s->enq += 1;
   if (s->nsel > 0 && s->enq % s->dblock == 0) {

@@ -23,10 +23,27 @@
 
 namespace gsr {
 
+// x3[3c + a] = x[n_astro + a*n_att + c]: the attitude unknowns with the three
+// axes interleaved, so that the 12 attitude unknowns of a row (4 consecutive
+// columns on each axis) are 96 contiguous bytes.
+__global__ void k_att_interleave(SysView s, const double* __restrict__ x, double* __restrict__ x3) {
+  const int64_t n3 = 3 * s.n_att;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n3; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = e / 3, axs = e - 3 * c;
+    x3[e] = x[s.n_astro + axs * s.n_att + c];
+  }
+}
+
+// The attitude windows of a tile are loaded cooperatively: the tile's 64
+// windows of 96 bytes are 384 16-byte pieces, loaded as 6 wave instructions
+// in which consecutive lanes take consecutive pieces of the same window (a
+// row-per-lane load would touch a separate cache line in every lane), then
+// regrouped per row through LDS.
 template <typename VT, int IL, int ATT_MODE>
 __global__ void __launch_bounds__(kBlock) k_fused(SysView s, int waves, const double* __restrict__ x,
-                                                  double* __restrict__ u, double* __restrict__ gA,
-                                                  double* __restrict__ acc, Scalars* sc, Work wk) {
+                                                  const double* __restrict__ x3, double* __restrict__ u,
+                                                  double* __restrict__ gA, double* __restrict__ acc, Scalars* sc,
+                                                  Work wk) {
   constexpr int CPR = Geo<VT>::CPR;
   __shared__ u4 slabs[kWavesPerBlock][kWave * (CPR + 1)];
   __shared__ int64_t bnds[kWavesPerBlock][kWave];
@@ -102,19 +119,17 @@ __global__ void __launch_bounds__(kBlock) k_fused(SysView s, int waves, const do
       }
       // gathers of x for this tile, issued before the next tile's loads
       const double xs = x[min(5 * sf + lane, xa_last)];
-      double gx[kSlots];
+      dd2u cw[6];  // piece j*64 + lane of the tile's attitude windows
 #pragma unroll
-      for (int axs = 0; axs < 3; ++axs) {
-        const dd2u* xt = reinterpret_cast<const dd2u*>(x + s.n_astro + axs * s.n_att + at_c);
-        const dd2u p0 = xt[0], p1 = xt[1];
-        gx[5 + 4 * axs] = p0.x;
-        gx[6 + 4 * axs] = p0.y;
-        gx[7 + 4 * axs] = p1.x;
-        gx[8 + 4 * axs] = p1.y;
+      for (int j = 0; j < 6; ++j) {
+        const int c = j * kWave + lane, i = c / 6, q = c - 6 * i;
+        const int at_i = __shfl(at_c, i, kWave);
+        cw[j] = *reinterpret_cast<const dd2u*>(x3 + 3 * (int64_t)at_i + 2 * q);
       }
+      double gxi[6];  // instrumental x when it is not in LDS
       if (!IL) {
 #pragma unroll
-        for (int q = 0; q < 6; ++q) gx[17 + q] = x[NI + ic[q]];
+        for (int q = 0; q < 6; ++q) gxi[q] = x[NI + ic[q]];
       }
       bnds[wid][lane] = bv_c;
       lds_put<CPR>(tmp, nrow, slabs[wid], lane);
@@ -127,23 +142,44 @@ __global__ void __launch_bounds__(kBlock) k_fused(SysView s, int waves, const do
       const int64_t st = tile_star(s, t0, lane, bnds[wid], sf, &rbeg, &rend);
       VT a[kSlots];
       __builtin_memcpy(a, mine, sizeof(a));
-      if (IL) {
-#pragma unroll
-        for (int q = 0; q < 6; ++q) gx[17 + q] = xil[ic[q]];
-      }
+      // u'_r = u_scale * u_r + (A x)_r, each gathered x consumed as it is formed
+      double ax = 0.0;
       {
         const int base = valid ? 5 * (int)min<int64_t>(st - sf, 12) : 0;
+        double xa5[5];
 #pragma unroll
-        for (int k = 0; k < 5; ++k) gx[k] = __shfl(xs, base + k, kWave);
+        for (int k = 0; k < 5; ++k) xa5[k] = __shfl(xs, base + k, kWave);
+        if (span > 12) {  // many short stars in this tile: per-lane gathers
+#pragma unroll
+          for (int k = 0; k < 5; ++k) xa5[k] = x[5 * st + k];
+        }
+#pragma unroll
+        for (int k = 0; k < 5; ++k) ax += (double)a[k] * xa5[k];
       }
-      if (span > 12) {  // many short stars in this tile: per-lane gathers
+      {
+        // regroup the attitude windows per row through the (now free) slab;
+        // window element e = 3j + axis is column at+j of that axis
+        dd2u* wl = reinterpret_cast<dd2u*>(slabs[wid]);
 #pragma unroll
-        for (int k = 0; k < 5; ++k) gx[k] = x[5 * st + k];
+        for (int j = 0; j < 6; ++j) {
+          const int c = j * kWave + lane, i = c / 6, q = c - 6 * i;
+          wl[i * 7 + q] = cw[j];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+          const dd2u pq = wl[lane * 7 + q];
+          const int e0 = 2 * q, e1 = 2 * q + 1;
+          ax += (double)a[5 + 4 * (e0 % 3) + e0 / 3] * pq.x;
+          ax += (double)a[5 + 4 * (e1 % 3) + e1 / 3] * pq.y;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
       }
-      // u'_r = u_scale * u_r + (A x)_r
-      double ax = 0.0;
 #pragma unroll
-      for (int k = 0; k < 23; ++k) ax += (double)a[k] * gx[k];
+      for (int q = 0; q < 6; ++q) ax += (double)a[17 + q] * (IL ? xil[ic[q]] : gxi[q]);
       if (s.n_glob) ax += (double)a[23] * xg;
       const double un = uo_c + ax;
       r_out = valid ? r : -1;
@@ -224,31 +260,40 @@ __global__ void __launch_bounds__(kBlock) k_fused(SysView s, int waves, const do
 
 template <typename VT>
 static void fused_launch(int il, int mode, dim3 g, dim3 b, size_t lds, hipStream_t st, const SysView& s, int waves,
-                         const double* vg, double* u, double* gA, double* acc, Scalars* sc, Work w) {
+                         const double* vg, const double* x3, double* u, double* gA, double* acc, Scalars* sc,
+                         Work w) {
   if (mode == 0) {
     if (il)
-      hipLaunchKernelGGL((k_fused<VT, 1, 0>), g, b, lds, st, s, waves, vg, u, gA, acc, sc, w);
+      hipLaunchKernelGGL((k_fused<VT, 1, 0>), g, b, lds, st, s, waves, vg, x3, u, gA, acc, sc, w);
     else
-      hipLaunchKernelGGL((k_fused<VT, 0, 0>), g, b, lds, st, s, waves, vg, u, gA, acc, sc, w);
+      hipLaunchKernelGGL((k_fused<VT, 0, 0>), g, b, lds, st, s, waves, vg, x3, u, gA, acc, sc, w);
   } else {
     if (il)
-      hipLaunchKernelGGL((k_fused<VT, 1, 3>), g, b, lds, st, s, waves, vg, u, gA, acc, sc, w);
+      hipLaunchKernelGGL((k_fused<VT, 1, 3>), g, b, lds, st, s, waves, vg, x3, u, gA, acc, sc, w);
     else
-      hipLaunchKernelGGL((k_fused<VT, 0, 3>), g, b, lds, st, s, waves, vg, u, gA, acc, sc, w);
+      hipLaunchKernelGGL((k_fused<VT, 0, 3>), g, b, lds, st, s, waves, vg, x3, u, gA, acc, sc, w);
   }
 }
 
-hipError_t launch_fused(const SysView& s, StreamShape sh, int att_mode, const double* vg, double* u, double* gA,
-                        double* acc, Scalars* sc, Work w, hipStream_t st) {
+hipError_t launch_fused(const SysView& s, StreamShape sh, int att_mode, const double* vg, const double* x3, double* u,
+                        double* gA, double* acc, Scalars* sc, Work w, hipStream_t st) {
   if (att_mode != 0 && att_mode != 3) return hipErrorInvalidValue;
   const int il = s.n_instr <= kLdsInstrMax ? 1 : 0;
   const int64_t hlen = att_mode == 0 ? s.tail_len : s.tail_len - 3 * s.n_att;
   const size_t lds = sizeof(double) * (size_t)(hlen + (il ? s.n_instr : 0));
   const dim3 g(sh.blocks), b(kBlock);
   if (s.value_type == GSR_F32)
-    fused_launch<float>(il, att_mode, g, b, lds, st, s, sh.waves, vg, u, gA, acc, sc, w);
+    fused_launch<float>(il, att_mode, g, b, lds, st, s, sh.waves, vg, x3, u, gA, acc, sc, w);
   else
-    fused_launch<double>(il, att_mode, g, b, lds, st, s, sh.waves, vg, u, gA, acc, sc, w);
+    fused_launch<double>(il, att_mode, g, b, lds, st, s, sh.waves, vg, x3, u, gA, acc, sc, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_att_interleave(const SysView& s, const double* x, double* x3, hipStream_t st) {
+  const int64_t n3 = 3 * s.n_att;
+  if (n3 == 0) return hipSuccess;
+  const int blocks = (int)std::min<int64_t>(1024, (n3 + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_att_interleave, dim3(blocks), dim3(kBlock), 0, st, s, x, x3);
   return hipGetLastError();
 }
 
