@@ -37,12 +37,13 @@ namespace gsr {
 // Gathers of x per tile: the astrometric x of the tile's stars with one
 // contiguous load and lane shuffles (when the tile spans at most 12 stars),
 // the three 4-column attitude windows with two 16-byte loads each, and the
-// instrumental x from an LDS copy (IL = 1, up to kLdsInstrMax entries).
+// instrumental x from an LDS copy (a system has at most kLdsTailMax - 1
+// instrumental columns).
 // Every global load and store of the steady-state loop is unconditional or
 // issued before the next tile's prefetch (y of a tile is stored at the start
 // of the next one), so the waits before the compute cover only this tile's
 // gathers.
-template <typename VT, int PM, int IL>
+template <typename VT, int PM>
 __global__ void __launch_bounds__(kBlock) k_aprod1(SysView s, int waves, const double* __restrict__ x,
                                                    double* __restrict__ y, double scale, double ax, Scalars* sc,
                                                    Work wk, int lsqr_stage) {
@@ -51,16 +52,14 @@ __global__ void __launch_bounds__(kBlock) k_aprod1(SysView s, int waves, const d
   __shared__ int64_t bnds[kWavesPerBlock][kWave];
   __shared__ double red[kWavesPerBlock];
   __shared__ int flag;
-  extern __shared__ double xil[];  // instrumental x when IL
+  extern __shared__ double xil[];  // instrumental x
   if (sc) {
     if (sc->done) return;
     scale = sc->u_scale;
   }
   const int64_t NI = s.n_astro + 3 * s.n_att;
-  if (IL) {
-    for (int64_t j = threadIdx.x; j < s.n_instr; j += kBlock) xil[j] = x[NI + j];
-    __syncthreads();
-  }
+  for (int64_t j = threadIdx.x; j < s.n_instr; j += kBlock) xil[j] = x[NI + j];
+  __syncthreads();
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   const int64_t w = (int64_t)blockIdx.x * kWavesPerBlock + wid;
   double sumsq = 0.0;
@@ -123,10 +122,6 @@ __global__ void __launch_bounds__(kBlock) k_aprod1(SysView s, int waves, const d
         gx[7 + 4 * axs] = p1.x;
         gx[8 + 4 * axs] = p1.y;
       }
-      if (!IL) {
-#pragma unroll
-        for (int q = 0; q < 6; ++q) gx[17 + q] = x[NI + ic[q]];
-      }
       bnds[wid][lane] = bv_c;
       lds_put<CPR>(tmp, nrow, slabs[wid], lane);
       order_point();
@@ -137,10 +132,8 @@ __global__ void __launch_bounds__(kBlock) k_aprod1(SysView s, int waves, const d
       const int64_t st = tile_star(s, t0, lane, bnds[wid], sf);
       VT a[kSlots];
       __builtin_memcpy(a, mine, sizeof(a));
-      if (IL) {
 #pragma unroll
-        for (int q = 0; q < 6; ++q) gx[17 + q] = xil[ic[q]];
-      }
+      for (int q = 0; q < 6; ++q) gx[17 + q] = xil[ic[q]];
       {
         const int base = valid ? 5 * (int)min<int64_t>(st - sf, 12) : 0;
 #pragma unroll
@@ -502,26 +495,16 @@ StreamShape stream_shape(const SysView& s, int cus, int waves_per_cu) {
   return sh;
 }
 
-template <typename VT, int PM>
-static void aprod1_il(int il, dim3 g, dim3 b, size_t lb, hipStream_t st, const SysView& s, int waves,
-                      const double* x, double* y, double scale, double ax, Scalars* sc, Work w, int lsqr_stage) {
-  if (il)
-    hipLaunchKernelGGL((k_aprod1<VT, PM, 1>), g, b, lb, st, s, waves, x, y, scale, ax, sc, w, lsqr_stage);
-  else
-    hipLaunchKernelGGL((k_aprod1<VT, PM, 0>), g, b, 0, st, s, waves, x, y, scale, ax, sc, w, lsqr_stage);
-}
-
 hipError_t launch_aprod1(const SysView& s, StreamShape sh, const double* x, double* y, double scale, double ax,
                          int pmode, Scalars* sc, Work w, int lsqr_stage, hipStream_t st) {
   const dim3 g(sh.blocks), b(kBlock);
-  const int il = s.n_instr <= kLdsInstrMax ? 1 : 0;
   const size_t lb = sizeof(double) * (size_t)std::max<int64_t>(s.n_instr, 1);
   if (s.value_type == GSR_F32 && pmode == 1)
-    aprod1_il<float, 1>(il, g, b, lb, st, s, sh.waves, x, y, scale, ax, sc, w, lsqr_stage);
+    hipLaunchKernelGGL((k_aprod1<float, 1>), g, b, lb, st, s, sh.waves, x, y, scale, ax, sc, w, lsqr_stage);
   else if (s.value_type == GSR_F32)
-    aprod1_il<float, 0>(il, g, b, lb, st, s, sh.waves, x, y, scale, ax, sc, w, lsqr_stage);
+    hipLaunchKernelGGL((k_aprod1<float, 0>), g, b, lb, st, s, sh.waves, x, y, scale, ax, sc, w, lsqr_stage);
   else
-    aprod1_il<double, 0>(il, g, b, lb, st, s, sh.waves, x, y, scale, ax, sc, w, lsqr_stage);
+    hipLaunchKernelGGL((k_aprod1<double, 0>), g, b, lb, st, s, sh.waves, x, y, scale, ax, sc, w, lsqr_stage);
   return hipGetLastError();
 }
 

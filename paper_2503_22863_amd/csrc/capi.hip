@@ -67,6 +67,7 @@ struct gsr_system {
   double *u = nullptr, *v = nullptr, *vg = nullptr, *w = nullptr, *y = nullptr, *var = nullptr;
   double* gA = nullptr;  // raw astrometric sums of the fused iteration pass
   double* x3 = nullptr;  // attitude part of vg, axes interleaved, for the fused pass
+  void* rix = nullptr;   // packed row indices for the fused pass (16 B per row); null: no fused pass
   int fused = 1;         // one pass over the rows per iteration (FP64 products, attitude mode 0 or 3)
   // refinement buffers
   double *r = nullptr, *xr = nullptr, *dx = nullptr, *nrm2 = nullptr;
@@ -179,6 +180,7 @@ static void release(gsr_system* s) {
   dfree(s->var);
   dfree(s->gA);
   dfree(s->x3);
+  dfree(s->rix);
   dfree(s->r);
   dfree(s->xr);
   dfree(s->dx);
@@ -286,6 +288,17 @@ extern "C" int gsr_create(gsr_system** out, const gsr_dims* d, const void* vals,
       s->att_atomics = 1;  // not enough memory for the copy: device atomics
     } else if (rc != GSR_OK) {
       return bail(fail(rc, "attitude view: %s", msg));
+    }
+  }
+  if (v.m > 0 && v.n_instr <= 65536) {
+    // packed row indices for the fused iteration pass; without memory for them
+    // iterations run as separate aprod 1 / aprod 2 passes
+    if (hipMalloc(&s->rix, 16 * (size_t)v.m) == hipSuccess) {
+      if (launch_pack_rows(v, s->rix, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
+        return bail(fail(GSR_EHIP, "packing row indices failed"));
+    } else {
+      (void)hipGetLastError();
+      s->rix = nullptr;
     }
   }
   {
@@ -493,7 +506,7 @@ static int ensure_vectors(gsr_system* s) {
 // tail passes) instead of separate aprod 1 and aprod 2 passes.
 static int iteration_fused(const gsr_system* s) {
   const int mode = att_mode(s);
-  return s->fused && s->pmode == 0 && (mode == 0 || mode == 3);
+  return s->fused && s->pmode == 0 && (mode == 0 || mode == 3) && s->rix != nullptr;
 }
 
 static int lsqr_begin(gsr_system* s, const double* b, const double* x0, const gsr_lsqr_opts* o, int32_t product,
@@ -555,7 +568,7 @@ static int enqueue_iteration(gsr_system* s, hipStream_t st) {
     const int mode = att_mode(s);
     {
       TimeScope ts(s, 0, st);
-      HIPCHK(launch_fused(s->s, s->sh, mode, vg, s->x3, s->u, s->gA, s->acc, s->sc, s->wk, st));
+      HIPCHK(launch_fused(s->s, s->sh, mode, vg, s->x3, s->rix, s->u, s->gA, s->acc, s->sc, s->wk, st));
     }
     if (mode == 3) {
       TimeScope ts(s, 1, st);

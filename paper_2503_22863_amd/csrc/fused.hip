@@ -23,6 +23,17 @@
 
 namespace gsr {
 
+// Row index record of the fused pass (when every instrumental column fits in
+// 16 bits): the attitude start and the six instrumental columns in 16 bytes,
+// fetched with one load instead of four (28 bytes).
+__global__ void k_pack_rows(SysView s, u4* __restrict__ rix) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < s.m; r += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t* ic = s.instr_col + 6 * r;
+    rix[r] = u4{(unsigned)s.att_start[r], (unsigned)ic[0] | ((unsigned)ic[1] << 16),
+                (unsigned)ic[2] | ((unsigned)ic[3] << 16), (unsigned)ic[4] | ((unsigned)ic[5] << 16)};
+  }
+}
+
 // x3[3c + a] = x[n_astro + a*n_att + c]: the attitude unknowns with the three
 // axes interleaved, so that the 12 attitude unknowns of a row (4 consecutive
 // columns on each axis) are 96 contiguous bytes.
@@ -39,17 +50,20 @@ __global__ void k_att_interleave(SysView s, const double* __restrict__ x, double
 // in which consecutive lanes take consecutive pieces of the same window (a
 // row-per-lane load would touch a separate cache line in every lane), then
 // regrouped per row through LDS.
-template <typename VT, int IL, int ATT_MODE>
-__global__ void __launch_bounds__(kBlock) k_fused(SysView s, int waves, const double* __restrict__ x,
-                                                  const double* __restrict__ x3, double* __restrict__ u,
-                                                  double* __restrict__ gA, double* __restrict__ acc, Scalars* sc,
-                                                  Work wk) {
+// Row indices come from the packed records; the instrumental x (at most
+// kLdsTailMax - 1 columns) from an LDS copy.
+// Two waves per SIMD: the register budget is held to 256 (it fits without spills).
+template <typename VT, int ATT_MODE>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) k_fused(SysView s, int waves, const double* __restrict__ x,
+                                                  const double* __restrict__ x3, const u4* __restrict__ rix,
+                                                  double* __restrict__ u, double* __restrict__ gA,
+                                                  double* __restrict__ acc, Scalars* sc, Work wk) {
   constexpr int CPR = Geo<VT>::CPR;
   __shared__ u4 slabs[kWavesPerBlock][kWave * (CPR + 1)];
   __shared__ int64_t bnds[kWavesPerBlock][kWave];
   __shared__ double red[kWavesPerBlock];
   __shared__ int flag;
-  extern __shared__ double dyn[];  // tail histogram, then the instrumental x when IL
+  extern __shared__ double dyn[];  // tail histogram, then the instrumental x
   if (sc->done) return;
   const double scale = sc->u_scale;
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
@@ -59,8 +73,7 @@ __global__ void __launch_bounds__(kBlock) k_fused(SysView s, int waves, const do
   double* xil = dyn + hlen;
   const int64_t NI = s.n_astro + 3 * s.n_att;
   for (int64_t j = threadIdx.x; j < hlen; j += kBlock) hist[j] = 0.0;
-  if (IL)
-    for (int64_t j = threadIdx.x; j < s.n_instr; j += kBlock) xil[j] = x[NI + j];
+  for (int64_t j = threadIdx.x; j < s.n_instr; j += kBlock) xil[j] = x[NI + j];
   __syncthreads();
 
   const int64_t w = (int64_t)blockIdx.x * kWavesPerBlock + wid;
@@ -75,8 +88,7 @@ __global__ void __launch_bounds__(kBlock) k_fused(SysView s, int waves, const do
     const int64_t xa_last = 5 * s.n_stars - 1;
     const u4* vbase = reinterpret_cast<const u4*>(s.vals);
     u4 tmp[CPR];
-    int32_t at;
-    i2 i01, i23, i45;
+    u4 ri;
     double uo;
     int64_t bv;
     auto fetch = [&](int64_t tt) {
@@ -85,11 +97,7 @@ __global__ void __launch_bounds__(kBlock) k_fused(SysView s, int waves, const do
       const int nr = (int)min((int64_t)kWave, R1 - te);
       const int64_t rr = (lane < nr) ? te + lane : R1 - 1;
       issue_chunks<CPR>(vbase + te * CPR, nr, lane, tmp);
-      at = __builtin_nontemporal_load(s.att_start + rr);
-      const i2* icp = reinterpret_cast<const i2*>(s.instr_col + 6 * rr);
-      i01 = __builtin_nontemporal_load(icp);
-      i23 = __builtin_nontemporal_load(icp + 1);
-      i45 = __builtin_nontemporal_load(icp + 2);
+      ri = __builtin_nontemporal_load(rix + rr);
       uo = u[rr];
       bv = bnd_load(s, scur, lane);
     };
@@ -105,8 +113,9 @@ __global__ void __launch_bounds__(kBlock) k_fused(SysView s, int waves, const do
       const int nrow = (int)min((int64_t)kWave, R1 - t0);
       const bool valid = lane < nrow;
       const int64_t r = t0 + (valid ? lane : 0);
-      const int32_t at_c = at;
-      const int ic[6] = {i01.x, i01.y, i23.x, i23.y, i45.x, i45.y};
+      const int32_t at_c = (int32_t)ri.x;
+      const int ic[6] = {(int)(ri.y & 0xFFFFu), (int)(ri.y >> 16), (int)(ri.z & 0xFFFFu),
+                         (int)(ri.z >> 16),     (int)(ri.w & 0xFFFFu), (int)(ri.w >> 16)};
       const double uo_c = (scale == 0.0) ? 0.0 : scale * uo;
       const int64_t bv_c = bv;
       const int64_t sf = scur;  // star of row t0
@@ -125,11 +134,6 @@ __global__ void __launch_bounds__(kBlock) k_fused(SysView s, int waves, const do
         const int c = j * kWave + lane, i = c / 6, q = c - 6 * i;
         const int at_i = __shfl(at_c, i, kWave);
         cw[j] = *reinterpret_cast<const dd2u*>(x3 + 3 * (int64_t)at_i + 2 * q);
-      }
-      double gxi[6];  // instrumental x when it is not in LDS
-      if (!IL) {
-#pragma unroll
-        for (int q = 0; q < 6; ++q) gxi[q] = x[NI + ic[q]];
       }
       bnds[wid][lane] = bv_c;
       lds_put<CPR>(tmp, nrow, slabs[wid], lane);
@@ -179,7 +183,7 @@ __global__ void __launch_bounds__(kBlock) k_fused(SysView s, int waves, const do
         __builtin_amdgcn_wave_barrier();
       }
 #pragma unroll
-      for (int q = 0; q < 6; ++q) ax += (double)a[17 + q] * (IL ? xil[ic[q]] : gxi[q]);
+      for (int q = 0; q < 6; ++q) ax += (double)a[17 + q] * xil[ic[q]];
       if (s.n_glob) ax += (double)a[23] * xg;
       const double un = uo_c + ax;
       r_out = valid ? r : -1;
@@ -258,34 +262,31 @@ __global__ void __launch_bounds__(kBlock) k_fused(SysView s, int waves, const do
   }
 }
 
-template <typename VT>
-static void fused_launch(int il, int mode, dim3 g, dim3 b, size_t lds, hipStream_t st, const SysView& s, int waves,
-                         const double* vg, const double* x3, double* u, double* gA, double* acc, Scalars* sc,
-                         Work w) {
-  if (mode == 0) {
-    if (il)
-      hipLaunchKernelGGL((k_fused<VT, 1, 0>), g, b, lds, st, s, waves, vg, x3, u, gA, acc, sc, w);
+hipError_t launch_fused(const SysView& s, StreamShape sh, int att_mode, const double* vg, const double* x3,
+                        const void* rix, double* u, double* gA, double* acc, Scalars* sc, Work w, hipStream_t st) {
+  if ((att_mode != 0 && att_mode != 3) || !rix || s.n_instr + 1 > kLdsTailMax) return hipErrorInvalidValue;
+  const int64_t hlen = att_mode == 0 ? s.tail_len : s.tail_len - 3 * s.n_att;
+  const size_t lds = sizeof(double) * (size_t)(hlen + s.n_instr);
+  const dim3 g(sh.blocks), b(kBlock);
+  const u4* rx = reinterpret_cast<const u4*>(rix);
+  if (s.value_type == GSR_F32) {
+    if (att_mode == 0)
+      hipLaunchKernelGGL((k_fused<float, 0>), g, b, lds, st, s, sh.waves, vg, x3, rx, u, gA, acc, sc, w);
     else
-      hipLaunchKernelGGL((k_fused<VT, 0, 0>), g, b, lds, st, s, waves, vg, x3, u, gA, acc, sc, w);
+      hipLaunchKernelGGL((k_fused<float, 3>), g, b, lds, st, s, sh.waves, vg, x3, rx, u, gA, acc, sc, w);
   } else {
-    if (il)
-      hipLaunchKernelGGL((k_fused<VT, 1, 3>), g, b, lds, st, s, waves, vg, x3, u, gA, acc, sc, w);
+    if (att_mode == 0)
+      hipLaunchKernelGGL((k_fused<double, 0>), g, b, lds, st, s, sh.waves, vg, x3, rx, u, gA, acc, sc, w);
     else
-      hipLaunchKernelGGL((k_fused<VT, 0, 3>), g, b, lds, st, s, waves, vg, x3, u, gA, acc, sc, w);
+      hipLaunchKernelGGL((k_fused<double, 3>), g, b, lds, st, s, sh.waves, vg, x3, rx, u, gA, acc, sc, w);
   }
+  return hipGetLastError();
 }
 
-hipError_t launch_fused(const SysView& s, StreamShape sh, int att_mode, const double* vg, const double* x3, double* u,
-                        double* gA, double* acc, Scalars* sc, Work w, hipStream_t st) {
-  if (att_mode != 0 && att_mode != 3) return hipErrorInvalidValue;
-  const int il = s.n_instr <= kLdsInstrMax ? 1 : 0;
-  const int64_t hlen = att_mode == 0 ? s.tail_len : s.tail_len - 3 * s.n_att;
-  const size_t lds = sizeof(double) * (size_t)(hlen + (il ? s.n_instr : 0));
-  const dim3 g(sh.blocks), b(kBlock);
-  if (s.value_type == GSR_F32)
-    fused_launch<float>(il, att_mode, g, b, lds, st, s, sh.waves, vg, x3, u, gA, acc, sc, w);
-  else
-    fused_launch<double>(il, att_mode, g, b, lds, st, s, sh.waves, vg, x3, u, gA, acc, sc, w);
+hipError_t launch_pack_rows(const SysView& s, void* rix, hipStream_t st) {
+  if (s.m == 0) return hipSuccess;
+  const int blocks = (int)std::min<int64_t>(8192, (s.m + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_pack_rows, dim3(blocks), dim3(kBlock), 0, st, s, reinterpret_cast<u4*>(rix));
   return hipGetLastError();
 }
 

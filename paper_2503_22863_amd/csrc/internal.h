@@ -15,7 +15,6 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kSlots = 24;         // coefficients per row: 5 astro, 12 attitude, 6 instr, 1 global
 constexpr int kMaxPartials = 4096; // upper bound on workgroups of a reducing launch
 constexpr int kLdsTailMax = 2048;   // tail columns accumulated in LDS when they fit (16 KB)
-constexpr int kLdsInstrMax = 2048;  // instrumental x staged in LDS by aprod 1 up to this size
 constexpr int kXcds = 8;            // XCDs; workgroup b is dispatched to XCD b mod 8
 
 // Device-resident LSQR state.  Written only by the single "last" workgroup of
@@ -138,8 +137,11 @@ hipError_t launch_att_pass(const SysView& s, const AttView& av, double inv_beta,
 // rows, the astrometric, instrumental and global parts of A^T u on the
 // unnormalised u (astrometric sums to gA, the others into acc; mode 0 also
 // the attitude part).
-hipError_t launch_fused(const SysView& s, StreamShape sh, int att_mode, const double* vg, const double* x3, double* u,
-                        double* gA, double* acc, Scalars* sc, Work w, hipStream_t st);
+// rix: packed row indices from launch_pack_rows (required).
+hipError_t launch_fused(const SysView& s, StreamShape sh, int att_mode, const double* vg, const double* x3,
+                        const void* rix, double* u, double* gA, double* acc, Scalars* sc, Work w, hipStream_t st);
+// rix[r] <- {att_start[r], instr_col[r][0..5] as 16-bit pairs} (16 bytes per row; needs n_instr <= 65536)
+hipError_t launch_pack_rows(const SysView& s, void* rix, hipStream_t st);
 // x3 <- attitude part of x with the three axes interleaved (the fused pass's copy of vg)
 hipError_t launch_att_interleave(const SysView& s, const double* x, double* x3, hipStream_t st);
 // Tail of the fused iteration: every column x_j <- v_scale*x_j + S_j * raw_j / beta (raw_j from gA, acc

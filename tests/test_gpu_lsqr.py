@@ -268,13 +268,15 @@ def test_graph_replay_matches_direct_launches(dev, oracle_lib, precond, cov):
     S.close()
 
 
-@pytest.mark.parametrize("n_att,precond", [(32, True), (1000, True), (1000, False)])
-def test_fused_iteration_matches_separate_products(dev, oracle_lib, n_att, precond):
+@pytest.mark.parametrize("n_att,n_instr,precond", [(32, 16, True), (1000, 16, True), (1000, 16, False),
+                                                   (1000, 2000, True)])
+def test_fused_iteration_matches_separate_products(dev, oracle_lib, n_att, n_instr, precond):
     """One pass over the rows per iteration (A v and the star part of A^T u on the
     unnormalised u) against the oracle and against separate aprod 1 / aprod 2 passes.
-    n_att = 32 keeps the tail in LDS; 1000 uses the bucketed attitude pass."""
-    print(f"[lsqr] fused vs separate n_att={n_att} precond={precond}", flush=True)
-    g = gsr_synth.make_system(300, (20, 40), n_att, 16, 1, seed=17)
+    n_att = 32 keeps the tail in LDS; 1000 uses the bucketed attitude pass; 2000
+    instrumental columns is close to the largest supported (2047)."""
+    print(f"[lsqr] fused vs separate n_att={n_att} n_instr={n_instr} precond={precond}", flush=True)
+    g = gsr_synth.make_system(300, (20, 40), n_att, n_instr, 1, seed=17)
     o = oracle_lib.OSystem(g)
     bn = oracle_lib.known_terms(o, g.x_true, g.noise)
     b = torch.from_numpy(bn).cuda()
