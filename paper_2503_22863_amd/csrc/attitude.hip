@@ -184,7 +184,7 @@ int att_build(const SysView& s, AttView* av, int cus, char* err, size_t errlen, 
     return GSR_EINVAL;
   }
   const int64_t V = s.n_att - 3;  // distinct attitude starts
-  av->K = 4096;
+  av->K = 2048;
   av->Wb = std::max<int64_t>(32, (V + 127) / 128);
   av->nb = (V + av->Wb - 1) / av->Wb;
   av->nchunks = std::max<int64_t>(1, (s.m + av->K - 1) / av->K);
