@@ -135,12 +135,17 @@ def time_to_tolerance_fp32(gsr, g, tol=1e-10, label=""):
     xr, rr = S32.lsqr_refine(b, **ropts)
     err32 = _rel(xr, x_ref)
     t32 = _median_time(lambda: S32.lsqr_refine(b, **ropts))
+    # bytes-only form: FP32 storage, FP64 products (no refinement needed)
+    nb = _iters_to(S32, b, x_ref, tol, 2000, precond=True, product="f64")
+    tb = _median_time(lambda: S32.lsqr_solve(b, atol=0, btol=0, itmax=nb, precond=True, want_var=False,
+                                             product="f64"))
     S64.close()
     S32.close()
     return {"workload": label, "tol": tol, "fp64": {"iterations": n64, "seconds": t64},
             "fp32_refine": {"outer": rr["outer_steps"], "inner_total": rr["inner_total"], "seconds": t32,
                             "rel_err_vs_fp64": err32},
-            "speedup": t64 / t32}
+            "speedup": t64 / t32,
+            "fp32_storage_fp64_products": {"iterations": nb, "seconds": tb, "speedup": t64 / tb}}
 
 
 def time_to_tolerance_warm(gsr, tol=1e-10, train_steps=1500):

@@ -300,3 +300,22 @@ def test_fused_iteration_matches_separate_products(dev, oracle_lib, n_att, n_ins
     for k in ("rnorm", "anorm", "xnorm"):
         assert abs(out[True][2][k] - ref[k]) <= max(1e-10, 10 * ref["sens"][k]) * abs(ref[k])
     S.close()
+
+
+def test_fused_fp32_storage_fp64_products(dev, oracle_lib):
+    """FP32-stored coefficients with FP64 products (the bytes-only form): the fused
+    pass on float rows matches the FP64 oracle on the same FP32-representable matrix."""
+    print("[lsqr] fused, FP32 storage, FP64 products", flush=True)
+    g = gsr_synth.make_system(300, (20, 40), 1000, 16, 1, seed=18).as_f32()
+    g64 = gsr_synth.make_system(300, (20, 40), 1000, 16, 1, seed=18)
+    g64.vals = g.vals.astype(np.float64)  # the same values, exactly
+    o = oracle_lib.OSystem(g64)
+    bn = oracle_lib.known_terms(o, g64.x_true, g64.noise)
+    ref, sx, sv = _sensitivity(oracle_lib, g64, o, bn, atol=0, btol=0, itmax=25, precond=True)
+    S = dev.System.from_generated(g)
+    x, var, r = S.lsqr_solve(torch.from_numpy(bn).cuda(), atol=0, btol=0, itmax=25, precond=True, product="f64")
+    assert r["itn"] == 25
+    ex, ev = _rel(x.cpu().numpy(), ref["x"]), _rel(var.cpu().numpy(), ref["var"])
+    print(f"  x {ex:.2e} var {ev:.2e}", flush=True)
+    assert ex <= max(1e-12, 10 * sx) and ev <= max(1e-10, 10 * sv)
+    S.close()
