@@ -207,6 +207,32 @@ def time_to_tolerance_warm(gsr, tol=1e-10, train_steps=1500):
             "speedup_mlp_vs_zero": a[:, 3].mean() / a[:, 5].mean()}
 
 
+def syrk_bench(gsr, k=4000, reps=20):
+    """The covariance update C += D D^T alone (upper 32x32 tiles, FP64 MFMA) for
+    k selected unknowns and blocks of 64, 256 and 512 buffered iterations."""
+    import torch
+
+    rows = []
+    T = (k + 31) // 32
+    for cols in (64, 256, 512):
+        D = torch.randn(k, cols, dtype=torch.float64, device="cuda")
+        Cm = torch.zeros(k, k, dtype=torch.float64, device="cuda")
+        gsr.syrk(D, k, cols, cols, Cm)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            gsr.syrk(D, k, cols, cols, Cm)
+        b.record()
+        b.synchronize()
+        ms = a.elapsed_time(b) / reps
+        flops = 2.0 * cols * 32 * 32 * (T * (T + 1) // 2)  # the upper tiles computed
+        rows.append({"k": k, "cols": cols, "ms": ms, "tflops": flops / (ms * 1e-3) / 1e12,
+                     "frac_of_fp64_mfma_peak": flops / (ms * 1e-3) / 78.6e12})
+    return {"metric": "covariance SYRK FP64 MFMA rate", "unit": "TFLOP/s", "peak": 78.6, "results": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -217,6 +243,12 @@ def main():
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-1e-10 comparisons")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 2 GiB device copy (known bytes, for scaling HBM counters)")
+    ap.add_argument("--workload", choices=("share_1m", "share_3m"), default="share_1m",
+                    help="share_3m: 3e6 stars, 3x120,000 attitude, 500 instrumental unknowns")
+    ap.add_argument("--cov", type=int, default=0,
+                    help="covariances of this many selected unknowns (blocks of 64 iterations) during the run")
+    ap.add_argument("--syrk-bench", action="store_true",
+                    help="time the covariance SYRK alone (k = 4000) and print its MFMA rate instead")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU row split is not built.",
@@ -229,6 +261,9 @@ def main():
     import paper_2503_22863_amd as gsr
 
     torch.cuda.set_device(0)
+    if args.syrk_bench:
+        print(json.dumps(syrk_bench(gsr)), flush=True)
+        return
     if args.calib_copy:
         a = torch.empty(1 << 28, dtype=torch.float64, device="cuda")
         a.fill_(1.0)
@@ -238,10 +273,18 @@ def main():
         torch.cuda.synchronize()
         del a, c
     t = time.time()
-    g = gsr_synth.share_1m(n_stars=args.stars)
+    if args.workload == "share_3m":
+        g = gsr_synth.share_3m() if args.stars == 1_000_000 else gsr_synth.share_3m(n_stars=args.stars)
+    else:
+        g = gsr_synth.share_1m(n_stars=args.stars)
     m, n, ns = g.dims.m, g.dims.n, g.dims.n_stars
     print(f"# generated m={m} n={n} in {time.time() - t:.1f}s", file=sys.stderr, flush=True)
     S = gsr.System.from_generated(g)
+    if args.cov > 0:
+        nst = (args.cov * 3 // 5) // 5
+        S.cov_request(gsr_synth.covariance_selection(g.dims, nst, args.cov * 3 // 10 // 3, args.cov - 5 * nst
+                                                     - 3 * (args.cov * 3 // 10 // 3), seed=19), block=64)
+    dims = g.dims
     xt = torch.from_numpy(g.x_true).cuda()
     b = torch.from_numpy(g.noise).cuda()
     del g
@@ -265,7 +308,17 @@ def main():
     st = S.lsqr_status()
     if st["itn"] != W + K:
         raise RuntimeError(f"solve stopped early (itn={st['itn']}, istop={st['istop']}): timed steps not all real")
-    S.lsqr_end(want_var=False)
+    cov_ms = None
+    if args.cov > 0:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        S.lsqr_end(want_var=False)  # flushes the last partial covariance block
+        C = S.cov_get()
+        torch.cuda.synchronize()
+        cov_ms = 1e3 * (time.perf_counter() - t1)
+        del C
+    else:
+        S.lsqr_end(want_var=False)
 
     # timing scopes of an iteration: the fused row pass, the attitude passes
     # (partition of u and the bucketed sums), the tail, the x / w / var update
@@ -273,7 +326,7 @@ def main():
     att_ms = tm["aprod2_ms"] / max(1, tm["aprod2_n"])
     kname, by = "k_fused", FUSED_B_ROW * m + FUSED_B_STAR * ns
     achieved = by / (f_ms * 1e-3) / 1e9
-    workload = "share_1m"
+    workload = args.workload
     traffic = load_traffic(kname, workload)
     out = {
         "metric": "LSQR iterations/s (FP64, one-GPU share)",
@@ -288,8 +341,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{workload}: {ns} stars x U[50,90] obs (m={m}), 3x40000 attitude, 200 instr, "
-                               f"1 global (n={n}); unscaled FP64 LSQR, damp 0, variances on",
+        "config": {"workload": f"{workload}: {ns} stars x U[50,90] obs (m={m}), 3x{dims.n_att} attitude, "
+                               f"{dims.n_instr} instr, {dims.n_glob} global (n={n}); unscaled FP64 LSQR, damp 0, "
+                               f"variances on" + (f", covariances of {args.cov} unknowns" if args.cov else ""),
                    "global_batch": m, "seq_len": None, "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
@@ -298,6 +352,9 @@ def main():
                          "tail": tm["tail_ms"] / max(1, tm["tail_n"]),
                          "update": tm["update_ms"] / max(1, tm["update_n"])},
     }
+    if args.cov > 0:
+        out["covariances"] = {"k": args.cov, "block": 64, "syrk_ms_per_block": tm["syrk_ms"] / max(1, tm["syrk_n"]),
+                              "syrk_blocks_timed": tm["syrk_n"], "final_flush_and_get_ms": cov_ms}
     S.close()
     if not args.no_ttt:
         import gsr_synth as _gs
