@@ -4,7 +4,7 @@
 // reducing launch (device_common.h), so the host never waits inside a solve.
 #include <algorithm>
 
-#include "device_common.h"
+#include "row_tiles.h"
 
 namespace gsr {
 
@@ -111,20 +111,30 @@ __global__ void k_finish(int64_t n, const double* __restrict__ y, const double* 
 
 // ---------------------------------------------------------------- SYRK
 // C += D D^T over the first `cols` columns of D ([k][ldd], row-major), on the
-// upper triangle of 32 x 32 tiles of C ([k][k], row-major).  One wave per
-// tile, 2 x 2 blocks of v_mfma_f64_16x16x4f64.  The k index of an MFMA step
-// is permuted (lane group g holds columns 16g + s at step s) so that every
-// lane reads 16 consecutive doubles of a D row; A and B use the same
-// permutation, so the contraction is unchanged.
+// upper triangle of 32 x 32 tiles of C ([k][k], row-major).  A workgroup owns
+// a 64 x 64 tile of C (upper tiles only); its four waves each hold a 32 x 32
+// quadrant in 2 x 2 accumulators of v_mfma_f64_16x16x4f64.  D is staged 16
+// columns at a time: the 64 rows of the tile's row panel and of its column
+// panel go to LDS (row pitch 18 doubles: conflict-free 16-byte reads), the
+// next stage's panels are prefetched into registers meanwhile.  Inside a
+// stage the k index of MFMA step s for lane group g is 4g + s, so each lane
+// reads 4 consecutive doubles of a row; A and B use the same order, so the
+// contraction is unchanged.
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double dd2 __attribute__((ext_vector_type(2)));  // 16-byte aligned pair (LDS)
+constexpr int kSyT = 64;  // C tile per workgroup
+constexpr int kSyK = 16;  // D columns per stage
+constexpr int kSyP = 18;  // LDS row pitch (doubles)
 
 __global__ void __launch_bounds__(kBlock) k_syrk(const double* __restrict__ D, int64_t k, int64_t ldd,
                                                  double* __restrict__ C, Scalars* sc, Work wk, int64_t fixed_cols,
                                                  int64_t T, int64_t ntiles) {
+  __shared__ __align__(16) double pa[kSyT * kSyP];
+  __shared__ __align__(16) double pb[kSyT * kSyP];
   __shared__ int flag;
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   const int64_t cols = fixed_cols >= 0 ? fixed_cols : (int64_t)sc->dcount;
-  const int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + wid;
+  const int64_t tile = blockIdx.x;
   if (tile < ntiles && cols > 0) {
     int64_t ti = 0, rem = tile;
     while (rem >= T - ti) {
@@ -132,43 +142,85 @@ __global__ void __launch_bounds__(kBlock) k_syrk(const double* __restrict__ D, i
       ++ti;
     }
     const int64_t tj = ti + rem;
-    const int64_t row0 = ti * 32, col0 = tj * 32;
+    const int64_t r0 = ti * kSyT, c0 = tj * kSyT;
+    const int qi = wid >> 1, qj = wid & 1;  // this wave's 32 x 32 quadrant
     const int i16 = lane & 15, g = lane >> 4;
+    // global -> register staging: thread t moves 16-byte pieces t and t+256 of
+    // each 64 x 16 panel (8 pieces per row)
+    dd2 ra[2], rb[2];
+    auto fetch = [&](int64_t kk) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int c = (int)threadIdx.x + h * kBlock, row = c >> 3, part = c & 7;
+        const int64_t col = kk + 2 * part;
+        const int64_t ga = r0 + row, gb = c0 + row;
+        dd2 va = {0.0, 0.0}, vb = {0.0, 0.0};
+        if (ga < k) {
+          if (col < cols) va.x = D[ga * ldd + col];
+          if (col + 1 < cols) va.y = D[ga * ldd + col + 1];
+        }
+        if (gb < k) {
+          if (col < cols) vb.x = D[gb * ldd + col];
+          if (col + 1 < cols) vb.y = D[gb * ldd + col + 1];
+        }
+        ra[h] = va;
+        rb[h] = vb;
+      }
+    };
     d4 acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
       for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-    for (int64_t kc = 0; kc < cols; kc += 64) {
-      double av[2][16], bv[2][16];
+    fetch(0);
+    for (int64_t kk = 0; kk < cols; kk += kSyK) {
+      __syncthreads();  // the previous stage's reads are done
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int c = (int)threadIdx.x + h * kBlock, row = c >> 3, part = c & 7;
+        *reinterpret_cast<dd2*>(pa + row * kSyP + 2 * part) = ra[h];
+        *reinterpret_cast<dd2*>(pb + row * kSyP + 2 * part) = rb[h];
+      }
+      __syncthreads();
+      if (kk + kSyK < cols) fetch(kk + kSyK);
+      double av[2][4], bv[2][4];
 #pragma unroll
       for (int bi = 0; bi < 2; ++bi) {
-        const int64_t ra = row0 + 16 * bi + i16, rb = col0 + 16 * bi + i16;
-#pragma unroll
-        for (int s = 0; s < 16; ++s) {
-          const int64_t kk = kc + 16 * g + s;
-          av[bi][s] = (ra < k && kk < cols) ? D[ra * ldd + kk] : 0.0;
-          bv[bi][s] = (rb < k && kk < cols) ? D[rb * ldd + kk] : 0.0;
-        }
+        const double* a = pa + (32 * qi + 16 * bi + i16) * kSyP + 4 * g;
+        const double* b = pb + (32 * qj + 16 * bi + i16) * kSyP + 4 * g;
+        const dd2 a01 = *reinterpret_cast<const dd2*>(a), a23 = *reinterpret_cast<const dd2*>(a + 2);
+        const dd2 b01 = *reinterpret_cast<const dd2*>(b), b23 = *reinterpret_cast<const dd2*>(b + 2);
+        av[bi][0] = a01.x;
+        av[bi][1] = a01.y;
+        av[bi][2] = a23.x;
+        av[bi][3] = a23.y;
+        bv[bi][0] = b01.x;
+        bv[bi][1] = b01.y;
+        bv[bi][2] = b23.x;
+        bv[bi][3] = b23.y;
       }
 #pragma unroll
-      for (int s = 0; s < 16; ++s)
+      for (int st = 0; st < 4; ++st)
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
           for (int bj = 0; bj < 2; ++bj)
-            acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bi][s], bv[bj][s], acc[bi][bj], 0, 0, 0);
+            acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bi][st], bv[bj][st], acc[bi][bj], 0, 0, 0);
     }
-    // accumulator layout of the 16x16 f64 result: element e of lane l is row (l/16) + 4e, column l%16
+    // accumulator layout of the 16x16 f64 result: element e of lane l is row (l/16) + 4e, column l%16.
+    // Only 32 x 32 tiles on or above the diagonal are written.
+    const int64_t row32 = r0 + 32 * qi, col32 = c0 + 32 * qj;
+    if (row32 <= col32) {
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+      for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
+        for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int64_t r = row0 + 16 * bi + g + 4 * e, c = col0 + 16 * bj + i16;
-          if (r < k && c < k) C[r * k + c] += acc[bi][bj][e];
-        }
+          for (int e = 0; e < 4; ++e) {
+            const int64_t r = row32 + 16 * bi + g + 4 * e, c = col32 + 16 * bj + i16;
+            if (r < k && c < k) C[r * k + c] += acc[bi][bj][e];
+          }
+    }
   }
   if (fixed_cols < 0) {
     if (last_block(wk.tickets + T_SYRK, &flag) && threadIdx.x == 0) {
@@ -259,9 +311,9 @@ hipError_t launch_finish(int64_t n, const double* y, const double* var, const do
 
 hipError_t launch_syrk(const double* D, int64_t k, int64_t ldd, double* C, Scalars* sc, Work w, int64_t fixed_cols,
                        hipStream_t st) {
-  const int64_t T = (k + 31) / 32;
+  const int64_t T = (k + kSyT - 1) / kSyT;
   const int64_t ntiles = T * (T + 1) / 2;
-  const int64_t blocks = std::max<int64_t>(1, (ntiles + kWavesPerBlock - 1) / kWavesPerBlock);
+  const int64_t blocks = std::max<int64_t>(1, ntiles);
   hipLaunchKernelGGL(k_syrk, dim3((unsigned)blocks), dim3(kBlock), 0, st, D, k, ldd, C, sc, w, fixed_cols, T,
                      ntiles);
   return hipGetLastError();
