@@ -1,0 +1,81 @@
+"""Parity at the full one-GPU share (10^6 stars x U[50,90] observations, m ~ 7.0e7,
+n = 5,120,201), in the launch configuration bench.py times (default tuning,
+fused iteration, graph replay).
+
+The oracle runs the whole share on the host CPU (a few seconds per product), so
+every output is compared, not a sample: products at the 1e-13 normwise bar per
+block, and two unscaled LSQR iterations against the oracle's at the 1e-10
+converged-solution bar (the early iterates are far less sensitive than that)."""
+import numpy as np
+import pytest
+import torch
+
+import gsr_synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _blocks(d):
+    na = d.n_astro
+    nt = na + 3 * d.n_att
+    ni = nt + d.n_instr
+    out = {"astro": slice(0, na), "att": slice(na, nt), "instr": slice(nt, ni), "all": slice(0, d.n)}
+    if d.n_glob:
+        out["glob"] = slice(ni, ni + 1)
+    return out
+
+
+@pytest.fixture(scope="module")
+def share(oracle_lib):
+    import paper_2503_22863_amd as gsr
+
+    print("[full] generating the 10^6-star share", flush=True)
+    g = gsr_synth.share_1m()
+    o = oracle_lib.OSystem(g)
+    S = gsr.System.from_generated(g)
+    yield g, o, S
+    S.close()
+
+
+def test_full_share_products(oracle_lib, share):
+    g, o, S = share
+    d = g.dims
+    rng = np.random.default_rng(41)
+    x = rng.standard_normal(d.n)
+    y = rng.standard_normal(d.m)
+    print("[full] aprod 1 / aprod 2 on the GPU", flush=True)
+    y_gpu = S.aprod1(torch.from_numpy(x).cuda()).cpu().numpy()
+    x_gpu = S.aprod2(torch.from_numpy(y).cuda()).cpu().numpy()
+    print("[full] oracle products", flush=True)
+    y_ref = oracle_lib.aprod1(o, x)
+    x_ref = oracle_lib.aprod2(o, y)
+    e1 = _rel(y_gpu, y_ref)
+    print(f"  aprod1 {e1:.2e}", flush=True)
+    assert e1 <= 1e-13
+    for name, sl in _blocks(d).items():
+        e = _rel(x_gpu[sl], x_ref[sl])
+        print(f"  aprod2 {name} {e:.2e}", flush=True)
+        assert e <= 1e-13, name
+
+
+def test_full_share_lsqr_iterations(oracle_lib, share):
+    g, o, S = share
+    d = g.dims
+    b = oracle_lib.known_terms(o, g.x_true, g.noise)
+    print("[full] 2 LSQR iterations on the GPU (fused, graphs)", flush=True)
+    x, var, r = S.lsqr_solve(torch.from_numpy(b).cuda(), atol=0, btol=0, itmax=2, precond=False)
+    assert r["itn"] == 2
+    print("[full] 2 oracle LSQR iterations", flush=True)
+    ref = oracle_lib.lsqr(o, b, atol=0, btol=0, itmax=2, precond=False)
+    x, var = x.cpu().numpy(), var.cpu().numpy()
+    for name, sl in _blocks(d).items():
+        ex, ev = _rel(x[sl], ref["x"][sl]), _rel(var[sl], ref["var"][sl])
+        print(f"  {name}: x {ex:.2e} var {ev:.2e}", flush=True)
+        assert ex <= 1e-10 and ev <= 1e-10, name
+    for k in ("rnorm", "anorm", "xnorm"):
+        assert abs(r[k] - ref[k]) <= 1e-10 * abs(ref[k]), k
