@@ -194,6 +194,33 @@ int gsr_cov_get(gsr_system *sys, double *C, gsr_stream stream);
 int64_t gsr_cov_bytes(int32_t version, int64_t itn_cov_cp, int64_t count);
 
 /*
+ * Export of the whole per-iteration vectors d_i = w_i / rho_i (all n
+ * unknowns, in the preconditioned variable of the solve) for covariances
+ * chosen after the run: version 1 of the covariance pipeline of Sec. 2.2,
+ * whose per-cycle size is Eq. (5) (gsr_cov_bytes(1, block, n)).
+ *   gsr_cov_export attaches, for the next solves, the caller's host buffer
+ *   host [max_blocks][block][n] doubles (pinned memory from hipHostMalloc
+ *   lets the copies overlap the solve; pageable memory works but stalls it).
+ *   Every `block` iterations the block's vectors are copied asynchronously
+ *   from a device ring of 2*block*n doubles on a copy stream of the handle;
+ *   gsr_lsqr_end / gsr_lsqr_solve return once all copies have landed.  Block
+ *   b holds iterations b*block+1 .. (b+1)*block; blocks past max_blocks are
+ *   not stored.  block in [1, 1024]; block = 0 detaches.  Graph replay is
+ *   not used while exporting.
+ *   gsr_cov_export_status: blocks of the last solve and the vectors in its
+ *   last block (itn = (blocks-1)*block + last_cols).
+ * gsr_cov_from_export forms C = S_sel (sum_i d_i[sel] d_i[sel]^T) S_sel from
+ * such blocks (the covariances program of Sec. 2.2): blocks host
+ * [nblocks][block][n], the last holding last_cols vectors; sel host [k] in
+ * [0, n); S device [n], the column scaling the solve used (NULL if none);
+ * C device [k][k], full symmetric.  Synchronous on `stream`.
+ */
+int gsr_cov_export(gsr_system *sys, double *host, int64_t max_blocks, int32_t block);
+int gsr_cov_export_status(gsr_system *sys, int64_t *blocks, int32_t *last_cols);
+int gsr_cov_from_export(const double *blocks, int64_t n, int32_t block, int64_t nblocks, int32_t last_cols,
+                        const int64_t *sel, int64_t k, const double *S, double *C, gsr_stream stream);
+
+/*
  * One covariance update C += D[:, :cols] D[:, :cols]^T (Eq. 4 over a block of
  * buffered vectors) on the upper triangle of 32x32 tiles of C.
  *   D device [k][ldd] (cols <= ldd), C device [k][k]; lower-triangle tiles

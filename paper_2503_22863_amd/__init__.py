@@ -83,6 +83,10 @@ _SIGS = {
     "gsr_timing_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "gsr_set_graphs": (C.c_int, [C.c_void_p, C.c_int32]),
     "gsr_set_fused": (C.c_int, [C.c_void_p, C.c_int32]),
+    "gsr_cov_export": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32]),
+    "gsr_cov_export_status": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gsr_cov_from_export": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_int64, C.c_int32, C.c_void_p,
+                                      C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]),
     "gsr_timing_get": (C.c_int, [C.c_void_p, C.c_void_p]),
     "gsr_features": (C.c_int, [C.c_void_p] * 5),
     "gsr_mean_rows": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p]),
@@ -154,6 +158,17 @@ def cov_bytes(version, itn_cov_cp, count):
 
 def syrk(D, k, cols, ldd, Cmat, stream=None):
     _check(lib().gsr_syrk(_ptr(D), k, cols, ldd, _ptr(Cmat), _stream(stream)))
+
+
+def cov_from_export(blocks, n, block, nblocks, last_cols, sel, S=None, stream=None):
+    """Covariances of the selected unknowns from exported d_i blocks (host tensor
+    [>= nblocks][block][n]); S: the solve's column scaling (device) or None."""
+    sel = np.ascontiguousarray(np.asarray(sel, dtype=np.int64))
+    out = torch.empty((sel.size, sel.size), dtype=torch.float64, device="cuda")
+    _check(lib().gsr_cov_from_export(C.c_void_p(blocks.data_ptr()), int(n), int(block), int(nblocks),
+                                     int(last_cols), sel.ctypes.data if sel.size else None, sel.size,
+                                     _ptr(S) if S is not None else None, _ptr(out), _stream(stream)))
+    return out
 
 
 def mean_rows(X, stream=None):
@@ -349,6 +364,23 @@ class System:
         sel = np.ascontiguousarray(np.asarray(sel, dtype=np.int64))
         _check(lib().gsr_cov_request(self._h, sel.ctypes.data if sel.size else None, sel.size, int(block)))
         self.ncov = sel.size
+
+    def cov_export(self, host=None, block=64):
+        """Attach a host buffer [max_blocks][block][n] (CPU float64 tensor, pinned for overlap)
+        for the whole d_i of the next solves; host=None detaches."""
+        if host is None:
+            _check(lib().gsr_cov_export(self._h, None, 0, 0))
+            self._export = None
+            return
+        assert host.device.type == "cpu" and host.dtype == torch.float64 and host.is_contiguous()
+        assert host.shape[1] == block and host.shape[2] == self.n
+        _check(lib().gsr_cov_export(self._h, C.c_void_p(host.data_ptr()), host.shape[0], int(block)))
+        self._export = host  # keep alive
+
+    def cov_export_status(self):
+        nb, lc = C.c_int64(), C.c_int32()
+        _check(lib().gsr_cov_export_status(self._h, C.byref(nb), C.byref(lc)))
+        return nb.value, lc.value
 
     def cov_get(self, stream=None):
         out = torch.empty((self.ncov, self.ncov), dtype=torch.float64, device=self.device)

@@ -78,6 +78,18 @@ struct gsr_system {
   double* D = nullptr;
   double* Cacc = nullptr;
   int cov_precond = 0;
+  // export of whole d_i blocks (covariance pipeline version 1)
+  int32_t eblock = 0;              // 0: off
+  double* ering = nullptr;         // device ring [2*eblock][n]
+  double* ehost = nullptr;         // caller's host buffer [emax][eblock][n]
+  int64_t emax = 0;
+  hipStream_t estream = nullptr;   // copies
+  hipEvent_t eev[2] = {nullptr, nullptr};  // copy of ring half h done
+  hipEvent_t efill = nullptr;      // ring half filled (solve stream)
+  int eissued[2] = {0, 0};         // a copy from ring half h is outstanding
+  std::vector<char> ecopied;       // block b copied during this solve
+  int64_t eblocks = 0;             // blocks of the last solve
+  int32_t elast = 0;               // vectors in its last block
   // session
   int in_session = 0;
   int precond = 0;
@@ -179,6 +191,10 @@ static void release(gsr_system* s) {
   dfree(s->y);
   dfree(s->var);
   dfree(s->gA);
+  dfree(s->ering);
+  if (s->estream) (void)hipStreamDestroy(s->estream);
+  for (hipEvent_t e : {s->eev[0], s->eev[1], s->efill})
+    if (e) (void)hipEventDestroy(e);
   dfree(s->x3);
   dfree(s->rix);
   dfree(s->r);
@@ -522,6 +538,13 @@ static int lsqr_begin(gsr_system* s, const double* b, const double* x0, const gs
   s->x0 = x0;
   s->itmax = o->itmax;
   s->enq = 0;
+  if (s->eblock) {
+    HIPCHK(hipStreamSynchronize(s->estream));
+    s->eissued[0] = s->eissued[1] = 0;
+    s->ecopied.assign((size_t)((o->itmax + s->eblock - 1) / s->eblock + 1), 0);
+    s->eblocks = 0;
+    s->elast = 0;
+  }
   const double* S = o->precond ? s->S : nullptr;
 
   Scalars h;
@@ -561,9 +584,30 @@ extern "C" int gsr_lsqr_begin(gsr_system* s, const double* b, const double* x0, 
 
 // One LSQR iteration: aprod 1, aprod 2 (+ tail), update, and the covariance
 // SYRK when a block of `dblock` columns is complete.
+// Export: copy ring half h (block b, `rows` vectors) into the caller's buffer on
+// the copy stream, after what the solve stream has enqueued so far.
+static int export_copy(gsr_system* s, int64_t b, int64_t rows, hipStream_t st) {
+  const int h = (int)(b & 1);
+  const size_t n = (size_t)s->s.n;
+  if (b >= s->emax || rows <= 0) return GSR_OK;
+  HIPCHK(hipEventRecord(s->efill, st));
+  HIPCHK(hipStreamWaitEvent(s->estream, s->efill, 0));
+  HIPCHK(hipMemcpyAsync(s->ehost + (size_t)b * s->eblock * n, s->ering + (size_t)h * s->eblock * n,
+                        sizeof(double) * (size_t)rows * n, hipMemcpyDeviceToHost, s->estream));
+  HIPCHK(hipEventRecord(s->eev[h], s->estream));
+  s->eissued[h] = 1;
+  if ((size_t)b < s->ecopied.size()) s->ecopied[(size_t)b] = 1;
+  return GSR_OK;
+}
+
 static int enqueue_iteration(gsr_system* s, hipStream_t st) {
   const double* S = s->precond ? s->S : nullptr;
   double* vg = s->precond ? s->vg : s->v;
+  if (s->eblock && s->enq % s->eblock == 0) {
+    // this iteration starts refilling ring half h: its previous copy must be done
+    const int h = (int)((s->enq / s->eblock) & 1);
+    if (s->eissued[h]) HIPCHK(hipStreamWaitEvent(st, s->eev[h], 0));
+  }
   if (iteration_fused(s)) {
     const int mode = att_mode(s);
     {
@@ -588,7 +632,8 @@ static int enqueue_iteration(gsr_system* s, hipStream_t st) {
   }
   {
     TimeScope ts(s, 3, st);
-    HIPCHK(launch_update(s->s.n, s->v, vg, s->w, s->y, s->var, S, s->sc, s->wk, st));
+    HIPCHK(launch_update(s->s.n, s->v, vg, s->w, s->y, s->var, S, s->sc, s->wk, st, s->eblock ? s->ering : nullptr,
+                         s->eblock ? s->eblock : 1));
     if (iteration_fused(s)) HIPCHK(launch_att_interleave(s->s, vg, s->x3, st));
   }
   s->enq += 1;
@@ -596,6 +641,7 @@ static int enqueue_iteration(gsr_system* s, hipStream_t st) {
     TimeScope ts(s, 4, st);
     HIPCHK(launch_syrk(s->D, s->nsel, s->dblock, s->Cacc, s->sc, s->wk, -1, st));
   }
+  if (s->eblock && s->enq % s->eblock == 0) CHK(export_copy(s, s->enq / s->eblock - 1, s->eblock, st));
   return GSR_OK;
 }
 
@@ -656,7 +702,7 @@ static int lsqr_iterate(gsr_system* s, int64_t nit, hipStream_t st) {
   // blocks of G iterations by graph replay when no per-kernel timing is requested;
   // with covariances a block is the covariance block, aligned to it
   const int64_t G = s->nsel > 0 ? s->dblock : 16;
-  if (s->use_graphs && !s->timing) {
+  if (s->use_graphs && !s->timing && !s->eblock) {
     while (nit >= G && s->itmax - s->enq >= G && (s->nsel == 0 || s->enq % G == 0)) {
       CHK(graph_block(s, G, st));
       nit -= G;
@@ -715,6 +761,15 @@ static int lsqr_end(gsr_system* s, double* x, double* var, gsr_lsqr_result* r, h
   }
   HIPCHK(launch_finish(s->s.n, s->y, s->var, s->precond ? s->S : nullptr, s->x0, x, var, st));
   CHK(read_status(s, r, st));
+  if (s->eblock) {
+    // blocks of the iterations actually run; the last, possibly partial, one is
+    // copied now unless an eager copy (issued once its block was enqueued) covers it
+    const int64_t itn = s->sc_host->itn;  // read_status copied the scalars back
+    s->eblocks = (itn + s->eblock - 1) / s->eblock;
+    s->elast = (int32_t)(itn - (s->eblocks - 1) * s->eblock);
+    if (s->eblocks > 0 && !s->ecopied[(size_t)(s->eblocks - 1)]) CHK(export_copy(s, s->eblocks - 1, s->elast, st));
+    HIPCHK(hipStreamSynchronize(s->estream));
+  }
   s->in_session = 0;
   return GSR_OK;
 }
@@ -769,7 +824,9 @@ extern "C" int gsr_lsqr_refine(gsr_system* s, const double* b, const double* x0,
     HIPCHK(launch_fill(s->xr, (int64_t)n, 0.0, st));
   }
   const int64_t keep_sel = s->nsel;
-  s->nsel = 0;  // covariances are not accumulated across refinement steps
+  const int32_t keep_eblock = s->eblock;
+  s->nsel = 0;  // covariances are neither accumulated nor exported across refinement steps
+  s->eblock = 0;
   int64_t total = 0;
   int32_t steps = 0;
   gsr_lsqr_result last{};
@@ -799,6 +856,7 @@ extern "C" int gsr_lsqr_refine(gsr_system* s, const double* b, const double* x0,
     if (sqrt(h2[0]) <= o->outer_tol * sqrt(h2[1])) break;
   }
   s->nsel = keep_sel;
+  s->eblock = keep_eblock;
   if (rc) return rc;
   HIPCHK(hipMemcpyAsync(x, s->xr, n * sizeof(double), hipMemcpyDeviceToDevice, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -850,6 +908,104 @@ extern "C" int gsr_cov_get(gsr_system* s, double* C, gsr_stream stream) {
   NEED_DEV(C, "C");
   HIPCHK(launch_cov_out(s->Cacc, s->nsel, s->cov_precond ? s->S : nullptr, s->sel, C, (hipStream_t)stream));
   return GSR_OK;
+}
+
+extern "C" int gsr_cov_export(gsr_system* s, double* host, int64_t max_blocks, int32_t block) {
+  CHK(check_handle(s));
+  if (s->in_session) return fail(GSR_ESTATE, "gsr_cov_export: a solve is in progress");
+  if (block < 0 || block > 1024) return fail(GSR_EINVAL, "block must be in [0, 1024]");
+  if (block > 0 && (!host || max_blocks < 1)) return fail(GSR_EINVAL, "need a host buffer and max_blocks >= 1");
+  if (block > 0 && is_device_ptr(host)) return fail(GSR_EINVAL, "the export buffer must be host memory");
+  if (s->ering && block != s->eblock) {
+    dfree(s->ering);
+    s->ering = nullptr;
+  }
+  s->eblock = 0;
+  s->ehost = nullptr;
+  s->emax = 0;
+  s->eblocks = 0;
+  s->elast = 0;
+  if (block == 0) return GSR_OK;
+  if (!s->ering) CHK(dalloc(&s->ering, 2 * (size_t)block * (size_t)std::max<int64_t>(s->s.n, 1)));
+  if (!s->estream) {
+    HIPCHK(hipStreamCreateWithFlags(&s->estream, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&s->eev[0], hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&s->eev[1], hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&s->efill, hipEventDisableTiming));
+  }
+  s->eblock = block;
+  s->ehost = host;
+  s->emax = max_blocks;
+  drop_graph(s);
+  return GSR_OK;
+}
+
+extern "C" int gsr_cov_export_status(gsr_system* s, int64_t* blocks, int32_t* last_cols) {
+  CHK(check_handle(s));
+  if (!blocks || !last_cols) return fail(GSR_EINVAL, "null output");
+  *blocks = s->eblocks;
+  *last_cols = s->elast;
+  return GSR_OK;
+}
+
+extern "C" int gsr_cov_from_export(const double* blocks, int64_t n, int32_t block, int64_t nblocks, int32_t last_cols,
+                                   const int64_t* sel, int64_t k, const double* S, double* C, gsr_stream stream) {
+  if (n < 1 || block < 1 || block > 1024 || nblocks < 0 || k < 0) return fail(GSR_EINVAL, "bad sizes");
+  if (nblocks > 0 && (last_cols < 1 || last_cols > block)) return fail(GSR_EINVAL, "last_cols must be in [1, block]");
+  if (k == 0) return GSR_OK;
+  if (!sel || !C || (nblocks > 0 && !blocks)) return fail(GSR_EINVAL, "null argument");
+  if (is_device_ptr(blocks) || is_device_ptr(sel)) return fail(GSR_EINVAL, "blocks and sel must be host memory");
+  NEED_DEV(C, "C");
+  if (S) NEED_DEV(S, "S");
+  for (int64_t p = 0; p < k; ++p)
+    if (sel[p] < 0 || sel[p] >= n) return fail(GSR_EINVAL, "sel[%lld] out of range", (long long)p);
+  hipStream_t st = (hipStream_t)stream;
+  double *Dd = nullptr, *Cacc = nullptr, *stage = nullptr;
+  int64_t* seld = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  int rc = GSR_OK;
+  auto done = [&](int code) {
+    if (code != GSR_OK) (void)hipStreamSynchronize(st);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+    dfree(Dd);
+    dfree(Cacc);
+    dfree(seld);
+    if (stage) (void)hipHostFree(stage);
+    return code;
+  };
+  const size_t kb = (size_t)k * (size_t)block;
+  if ((rc = dalloc(&Dd, 2 * kb)) || (rc = dalloc(&Cacc, (size_t)k * (size_t)k)) || (rc = dalloc(&seld, (size_t)k)))
+    return done(rc);
+  if (hipHostMalloc((void**)&stage, sizeof(double) * 2 * kb, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return done(fail(GSR_ENOMEM, "pinned staging allocation failed"));
+  }
+  if (hipEventCreateWithFlags(&ev[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess ||
+      hipMemcpyAsync(seld, sel, sizeof(int64_t) * (size_t)k, hipMemcpyHostToDevice, st) != hipSuccess ||
+      launch_fill(Cacc, k * k, 0.0, st) != hipSuccess)
+    return done(fail(GSR_EHIP, "cov_from_export set-up failed"));
+  Work none{};
+  for (int64_t b = 0; b < nblocks; ++b) {
+    const int h = (int)(b & 1);
+    const int64_t cols = (b == nblocks - 1) ? last_cols : block;
+    if (b >= 2 && hipEventSynchronize(ev[h]) != hipSuccess) return done(fail(GSR_EHIP, "staging wait failed"));
+    // gather the selected rows of the block's vectors: stage[p][c] = d_{b*block+c}[sel[p]]
+    double* sg = stage + (size_t)h * kb;
+    const double* blk = blocks + (size_t)b * (size_t)block * (size_t)n;
+    for (int64_t c = 0; c < cols; ++c) {
+      const double* dv = blk + (size_t)c * (size_t)n;
+      for (int64_t p = 0; p < k; ++p) sg[(size_t)p * block + c] = dv[sel[p]];
+    }
+    double* dd = Dd + (size_t)h * kb;
+    if (hipMemcpyAsync(dd, sg, sizeof(double) * kb, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipEventRecord(ev[h], st) != hipSuccess || launch_syrk(dd, k, block, Cacc, nullptr, none, cols, st) != hipSuccess)
+      return done(fail(GSR_EHIP, "cov_from_export block %lld failed", (long long)b));
+  }
+  if (launch_cov_out(Cacc, k, S, seld, C, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
+    return done(fail(GSR_EHIP, "cov_from_export output failed"));
+  return done(GSR_OK);
 }
 
 extern "C" int gsr_syrk(const double* D, int64_t k, int64_t cols, int64_t ldd, double* C, gsr_stream stream) {

@@ -158,8 +158,10 @@ hipError_t launch_copy(const double* src, double* dst, int64_t n, hipStream_t st
 hipError_t launch_norm_init(const double* u, int64_t m, Scalars* sc, Work w, hipStream_t st);
 hipError_t launch_init_vectors(int64_t n, double* v, double* vg, double* w, double* y, double* var,
                                const double* S, Scalars* sc, hipStream_t st);
+// dring: export ring of 2*eblock rows of n (d_i stored in row itn mod 2*eblock), or null
 hipError_t launch_update(int64_t n, double* v, double* vg, double* w, double* y, double* var,
-                         const double* S, Scalars* sc, Work w_, hipStream_t st);
+                         const double* S, Scalars* sc, Work w_, hipStream_t st, double* dring = nullptr,
+                         int64_t eblock = 1);
 hipError_t launch_finish(int64_t n, const double* y, const double* var, const double* S, const double* x0,
                          double* x_out, double* var_out, hipStream_t st);
 hipError_t launch_syrk(const double* D, int64_t k, int64_t ldd, double* C, Scalars* sc, Work w,

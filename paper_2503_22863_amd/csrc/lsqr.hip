@@ -60,14 +60,19 @@ __global__ void k_init_vectors(int64_t n, double* __restrict__ v, double* __rest
 //   v <- v / alpha_{i+1};  d = w / rho;  y += (phi/rho) w;  var += d^2;
 //   w <- v - (theta/rho) w;  partial sums of ||y||^2 and ||d||^2.
 // The last workgroup evaluates the stopping tests.
+// With an export ring (dring != null, 2*eblock rows of n): d_i is also stored
+// whole, in row i mod 2*eblock, where i = sc->itn is read before this launch's
+// last workgroup advances it.
 __global__ void __launch_bounds__(kBlock) k_update(int64_t n, double* __restrict__ v, double* __restrict__ vg,
                                                    double* __restrict__ w, double* __restrict__ y,
                                                    double* __restrict__ var, const double* __restrict__ S,
-                                                   Scalars* sc, Work wk) {
+                                                   Scalars* sc, Work wk, double* __restrict__ dring,
+                                                   int64_t eblock) {
   __shared__ double red[kWavesPerBlock];
   __shared__ int flag;
   if (sc->done) return;
   const double ia = sc->inv_alpha, t1 = sc->t1, t2 = sc->t2, t3 = sc->t3;
+  double* drow = dring ? dring + (sc->itn % (2 * eblock)) * n : nullptr;
   double xs = 0.0, ds = 0.0;
   for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) {
     const double vj = v[j] * ia;
@@ -75,6 +80,7 @@ __global__ void __launch_bounds__(kBlock) k_update(int64_t n, double* __restrict
     if (S) vg[j] = S[j] * vj;
     const double wj = w[j];
     const double d = t3 * wj;
+    if (drow) drow[j] = d;
     const double yj = y[j] + t1 * wj;
     y[j] = yj;
     var[j] = var[j] + d * d;
@@ -297,8 +303,9 @@ hipError_t launch_init_vectors(int64_t n, double* v, double* vg, double* w, doub
 }
 
 hipError_t launch_update(int64_t n, double* v, double* vg, double* w, double* y, double* var, const double* S,
-                         Scalars* sc, Work w_, hipStream_t st) {
-  hipLaunchKernelGGL(k_update, dim3(blocks_for(n)), dim3(kBlock), 0, st, n, v, vg, w, y, var, S, sc, w_);
+                         Scalars* sc, Work w_, hipStream_t st, double* dring, int64_t eblock) {
+  hipLaunchKernelGGL(k_update, dim3(blocks_for(n)), dim3(kBlock), 0, st, n, v, vg, w, y, var, S, sc, w_, dring,
+                     eblock);
   return hipGetLastError();
 }
 

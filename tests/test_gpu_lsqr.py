@@ -319,3 +319,46 @@ def test_fused_fp32_storage_fp64_products(dev, oracle_lib):
     print(f"  x {ex:.2e} var {ev:.2e}", flush=True)
     assert ex <= max(1e-12, 10 * sx) and ev <= max(1e-10, 10 * sv)
     S.close()
+
+
+def test_cov_export_version1(dev, oracle_lib, tiny):
+    """Whole d_i vectors exported every `block` iterations (version 1 of the covariance
+    pipeline) against the oracle's d_i; covariances formed afterwards from the export
+    against the in-run covariances and the oracle's.  Two solves: a fixed count
+    ending in a partial block, and a converged solve stopping mid-block."""
+    print("[lsqr] covariance export (version 1)", flush=True)
+    g, o, b, S = tiny
+    n, block = g.dims.n, 16
+    sel = gsr_synth.covariance_selection(g.dims, 10, 5, 4, seed=1)
+    Sc = S.column_scale()
+    host = torch.empty((16, block, n), dtype=torch.float64).pin_memory()
+    S.cov_export(host, block)
+    S.cov_request(sel, block=block)
+    try:
+        for itmax, tol in ((40, 0.0), (200, 1e-12)):
+            x, var, r = S.lsqr_solve(torch.from_numpy(b).cuda(), atol=tol, btol=tol, itmax=itmax, precond=True)
+            nb, lc = S.cov_export_status()
+            itn = r["itn"]
+            print(f"  itmax={itmax}: itn={itn} blocks={nb} last={lc}", flush=True)
+            assert (nb - 1) * block + lc == itn and 1 <= lc <= block
+            ref = oracle_lib.lsqr(o, b, atol=tol, btol=tol, itmax=itmax, precond=True, sel=np.arange(n))
+            assert abs(ref["itn"] - itn) <= 1
+            k = min(itn, ref["itn"])
+            D = host[:nb].reshape(-1, n)[:k].numpy()
+            # the first 40 iterates are insensitive (1e-15); past convergence d_i shrinks
+            # like the residual and keeps a last-bit relative error of its own size
+            e = _rel(D[:40], ref["dsel"][:40])
+            print(f"    exported d_i vs oracle (first 40): {e:.2e}", flush=True)
+            assert e <= 1e-10
+            C_post = dev.cov_from_export(host, n, block, nb, lc, sel, S=Sc).cpu().numpy()
+            C_run = S.cov_get().cpu().numpy()
+            C_ref = oracle_lib.covariances(ref["dsel"][:, sel], ref["scale"][sel])
+            e_run, e_ref = _rel(C_post, C_run), _rel(C_post, C_ref)
+            print(f"    post-hoc C vs in-run {e_run:.2e}, vs oracle {e_ref:.2e}", flush=True)
+            assert e_run <= 1e-13
+            # C sums d_i d_i^T over every iterate: the oracle's own last-bit response is
+            # 3e-14 at 40 fixed iterations and 2.3e-5 for the converged solve (77 steps)
+            assert e_ref <= (1e-10 if tol == 0.0 else 3e-4)
+    finally:
+        S.cov_export(None)
+        S.cov_request([], block=64)
