@@ -247,6 +247,9 @@ def main():
                     help="share_3m: 3e6 stars, 3x120,000 attitude, 500 instrumental unknowns")
     ap.add_argument("--cov", type=int, default=0,
                     help="covariances of this many selected unknowns (blocks of 64 iterations) during the run")
+    ap.add_argument("--export", type=int, default=0,
+                    help="export the whole d_i every this many iterations to pinned host memory during the run, "
+                         "then form covariances of --cov unknowns from the export")
     ap.add_argument("--syrk-bench", action="store_true",
                     help="time the covariance SYRK alone (k = 4000) and print its MFMA rate instead")
     args = ap.parse_args()
@@ -285,6 +288,15 @@ def main():
         S.cov_request(gsr_synth.covariance_selection(g.dims, nst, args.cov * 3 // 10 // 3, args.cov - 5 * nst
                                                      - 3 * (args.cov * 3 // 10 // 3), seed=19), block=64)
     dims = g.dims
+    sel = None
+    if args.cov > 0:
+        sel = gsr_synth.covariance_selection(g.dims, nst, args.cov * 3 // 10 // 3,
+                                             args.cov - 5 * nst - 3 * (args.cov * 3 // 10 // 3), seed=19)
+    ehost = None
+    if args.export > 0:
+        nblk = (args.warmup + args.steps + args.export - 1) // args.export + 1
+        ehost = torch.empty((nblk, args.export, g.dims.n), dtype=torch.float64).pin_memory()
+        S.cov_export(ehost, args.export)
     xt = torch.from_numpy(g.x_true).cuda()
     b = torch.from_numpy(g.noise).cuda()
     del g
@@ -352,6 +364,19 @@ def main():
                          "tail": tm["tail_ms"] / max(1, tm["tail_n"]),
                          "update": tm["update_ms"] / max(1, tm["update_n"])},
     }
+    if args.export > 0:
+        nb, lc = S.cov_export_status()
+        out["export"] = {"block": args.export, "blocks": nb, "last_cols": lc,
+                         "bytes_per_block": 8 * args.export * n,
+                         "iteration_ms_with_export": 1e3 * T / K}
+        if sel is not None:
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            Cx = gsr.cov_from_export(ehost, n, args.export, nb, lc, sel)
+            torch.cuda.synchronize()
+            out["export"]["read_cov_ms_per_block"] = 1e3 * (time.perf_counter() - t1) / max(1, nb)
+            out["export"]["k"] = int(sel.size)
+            del Cx
     if args.cov > 0:
         out["covariances"] = {"k": args.cov, "block": 64, "syrk_ms_per_block": tm["syrk_ms"] / max(1, tm["syrk_n"]),
                               "syrk_blocks_timed": tm["syrk_n"], "final_flush_and_get_ms": cov_ms}
