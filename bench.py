@@ -250,6 +250,8 @@ def main():
     ap.add_argument("--export", type=int, default=0,
                     help="export the whole d_i every this many iterations to pinned host memory during the run, "
                          "then form covariances of --cov unknowns from the export")
+    ap.add_argument("--pairs", type=int, default=0,
+                    help="covariances of this many random index pairs (blocks of 64 iterations) during the run")
     ap.add_argument("--syrk-bench", action="store_true",
                     help="time the covariance SYRK alone (k = 4000) and print its MFMA rate instead")
     args = ap.parse_args()
@@ -258,6 +260,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
 
     import gsr_synth
@@ -287,6 +290,9 @@ def main():
         nst = (args.cov * 3 // 5) // 5
         S.cov_request(gsr_synth.covariance_selection(g.dims, nst, args.cov * 3 // 10 // 3, args.cov - 5 * nst
                                                      - 3 * (args.cov * 3 // 10 // 3), seed=19), block=64)
+    if args.pairs > 0:
+        rngp = np.random.default_rng(29)
+        S.cov_request_pairs(rngp.integers(0, g.dims.n, size=(args.pairs, 2)), block=64)
     dims = g.dims
     sel = None
     if args.cov > 0:
@@ -377,6 +383,10 @@ def main():
             out["export"]["read_cov_ms_per_block"] = 1e3 * (time.perf_counter() - t1) / max(1, nb)
             out["export"]["k"] = int(sel.size)
             del Cx
+    if args.pairs > 0:
+        out["pair_covariances"] = {"pairs": args.pairs, "block": 64,
+                                   "pair_dots_ms_per_block": tm["syrk_ms"] / max(1, tm["syrk_n"]),
+                                   "blocks_timed": tm["syrk_n"]}
     if args.cov > 0:
         out["covariances"] = {"k": args.cov, "block": 64, "syrk_ms_per_block": tm["syrk_ms"] / max(1, tm["syrk_n"]),
                               "syrk_blocks_timed": tm["syrk_n"], "final_flush_and_get_ms": cov_ms}

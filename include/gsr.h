@@ -194,6 +194,27 @@ int gsr_cov_get(gsr_system *sys, double *C, gsr_stream stream);
 int64_t gsr_cov_bytes(int32_t version, int64_t itn_cov_cp, int64_t count);
 
 /*
+ * Covariances for a list of index pairs instead of a dense block (version 2
+ * of the covariance pipeline, Sec. 2.2, whose files hold the x_Cycle entries
+ * of the indexes j1, j2 of Eq. (4)):
+ *   gsr_cov_request_pairs attaches pairs host [P][2] of unknowns in [0, n)
+ *   (repeats allowed; (j, j) gives var[j]) for the next solves.  Their
+ *   distinct indexes are buffered per iteration as by gsr_cov_request and,
+ *   every `block` iterations, C_p += sum_i d_i[j1_p] d_i[j2_p] is formed by a
+ *   dot-product kernel (16 lanes per pair); block in [1, 1024].  Replaces a
+ *   dense request (and vice versa); P = 0 detaches.
+ *   gsr_cov_get_pairs writes out device [P]: C_p = s_j1 s_j2 sum_i ... of the
+ *   last solve.
+ *   gsr_cov_pairs_from_export forms the same values from blocks written by
+ *   gsr_cov_export (arguments as gsr_cov_from_export; pairs host [P][2];
+ *   out device [P]).
+ */
+int gsr_cov_request_pairs(gsr_system *sys, const int64_t *pairs, int64_t P, int32_t block);
+int gsr_cov_get_pairs(gsr_system *sys, double *out, gsr_stream stream);
+int gsr_cov_pairs_from_export(const double *blocks, int64_t n, int32_t block, int64_t nblocks, int32_t last_cols,
+                              const int64_t *pairs, int64_t P, const double *S, double *out, gsr_stream stream);
+
+/*
  * Export of the whole per-iteration vectors d_i = w_i / rho_i (all n
  * unknowns, in the preconditioned variable of the solve) for covariances
  * chosen after the run: version 1 of the covariance pipeline of Sec. 2.2,

@@ -87,6 +87,10 @@ _SIGS = {
     "gsr_cov_export_status": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "gsr_cov_from_export": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_int64, C.c_int32, C.c_void_p,
                                       C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gsr_cov_request_pairs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32]),
+    "gsr_cov_get_pairs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gsr_cov_pairs_from_export": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_int64, C.c_int32, C.c_void_p,
+                                            C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]),
     "gsr_timing_get": (C.c_int, [C.c_void_p, C.c_void_p]),
     "gsr_features": (C.c_int, [C.c_void_p] * 5),
     "gsr_mean_rows": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p]),
@@ -168,6 +172,17 @@ def cov_from_export(blocks, n, block, nblocks, last_cols, sel, S=None, stream=No
     _check(lib().gsr_cov_from_export(C.c_void_p(blocks.data_ptr()), int(n), int(block), int(nblocks),
                                      int(last_cols), sel.ctypes.data if sel.size else None, sel.size,
                                      _ptr(S) if S is not None else None, _ptr(out), _stream(stream)))
+    return out
+
+
+def cov_pairs_from_export(blocks, n, block, nblocks, last_cols, pairs, S=None, stream=None):
+    """Covariances of the index pairs [P][2] from exported d_i blocks; S as cov_from_export."""
+    pairs = np.ascontiguousarray(np.asarray(pairs, dtype=np.int64).reshape(-1, 2))
+    out = torch.empty(pairs.shape[0], dtype=torch.float64, device="cuda")
+    _check(lib().gsr_cov_pairs_from_export(C.c_void_p(blocks.data_ptr()), int(n), int(block), int(nblocks),
+                                           int(last_cols), pairs.ctypes.data if pairs.size else None,
+                                           pairs.shape[0], _ptr(S) if S is not None else None, _ptr(out),
+                                           _stream(stream)))
     return out
 
 
@@ -381,6 +396,17 @@ class System:
         nb, lc = C.c_int64(), C.c_int32()
         _check(lib().gsr_cov_export_status(self._h, C.byref(nb), C.byref(lc)))
         return nb.value, lc.value
+
+    def cov_request_pairs(self, pairs, block=64):
+        pairs = np.ascontiguousarray(np.asarray(pairs, dtype=np.int64).reshape(-1, 2))
+        _check(lib().gsr_cov_request_pairs(self._h, pairs.ctypes.data if pairs.size else None, pairs.shape[0],
+                                           int(block)))
+        self.npairs = pairs.shape[0]
+
+    def cov_get_pairs(self, stream=None):
+        out = torch.empty(self.npairs, dtype=torch.float64, device=self.device)
+        _check(lib().gsr_cov_get_pairs(self._h, _ptr(out), _stream(stream)))
+        return out
 
     def cov_get(self, stream=None):
         out = torch.empty((self.ncov, self.ncov), dtype=torch.float64, device=self.device)

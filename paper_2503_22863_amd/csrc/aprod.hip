@@ -436,21 +436,9 @@ __global__ void __launch_bounds__(kBlock) k_tail(SysView s, AttView av, int att_
   if (last_block(wk.tickets + T_TAIL, &flag)) {
     double tot = sum_partials(wk.part_b, L.astro_parts, red);
     tot += sum_partials(wk.part_a, gridDim.x, red);
-    __shared__ double t3s;
-    __shared__ int64_t cols;
     if (threadIdx.x == 0) {
       epi_alpha(sc, tot, L.lsqr_stage == 0);
-      t3s = sc->t3;
-      cols = sc->dcount;
       ticket_reset(wk.tickets + T_TAIL);
-    }
-    __syncthreads();
-    if (L.lsqr_stage != 0 && sc->nsel > 0) {
-      const int64_t ld = sc->dblock;
-      if (cols < ld) {
-        for (int64_t p = threadIdx.x; p < sc->nsel; p += kBlock) L.D[p * ld + cols] = t3s * L.w[L.sel[p]];
-        if (threadIdx.x == 0) sc->dcount = (int32_t)(cols + 1);
-      }
     }
   }
 }
@@ -549,20 +537,18 @@ hipError_t launch_aprod2(const SysView& s, StreamShape sh, int att_mode, const v
 }
 
 hipError_t launch_tail(const SysView& s, const AttView& av, int att_mode, double* x, double* acc, const double* S,
-                       double scale, Scalars* sc, Work w, int lsqr_stage, int astro_parts, const int64_t* sel,
-                       const double* wv, double* D, hipStream_t st) {
+                       double scale, Scalars* sc, Work w, int lsqr_stage, int astro_parts, hipStream_t st) {
   int blocks = (int)std::min<int64_t>(512, std::max<int64_t>(1, (s.tail_len + kBlock - 1) / kBlock));
-  TailLsqr L{lsqr_stage, astro_parts, sel, wv, D, nullptr};
+  TailLsqr L{lsqr_stage, astro_parts, nullptr};
   hipLaunchKernelGGL(k_tail, dim3(blocks), dim3(kBlock), 0, st, s, av, att_mode, x, acc, S, scale, sc, w, L);
   return hipGetLastError();
 }
 
 hipError_t launch_tail_fused(const SysView& s, const AttView& av, int att_mode, double* x, double* acc,
-                             const double* S, const double* gA, Scalars* sc, Work w, const int64_t* sel,
-                             const double* wv, double* D, hipStream_t st) {
+                             const double* S, const double* gA, Scalars* sc, Work w, hipStream_t st) {
   const int64_t cols = s.n_astro + s.tail_len;
   int blocks = (int)std::min<int64_t>(kMaxPartials, std::max<int64_t>(1, (cols + kBlock - 1) / kBlock));
-  TailLsqr L{1, 0, sel, wv, D, gA};
+  TailLsqr L{1, 0, gA};
   hipLaunchKernelGGL(k_tail, dim3(blocks), dim3(kBlock), 0, st, s, av, att_mode, x, acc, S, 0.0, sc, w, L);
   return hipGetLastError();
 }

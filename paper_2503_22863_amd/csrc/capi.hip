@@ -78,6 +78,10 @@ struct gsr_system {
   double* D = nullptr;
   double* Cacc = nullptr;
   int cov_precond = 0;
+  // covariances for a pair list instead of a dense block (sel = the pairs' distinct unknowns)
+  int64_t npairs = 0;
+  int32_t *pa = nullptr, *pb = nullptr;  // positions in sel
+  double* Cp = nullptr;
   // export of whole d_i blocks (covariance pipeline version 1)
   int32_t eblock = 0;              // 0: off
   double* ering = nullptr;         // device ring [2*eblock][n]
@@ -191,6 +195,9 @@ static void release(gsr_system* s) {
   dfree(s->y);
   dfree(s->var);
   dfree(s->gA);
+  dfree(s->pa);
+  dfree(s->pb);
+  dfree(s->Cp);
   dfree(s->ering);
   if (s->estream) (void)hipStreamDestroy(s->estream);
   for (hipEvent_t e : {s->eev[0], s->eev[1], s->efill})
@@ -453,11 +460,9 @@ static int aprod2_launches(gsr_system* s, const double* y, double* x, const doub
   }
   TimeScope ts(s, 2, st);
   if (sc)
-    HIPCHK(launch_tail(s->s, s->av, mode, x, s->acc, S, 0.0, sc, s->wk, lsqr_stage, s->sh.blocks, s->sel, s->w, s->D,
-                       st));
+    HIPCHK(launch_tail(s->s, s->av, mode, x, s->acc, S, 0.0, sc, s->wk, lsqr_stage, s->sh.blocks, st));
   else
-    HIPCHK(launch_tail(s->s, s->av, mode, x, s->acc, nullptr, scale, nullptr, s->wk, 0, 0, nullptr, nullptr, nullptr,
-                       st));
+    HIPCHK(launch_tail(s->s, s->av, mode, x, s->acc, nullptr, scale, nullptr, s->wk, 0, 0, st));
   return GSR_OK;
 }
 
@@ -559,7 +564,10 @@ static int lsqr_begin(gsr_system* s, const double* b, const double* x0, const gs
   *s->sc_host = h;
   HIPCHK(hipMemcpyAsync(s->sc, s->sc_host, sizeof(Scalars), hipMemcpyHostToDevice, st));
   if (s->nsel > 0) {
-    HIPCHK(launch_fill(s->Cacc, s->nsel * s->nsel, 0.0, st));
+    if (s->npairs > 0)
+      HIPCHK(launch_fill(s->Cp, s->npairs, 0.0, st));
+    else
+      HIPCHK(launch_fill(s->Cacc, s->nsel * s->nsel, 0.0, st));
     s->cov_precond = o->precond;
   }
   // r0 = b - A x0
@@ -584,6 +592,13 @@ extern "C" int gsr_lsqr_begin(gsr_system* s, const double* b, const double* x0, 
 
 // One LSQR iteration: aprod 1, aprod 2 (+ tail), update, and the covariance
 // SYRK when a block of `dblock` columns is complete.
+// One covariance update from the buffered columns: SYRK for a dense block, the
+// pair dot products for a pair list.
+static hipError_t cov_flush(gsr_system* s, hipStream_t st) {
+  if (s->npairs > 0) return launch_pairdot(s->D, s->dblock, s->pa, s->pb, s->npairs, s->Cp, s->sc, s->wk, -1, st);
+  return launch_syrk(s->D, s->nsel, s->dblock, s->Cacc, s->sc, s->wk, -1, st);
+}
+
 // Export: copy ring half h (block b, `rows` vectors) into the caller's buffer on
 // the copy stream, after what the solve stream has enqueued so far.
 static int export_copy(gsr_system* s, int64_t b, int64_t rows, hipStream_t st) {
@@ -621,7 +636,7 @@ static int enqueue_iteration(gsr_system* s, hipStream_t st) {
     }
     {
       TimeScope ts(s, 2, st);
-      HIPCHK(launch_tail_fused(s->s, s->av, mode, s->v, s->acc, S, s->gA, s->sc, s->wk, s->sel, s->w, s->D, st));
+      HIPCHK(launch_tail_fused(s->s, s->av, mode, s->v, s->acc, S, s->gA, s->sc, s->wk, st));
     }
   } else {
     {
@@ -629,6 +644,10 @@ static int enqueue_iteration(gsr_system* s, hipStream_t st) {
       HIPCHK(launch_aprod1(s->s, s->sh, vg, s->u, 0.0, 1.0, s->pmode, s->sc, s->wk, 1, st));
     }
     CHK(aprod2_launches(s, s->u, s->v, S, 0.0, s->pmode, 0, s->sc, 1, st));
+  }
+  if (s->nsel > 0) {
+    TimeScope ts(s, 2, st);
+    HIPCHK(launch_cov_gather(s->nsel, s->sel, s->w, s->D, s->sc, s->wk, st));
   }
   {
     TimeScope ts(s, 3, st);
@@ -639,7 +658,7 @@ static int enqueue_iteration(gsr_system* s, hipStream_t st) {
   s->enq += 1;
   if (s->nsel > 0 && s->enq % s->dblock == 0) {
     TimeScope ts(s, 4, st);
-    HIPCHK(launch_syrk(s->D, s->nsel, s->dblock, s->Cacc, s->sc, s->wk, -1, st));
+    HIPCHK(cov_flush(s, st));
   }
   if (s->eblock && s->enq % s->eblock == 0) CHK(export_copy(s, s->enq / s->eblock - 1, s->eblock, st));
   return GSR_OK;
@@ -757,7 +776,7 @@ static int lsqr_end(gsr_system* s, double* x, double* var, gsr_lsqr_result* r, h
   if (var) NEED_DEV(var, "var");
   if (s->nsel > 0) {
     TimeScope ts(s, 4, st);
-    HIPCHK(launch_syrk(s->D, s->nsel, s->dblock, s->Cacc, s->sc, s->wk, -1, st));
+    HIPCHK(cov_flush(s, st));
   }
   HIPCHK(launch_finish(s->s.n, s->y, s->var, s->precond ? s->S : nullptr, s->x0, x, var, st));
   CHK(read_status(s, r, st));
@@ -874,6 +893,35 @@ extern "C" int64_t gsr_cov_bytes(int32_t version, int64_t itn_cov_cp, int64_t co
   return 8 * itn_cov_cp * count;  // Eq. (5) with count = N_unk, Eq. (6) with count = N_cov,indexes
 }
 
+static void cov_clear(gsr_system* s) {
+  for (void* p : {(void*)s->sel, (void*)s->D, (void*)s->Cacc, (void*)s->pa, (void*)s->pb, (void*)s->Cp}) dfree(p);
+  s->sel = nullptr;
+  s->D = nullptr;
+  s->Cacc = nullptr;
+  s->pa = s->pb = nullptr;
+  s->Cp = nullptr;
+  s->nsel = 0;
+  s->npairs = 0;
+}
+
+// Distinct unknowns of a pair list (sorted) and each pair's two positions in them.
+static int pair_index(const int64_t* pairs, int64_t P, int64_t n, std::vector<int64_t>* U, std::vector<int32_t>* a,
+                      std::vector<int32_t>* b) {
+  U->assign(pairs, pairs + 2 * P);
+  for (int64_t v : *U)
+    if (v < 0 || v >= n) return fail(GSR_EINVAL, "pair index %lld out of range", (long long)v);
+  std::sort(U->begin(), U->end());
+  U->erase(std::unique(U->begin(), U->end()), U->end());
+  if (U->size() >= ((size_t)1 << 31)) return fail(GSR_EINVAL, "too many distinct pair indexes");
+  a->resize((size_t)P);
+  b->resize((size_t)P);
+  for (int64_t p = 0; p < P; ++p) {
+    (*a)[(size_t)p] = (int32_t)(std::lower_bound(U->begin(), U->end(), pairs[2 * p]) - U->begin());
+    (*b)[(size_t)p] = (int32_t)(std::lower_bound(U->begin(), U->end(), pairs[2 * p + 1]) - U->begin());
+  }
+  return GSR_OK;
+}
+
 extern "C" int gsr_cov_request(gsr_system* s, const int64_t* sel, int64_t k, int32_t block) {
   CHK(check_handle(s));
   if (k < 0) return fail(GSR_EINVAL, "k < 0");
@@ -882,15 +930,10 @@ extern "C" int gsr_cov_request(gsr_system* s, const int64_t* sel, int64_t k, int
   for (int64_t p = 0; p < k; ++p)
     if (sel[p] < 0 || sel[p] >= s->s.n) return fail(GSR_EINVAL, "sel[%lld] = %lld out of range", (long long)p,
                                                      (long long)sel[p]);
+  if (s->in_session) return fail(GSR_ESTATE, "gsr_cov_request: a solve is in progress");
   (void)hipDeviceSynchronize();
   drop_graph(s);
-  dfree(s->sel);
-  dfree(s->D);
-  dfree(s->Cacc);
-  s->sel = nullptr;
-  s->D = nullptr;
-  s->Cacc = nullptr;
-  s->nsel = 0;
+  cov_clear(s);
   if (k == 0) return GSR_OK;
   CHK(dalloc(&s->sel, (size_t)k));
   CHK(dalloc(&s->D, (size_t)k * block));
@@ -902,8 +945,47 @@ extern "C" int gsr_cov_request(gsr_system* s, const int64_t* sel, int64_t k, int
   return GSR_OK;
 }
 
+extern "C" int gsr_cov_request_pairs(gsr_system* s, const int64_t* pairs, int64_t P, int32_t block) {
+  CHK(check_handle(s));
+  if (s->in_session) return fail(GSR_ESTATE, "gsr_cov_request_pairs: a solve is in progress");
+  if (P < 0) return fail(GSR_EINVAL, "P < 0");
+  if (P > 0 && !pairs) return fail(GSR_EINVAL, "pairs is null");
+  if (block < 1 || block > 1024) return fail(GSR_EINVAL, "block must be in [1, 1024]");
+  std::vector<int64_t> U;
+  std::vector<int32_t> a, b;
+  if (P > 0) CHK(pair_index(pairs, P, s->s.n, &U, &a, &b));
+  (void)hipDeviceSynchronize();
+  drop_graph(s);
+  cov_clear(s);
+  if (P == 0) return GSR_OK;
+  const int64_t k = (int64_t)U.size();
+  CHK(dalloc(&s->sel, (size_t)k));
+  CHK(dalloc(&s->D, (size_t)k * block));
+  CHK(dalloc(&s->pa, (size_t)P));
+  CHK(dalloc(&s->pb, (size_t)P));
+  CHK(dalloc(&s->Cp, (size_t)P));
+  HIPCHK(hipMemcpy(s->sel, U.data(), (size_t)k * sizeof(int64_t), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(s->pa, a.data(), (size_t)P * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(s->pb, b.data(), (size_t)P * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIPCHK(hipMemset(s->Cp, 0, (size_t)P * sizeof(double)));
+  s->nsel = k;
+  s->npairs = P;
+  s->dblock = block;
+  return GSR_OK;
+}
+
+extern "C" int gsr_cov_get_pairs(gsr_system* s, double* out, gsr_stream stream) {
+  CHK(check_handle(s));
+  if (s->npairs == 0) return fail(GSR_ESTATE, "no pair list");
+  NEED_DEV(out, "out");
+  HIPCHK(launch_pair_out(s->Cp, s->npairs, s->pa, s->pb, s->cov_precond ? s->S : nullptr, s->sel, out,
+                         (hipStream_t)stream));
+  return GSR_OK;
+}
+
 extern "C" int gsr_cov_get(gsr_system* s, double* C, gsr_stream stream) {
   CHK(check_handle(s));
+  if (s->npairs > 0) return fail(GSR_ESTATE, "the covariance request is a pair list: use gsr_cov_get_pairs");
   if (s->nsel == 0) return fail(GSR_ESTATE, "no covariance selection");
   NEED_DEV(C, "C");
   HIPCHK(launch_cov_out(s->Cacc, s->nsel, s->cov_precond ? s->S : nullptr, s->sel, C, (hipStream_t)stream));
@@ -948,50 +1030,38 @@ extern "C" int gsr_cov_export_status(gsr_system* s, int64_t* blocks, int32_t* la
   return GSR_OK;
 }
 
-extern "C" int gsr_cov_from_export(const double* blocks, int64_t n, int32_t block, int64_t nblocks, int32_t last_cols,
-                                   const int64_t* sel, int64_t k, const double* S, double* C, gsr_stream stream) {
-  if (n < 1 || block < 1 || block > 1024 || nblocks < 0 || k < 0) return fail(GSR_EINVAL, "bad sizes");
-  if (nblocks > 0 && (last_cols < 1 || last_cols > block)) return fail(GSR_EINVAL, "last_cols must be in [1, block]");
-  if (k == 0) return GSR_OK;
-  if (!sel || !C || (nblocks > 0 && !blocks)) return fail(GSR_EINVAL, "null argument");
-  if (is_device_ptr(blocks) || is_device_ptr(sel)) return fail(GSR_EINVAL, "blocks and sel must be host memory");
-  NEED_DEV(C, "C");
-  if (S) NEED_DEV(S, "S");
-  for (int64_t p = 0; p < k; ++p)
-    if (sel[p] < 0 || sel[p] >= n) return fail(GSR_EINVAL, "sel[%lld] out of range", (long long)p);
-  hipStream_t st = (hipStream_t)stream;
-  double *Dd = nullptr, *Cacc = nullptr, *stage = nullptr;
-  int64_t* seld = nullptr;
+// Post-hoc covariance accumulation over exported blocks: for each block, the
+// rows sel of its vectors are gathered on the host into a pinned [k][block]
+// stage, copied, and reduced into Cacc (dense, SYRK) or Cp (pair list).
+static int export_accumulate(const double* blocks, int64_t n, int32_t block, int64_t nblocks, int32_t last_cols,
+                             const int64_t* sel, int64_t k, double* Cacc, const int32_t* pa, const int32_t* pb,
+                             int64_t P, double* Cp, hipStream_t st) {
+  double *Dd = nullptr, *stage = nullptr;
   hipEvent_t ev[2] = {nullptr, nullptr};
-  int rc = GSR_OK;
   auto done = [&](int code) {
-    if (code != GSR_OK) (void)hipStreamSynchronize(st);
+    (void)hipStreamSynchronize(st);
     for (hipEvent_t e : ev)
       if (e) (void)hipEventDestroy(e);
     dfree(Dd);
-    dfree(Cacc);
-    dfree(seld);
     if (stage) (void)hipHostFree(stage);
     return code;
   };
   const size_t kb = (size_t)k * (size_t)block;
-  if ((rc = dalloc(&Dd, 2 * kb)) || (rc = dalloc(&Cacc, (size_t)k * (size_t)k)) || (rc = dalloc(&seld, (size_t)k)))
-    return done(rc);
+  int rc = dalloc(&Dd, 2 * kb);
+  if (rc) return done(rc);
   if (hipHostMalloc((void**)&stage, sizeof(double) * 2 * kb, hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
     return done(fail(GSR_ENOMEM, "pinned staging allocation failed"));
   }
   if (hipEventCreateWithFlags(&ev[0], hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess ||
-      hipMemcpyAsync(seld, sel, sizeof(int64_t) * (size_t)k, hipMemcpyHostToDevice, st) != hipSuccess ||
-      launch_fill(Cacc, k * k, 0.0, st) != hipSuccess)
-    return done(fail(GSR_EHIP, "cov_from_export set-up failed"));
+      hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess)
+    return done(fail(GSR_EHIP, "event creation failed"));
   Work none{};
   for (int64_t b = 0; b < nblocks; ++b) {
     const int h = (int)(b & 1);
     const int64_t cols = (b == nblocks - 1) ? last_cols : block;
     if (b >= 2 && hipEventSynchronize(ev[h]) != hipSuccess) return done(fail(GSR_EHIP, "staging wait failed"));
-    // gather the selected rows of the block's vectors: stage[p][c] = d_{b*block+c}[sel[p]]
+    // stage[p][c] = d_{b*block+c}[sel[p]]
     double* sg = stage + (size_t)h * kb;
     const double* blk = blocks + (size_t)b * (size_t)block * (size_t)n;
     for (int64_t c = 0; c < cols; ++c) {
@@ -999,13 +1069,84 @@ extern "C" int gsr_cov_from_export(const double* blocks, int64_t n, int32_t bloc
       for (int64_t p = 0; p < k; ++p) sg[(size_t)p * block + c] = dv[sel[p]];
     }
     double* dd = Dd + (size_t)h * kb;
-    if (hipMemcpyAsync(dd, sg, sizeof(double) * kb, hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipEventRecord(ev[h], st) != hipSuccess || launch_syrk(dd, k, block, Cacc, nullptr, none, cols, st) != hipSuccess)
-      return done(fail(GSR_EHIP, "cov_from_export block %lld failed", (long long)b));
+    hipError_t e = hipMemcpyAsync(dd, sg, sizeof(double) * kb, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipEventRecord(ev[h], st);
+    if (e == hipSuccess)
+      e = P > 0 ? launch_pairdot(dd, block, pa, pb, P, Cp, nullptr, none, cols, st)
+                : launch_syrk(dd, k, block, Cacc, nullptr, none, cols, st);
+    if (e != hipSuccess) return done(fail(GSR_EHIP, "block %lld: %s", (long long)b, hipGetErrorString(e)));
   }
-  if (launch_cov_out(Cacc, k, S, seld, C, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
-    return done(fail(GSR_EHIP, "cov_from_export output failed"));
   return done(GSR_OK);
+}
+
+static int check_export_args(const double* blocks, int64_t n, int32_t block, int64_t nblocks, int32_t last_cols) {
+  if (n < 1 || block < 1 || block > 1024 || nblocks < 0) return fail(GSR_EINVAL, "bad sizes");
+  if (nblocks > 0 && (last_cols < 1 || last_cols > block)) return fail(GSR_EINVAL, "last_cols must be in [1, block]");
+  if (nblocks > 0 && !blocks) return fail(GSR_EINVAL, "blocks is null");
+  if (is_device_ptr(blocks)) return fail(GSR_EINVAL, "blocks must be host memory");
+  return GSR_OK;
+}
+
+extern "C" int gsr_cov_from_export(const double* blocks, int64_t n, int32_t block, int64_t nblocks, int32_t last_cols,
+                                   const int64_t* sel, int64_t k, const double* S, double* C, gsr_stream stream) {
+  CHK(check_export_args(blocks, n, block, nblocks, last_cols));
+  if (k < 0) return fail(GSR_EINVAL, "k < 0");
+  if (k == 0) return GSR_OK;
+  if (!sel || is_device_ptr(sel)) return fail(GSR_EINVAL, "sel must be host memory");
+  NEED_DEV(C, "C");
+  if (S) NEED_DEV(S, "S");
+  for (int64_t p = 0; p < k; ++p)
+    if (sel[p] < 0 || sel[p] >= n) return fail(GSR_EINVAL, "sel[%lld] out of range", (long long)p);
+  hipStream_t st = (hipStream_t)stream;
+  double* Cacc = nullptr;
+  int64_t* seld = nullptr;
+  int rc = GSR_OK;
+  if (!(rc = dalloc(&Cacc, (size_t)k * (size_t)k)) && !(rc = dalloc(&seld, (size_t)k))) {
+    if (hipMemcpyAsync(seld, sel, sizeof(int64_t) * (size_t)k, hipMemcpyHostToDevice, st) != hipSuccess ||
+        launch_fill(Cacc, k * k, 0.0, st) != hipSuccess)
+      rc = fail(GSR_EHIP, "cov_from_export set-up failed");
+    if (!rc) rc = export_accumulate(blocks, n, block, nblocks, last_cols, sel, k, Cacc, nullptr, nullptr, 0, nullptr, st);
+    if (!rc && (launch_cov_out(Cacc, k, S, seld, C, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess))
+      rc = fail(GSR_EHIP, "cov_from_export output failed");
+  }
+  (void)hipStreamSynchronize(st);
+  dfree(Cacc);
+  dfree(seld);
+  return rc;
+}
+
+extern "C" int gsr_cov_pairs_from_export(const double* blocks, int64_t n, int32_t block, int64_t nblocks,
+                                         int32_t last_cols, const int64_t* pairs, int64_t P, const double* S,
+                                         double* out, gsr_stream stream) {
+  CHK(check_export_args(blocks, n, block, nblocks, last_cols));
+  if (P < 0) return fail(GSR_EINVAL, "P < 0");
+  if (P == 0) return GSR_OK;
+  if (!pairs || is_device_ptr(pairs)) return fail(GSR_EINVAL, "pairs must be host memory");
+  NEED_DEV(out, "out");
+  if (S) NEED_DEV(S, "S");
+  std::vector<int64_t> U;
+  std::vector<int32_t> a, b;
+  CHK(pair_index(pairs, P, n, &U, &a, &b));
+  const int64_t k = (int64_t)U.size();
+  hipStream_t st = (hipStream_t)stream;
+  double* Cp = nullptr;
+  int32_t *pa = nullptr, *pb = nullptr;
+  int64_t* seld = nullptr;
+  int rc = GSR_OK;
+  if (!(rc = dalloc(&Cp, (size_t)P)) && !(rc = dalloc(&pa, (size_t)P)) && !(rc = dalloc(&pb, (size_t)P)) &&
+      !(rc = dalloc(&seld, (size_t)k))) {
+    if (hipMemcpyAsync(seld, U.data(), sizeof(int64_t) * (size_t)k, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(pa, a.data(), sizeof(int32_t) * (size_t)P, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(pb, b.data(), sizeof(int32_t) * (size_t)P, hipMemcpyHostToDevice, st) != hipSuccess ||
+        launch_fill(Cp, P, 0.0, st) != hipSuccess)
+      rc = fail(GSR_EHIP, "cov_pairs_from_export set-up failed");
+    if (!rc) rc = export_accumulate(blocks, n, block, nblocks, last_cols, U.data(), k, nullptr, pa, pb, P, Cp, st);
+    if (!rc && (launch_pair_out(Cp, P, pa, pb, S, seld, out, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess))
+      rc = fail(GSR_EHIP, "cov_pairs_from_export output failed");
+  }
+  (void)hipStreamSynchronize(st);
+  for (void* p : {(void*)Cp, (void*)pa, (void*)pb, (void*)seld}) dfree(p);
+  return rc;
 }
 
 extern "C" int gsr_syrk(const double* D, int64_t k, int64_t cols, int64_t ldd, double* C, gsr_stream stream) {

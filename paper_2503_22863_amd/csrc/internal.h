@@ -51,7 +51,7 @@ struct Work {
   unsigned* tickets;         // [8] last-workgroup tickets, one per kernel kind
 };
 
-enum Ticket { T_APROD1 = 0, T_APROD2 = 1, T_TAIL = 2, T_UPDATE = 3, T_INIT = 4, T_SYRK = 5, T_VALID = 6 };
+enum Ticket { T_APROD1 = 0, T_APROD2 = 1, T_TAIL = 2, T_UPDATE = 3, T_INIT = 4, T_SYRK = 5, T_VALID = 6, T_GATHER = 7 };
 
 // A borrowed view of the caller's system arrays plus the sizes derived from them.
 struct SysView {
@@ -104,9 +104,6 @@ struct AttView {
 struct TailLsqr {
   int lsqr_stage;       // 0 init, 1 iteration
   int astro_parts;      // partials written by the aprod2 launch
-  const int64_t* sel;   // selected unknowns (nsel = sc->nsel)
-  const double* w;      // search direction w_i
-  double* D;            // [nsel][dblock]
   const double* gA;     // fused iteration: raw astrometric column sums (scaled here by 1/beta); else null
 };
 
@@ -122,8 +119,7 @@ hipError_t launch_aprod2(const SysView& s, StreamShape sh, int att_mode, const v
                          Scalars* sc, Work w, hipStream_t st);
 // tail part: x_t <- scale*x_t + S_t * (acc_t or window sums), acc cleared; LSQR epilogue when sc != nullptr.
 hipError_t launch_tail(const SysView& s, const AttView& av, int att_mode, double* x, double* acc, const double* S,
-                       double scale, Scalars* sc, Work w, int lsqr_stage, int astro_parts, const int64_t* sel,
-                       const double* wv, double* D, hipStream_t st);
+                       double scale, Scalars* sc, Work w, int lsqr_stage, int astro_parts, hipStream_t st);
 int att_mode_of(const SysView& s, const AttView& av, int force_atomics);
 // bucketed attitude pass (attitude.hip)
 int att_build(const SysView& s, AttView* av, int cus, char* err, size_t errlen, hipStream_t st);
@@ -145,10 +141,13 @@ hipError_t launch_pack_rows(const SysView& s, void* rix, hipStream_t st);
 // x3 <- attitude part of x with the three axes interleaved (the fused pass's copy of vg)
 hipError_t launch_att_interleave(const SysView& s, const double* x, double* x3, hipStream_t st);
 // Tail of the fused iteration: every column x_j <- v_scale*x_j + S_j * raw_j / beta (raw_j from gA, acc
-// or the attitude windows), then alpha_{i+1}, the rotations and the covariance column, as launch_tail.
+// or the attitude windows), then alpha_{i+1} and the rotations, as launch_tail.
 hipError_t launch_tail_fused(const SysView& s, const AttView& av, int att_mode, double* x, double* acc,
-                             const double* S, const double* gA, Scalars* sc, Work w, const int64_t* sel,
-                             const double* wv, double* D, hipStream_t st);
+                             const double* S, const double* gA, Scalars* sc, Work w, hipStream_t st);
+// Covariance column of the iteration: D[p][dcount] = w[sel[p]] / rho_i for p < nsel (after the tail);
+// the last workgroup advances dcount.  Skipped once the solve has stopped or the block is full.
+hipError_t launch_cov_gather(int64_t nsel, const int64_t* sel, const double* w, double* D, Scalars* sc, Work wk,
+                             hipStream_t st);
 // bad[0] <- first row with an out-of-range index, bad[1] <- first bad star, bad[2] <- 1 if a star is empty
 hipError_t launch_validate(const SysView& s, unsigned long long* bad, hipStream_t st);
 hipError_t launch_scale_from_sq(int64_t n, double* S, hipStream_t st);
@@ -166,6 +165,12 @@ hipError_t launch_finish(int64_t n, const double* y, const double* var, const do
                          double* x_out, double* var_out, hipStream_t st);
 hipError_t launch_syrk(const double* D, int64_t k, int64_t ldd, double* C, Scalars* sc, Work w,
                        int64_t fixed_cols, hipStream_t st);
+// Cp[p] += sum_{c<cols} D[pa[p]][c] D[pb[p]][c] (cols = fixed_cols, or sc->dcount then reset to 0)
+hipError_t launch_pairdot(const double* D, int64_t ldd, const int32_t* pa, const int32_t* pb, int64_t P, double* Cp,
+                          Scalars* sc, Work w, int64_t fixed_cols, hipStream_t st);
+// out[p] = S[sel[pa[p]]] S[sel[pb[p]]] Cp[p] (S may be null)
+hipError_t launch_pair_out(const double* Cp, int64_t P, const int32_t* pa, const int32_t* pb, const double* S,
+                           const int64_t* sel, double* out, hipStream_t st);
 hipError_t launch_cov_out(const double* C, int64_t k, const double* S, const int64_t* sel, double* out,
                           hipStream_t st);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);

@@ -236,6 +236,64 @@ __global__ void __launch_bounds__(kBlock) k_syrk(const double* __restrict__ D, i
   }
 }
 
+// d_i[sel] = w_i[sel] / rho_i as column dcount of D ([nsel][dblock]).
+__global__ void __launch_bounds__(kBlock) k_cov_gather(int64_t nsel, const int64_t* __restrict__ sel,
+                                                       const double* __restrict__ w, double* __restrict__ D,
+                                                       Scalars* sc, Work wk) {
+  __shared__ int flag;
+  if (sc->done) return;
+  const int64_t cols = sc->dcount, ld = sc->dblock;
+  if (cols >= ld) return;
+  const double t3 = sc->t3;
+  for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < nsel; p += (int64_t)gridDim.x * kBlock)
+    D[p * ld + cols] = t3 * w[sel[p]];
+  if (last_block(wk.tickets + T_GATHER, &flag) && threadIdx.x == 0) {
+    sc->dcount = (int32_t)(cols + 1);
+    ticket_reset(wk.tickets + T_GATHER);
+  }
+}
+
+// Covariances for a list of pairs (version 2 of the covariance pipeline,
+// Sec. 2.2: (j1, j2) index pairs rather than a dense block):
+// Cp[p] += sum_{c < cols} D[a_p][c] D[b_p][c], 16 lanes per pair.
+__global__ void __launch_bounds__(kBlock) k_pairdot(const double* __restrict__ D, int64_t ldd,
+                                                    const int32_t* __restrict__ pa, const int32_t* __restrict__ pb,
+                                                    int64_t P, double* __restrict__ Cp, Scalars* sc, Work wk,
+                                                    int64_t fixed_cols) {
+  __shared__ int flag;
+  const int64_t cols = fixed_cols >= 0 ? fixed_cols : (int64_t)sc->dcount;
+  const int l = threadIdx.x & 15;
+  constexpr int kPerBlock = kBlock / 16;
+  if (cols > 0) {
+    for (int64_t p0 = (int64_t)blockIdx.x * kPerBlock; p0 < P; p0 += (int64_t)gridDim.x * kPerBlock) {
+      const int64_t p = p0 + threadIdx.x / 16;
+      double acc = 0.0;
+      if (p < P) {
+        const double* da = D + (int64_t)pa[p] * ldd;
+        const double* db = D + (int64_t)pb[p] * ldd;
+        for (int64_t c = l; c < cols; c += 16) acc += da[c] * db[c];
+      }
+#pragma unroll
+      for (int off = 8; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 16);
+      if (p < P && l == 0) Cp[p] += acc;
+    }
+  }
+  if (fixed_cols < 0) {
+    if (last_block(wk.tickets + T_SYRK, &flag) && threadIdx.x == 0) {
+      sc->dcount = 0;
+      ticket_reset(wk.tickets + T_SYRK);
+    }
+  }
+}
+
+// out[p] = s_{sel[a_p]} s_{sel[b_p]} Cp[p]
+__global__ void k_pair_out(const double* __restrict__ Cp, int64_t P, const int32_t* __restrict__ pa,
+                           const int32_t* __restrict__ pb, const double* __restrict__ S,
+                           const int64_t* __restrict__ sel, double* __restrict__ out) {
+  for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < P; p += (int64_t)gridDim.x * kBlock)
+    out[p] = (S ? S[sel[pa[p]]] * S[sel[pb[p]]] : 1.0) * Cp[p];
+}
+
 // out[p][q] = s_p s_q C[min(p,q)][max(p,q)], s = column scaling at the selected unknowns.
 __global__ void k_cov_out(const double* __restrict__ C, int64_t k, const double* __restrict__ S,
                           const int64_t* __restrict__ sel, double* __restrict__ out) {
@@ -323,6 +381,28 @@ hipError_t launch_syrk(const double* D, int64_t k, int64_t ldd, double* C, Scala
   const int64_t blocks = std::max<int64_t>(1, ntiles);
   hipLaunchKernelGGL(k_syrk, dim3((unsigned)blocks), dim3(kBlock), 0, st, D, k, ldd, C, sc, w, fixed_cols, T,
                      ntiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_cov_gather(int64_t nsel, const int64_t* sel, const double* w, double* D, Scalars* sc, Work wk,
+                             hipStream_t st) {
+  if (nsel <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cov_gather, dim3(blocks_for(nsel)), dim3(kBlock), 0, st, nsel, sel, w, D, sc, wk);
+  return hipGetLastError();
+}
+
+hipError_t launch_pairdot(const double* D, int64_t ldd, const int32_t* pa, const int32_t* pb, int64_t P, double* Cp,
+                          Scalars* sc, Work w, int64_t fixed_cols, hipStream_t st) {
+  const int64_t blocks = std::min<int64_t>(kMaxPartials, std::max<int64_t>(1, (P + kBlock / 16 - 1) / (kBlock / 16)));
+  hipLaunchKernelGGL(k_pairdot, dim3((unsigned)blocks), dim3(kBlock), 0, st, D, ldd, pa, pb, P, Cp, sc, w,
+                     fixed_cols);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_out(const double* Cp, int64_t P, const int32_t* pa, const int32_t* pb, const double* S,
+                           const int64_t* sel, double* out, hipStream_t st) {
+  if (P <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pair_out, dim3(blocks_for(P)), dim3(kBlock), 0, st, Cp, P, pa, pb, S, sel, out);
   return hipGetLastError();
 }
 

@@ -362,3 +362,39 @@ def test_cov_export_version1(dev, oracle_lib, tiny):
     finally:
         S.cov_export(None)
         S.cov_request([], block=64)
+
+
+def test_cov_pairs(dev, oracle_lib, tiny):
+    """Covariances of a pair list (version 2 of the covariance pipeline), in-run and from
+    an export, against the oracle's dense covariances of the pairs' indexes; (j, j)
+    pairs give the variances."""
+    print("[lsqr] covariance pair list", flush=True)
+    g, o, b, S = tiny
+    n, block, itmax = g.dims.n, 16, 40
+    rng = np.random.default_rng(23)
+    pairs = rng.integers(0, n, size=(500, 2))
+    pairs[:20, 1] = pairs[:20, 0]  # variances
+    pairs[20:30] = pairs[30:40]    # repeated pairs
+    U, inv = np.unique(pairs.reshape(-1), return_inverse=True)
+    inv = inv.reshape(-1, 2)
+    ref = oracle_lib.lsqr(o, b, atol=0, btol=0, itmax=itmax, precond=True, sel=U)
+    Cref = ref["cov"][inv[:, 0], inv[:, 1]]
+    host = torch.empty((4, block, n), dtype=torch.float64).pin_memory()
+    S.cov_export(host, block)
+    S.cov_request_pairs(pairs, block=block)
+    try:
+        x, var, r = S.lsqr_solve(torch.from_numpy(b).cuda(), atol=0, btol=0, itmax=itmax, precond=True)
+        assert r["itn"] == itmax
+        cp = S.cov_get_pairs().cpu().numpy()
+        nb, lc = S.cov_export_status()
+        cx = dev.cov_pairs_from_export(host, n, block, nb, lc, pairs, S=S.column_scale()).cpu().numpy()
+        v = var.cpu().numpy()
+        print(f"  in-run {_rel(cp, Cref):.2e}  from export {_rel(cx, Cref):.2e}", flush=True)
+        assert _rel(cp, Cref) <= 1e-10 and _rel(cx, Cref) <= 1e-10
+        assert _rel(cp[:20], v[pairs[:20, 0]]) <= 1e-12
+        np.testing.assert_array_equal(cp[20:30], cp[30:40])
+        with pytest.raises(dev.GsrError):
+            S.cov_get()  # a pair request has no dense block
+    finally:
+        S.cov_export(None)
+        S.cov_request_pairs([], block=64)
