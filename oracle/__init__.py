@@ -37,7 +37,8 @@ def build(force: bool = True) -> str:
 class _Sys(C.Structure):
     _fields_ = [("n_stars", C.c_int64), ("m", C.c_int64), ("n_att", C.c_int64), ("n_instr", C.c_int64),
                 ("n_glob", C.c_int32), ("f32", C.c_int32), ("vals", C.c_void_p),
-                ("star_row_ptr", C.c_void_p), ("att_start", C.c_void_p), ("instr_col", C.c_void_p)]
+                ("star_row_ptr", C.c_void_p), ("att_start", C.c_void_p), ("instr_col", C.c_void_p),
+                ("ncon", C.c_int64), ("con_ptr", C.c_void_p), ("con_col", C.c_void_p), ("con_val", C.c_void_p)]
 
 
 class _Opts(C.Structure):
@@ -62,6 +63,8 @@ def _L():
         vp, i64, i32, d = C.c_void_p, C.c_int64, C.c_int32, C.c_double
         lib.orc_n_unknowns.restype = i64
         lib.orc_n_unknowns.argtypes = [vp]
+        lib.orc_rows.restype = i64
+        lib.orc_rows.argtypes = [vp]
         lib.orc_col.restype = i64
         lib.orc_col.argtypes = [vp, i64, i64, C.c_int]
         lib.orc_aprod1.restype = None
@@ -87,9 +90,10 @@ def _p(a):
 
 
 class OSystem:
-    """Oracle view of a generated system (keeps the numpy arrays alive)."""
+    """Oracle view of a generated system (keeps the numpy arrays alive).
+    constraints: optional (con_ptr [ncon+1], con_col, con_val) CSR rows appended to A."""
 
-    def __init__(self, sysgen):
+    def __init__(self, sysgen, constraints=None):
         d = sysgen.dims
         self.dims = d
         self.vals = np.ascontiguousarray(sysgen.vals)
@@ -99,10 +103,19 @@ class OSystem:
         self.att_start = np.ascontiguousarray(sysgen.att_start, dtype=np.int32)
         self.instr_col = np.ascontiguousarray(sysgen.instr_col, dtype=np.int32)
         self.n = d.n
-        self.m = d.m
+        if constraints is None:
+            self.con = (np.zeros(1, np.int64), np.zeros(0, np.int64), np.zeros(0, np.float64))
+        else:
+            self.con = (np.ascontiguousarray(constraints[0], dtype=np.int64),
+                        np.ascontiguousarray(constraints[1], dtype=np.int64),
+                        np.ascontiguousarray(constraints[2], dtype=np.float64))
+        self.ncon = self.con[0].size - 1
+        self.m = d.m + self.ncon  # rows of [A; C]
         self._s = _Sys(d.n_stars, d.m, d.n_att, d.n_instr, d.n_glob, int(self.vals.dtype == np.float32),
-                       _p(self.vals), _p(self.star_row_ptr), _p(self.att_start), _p(self.instr_col))
+                       _p(self.vals), _p(self.star_row_ptr), _p(self.att_start), _p(self.instr_col),
+                       self.ncon, _p(self.con[0]), _p(self.con[1]), _p(self.con[2]))
         assert _L().orc_n_unknowns(C.byref(self._s)) == d.n
+        assert _L().orc_rows(C.byref(self._s)) == self.m
 
     @property
     def ref(self):
@@ -140,8 +153,10 @@ def colnorms(osys: OSystem):
 
 
 def known_terms(osys: OSystem, x_true, noise):
-    """b = A x_true + noise (the synthetic known terms)."""
-    return aprod1(osys, x_true, y=noise, scale=1.0)
+    """b = A x_true + noise (the synthetic known terms); with constraint rows the
+    consistent right-hand sides c = C x_true follow."""
+    y = np.concatenate([np.asarray(noise, dtype=np.float64), np.zeros(osys.ncon)])
+    return aprod1(osys, x_true, y=y, scale=1.0)
 
 
 def lsqr(osys: OSystem, b, x0=None, damp=0.0, atol=1e-12, btol=1e-12, conlim=0.0, itmax=200,

@@ -21,6 +21,11 @@
  *     17 <= k < 23 N_A + 3*n_att + instr_col[r][k-17]
  *     k = 23      N_A + 3*n_att + n_instr            (only when n_glob = 1)
  * with N_A = 5*n_stars.  Rows are sorted by star.
+ *
+ * Constraint equations (Sec. 2: a set of them makes the solution unique): ncon
+ * extra sparse rows after the m observation rows, row i holding the entries
+ * con_col[e], con_val[e] for e in [con_ptr[i], con_ptr[i+1]).  The system is
+ * then [A; C] x = [b; c], and every m-sized vector has m + ncon entries.
  */
 #include <math.h>
 #include <stdint.h>
@@ -35,6 +40,10 @@ typedef struct {
     const int64_t *star_row_ptr; /* [n_stars+1] */
     const int32_t *att_start;    /* [m] */
     const int32_t *instr_col;    /* [m][6] */
+    int64_t ncon;                /* constraint rows (0: none) */
+    const int64_t *con_ptr;      /* [ncon+1] */
+    const int64_t *con_col;      /* [con_ptr[ncon]] */
+    const double *con_val;       /* [con_ptr[ncon]] */
 } orc_sys;
 
 /* product modes */
@@ -47,6 +56,9 @@ int64_t orc_n_unknowns(const orc_sys *A)
 }
 
 static int n_slots(const orc_sys *A) { return A->n_glob ? 24 : 23; }
+
+/* Rows of [A; C]. */
+int64_t orc_rows(const orc_sys *A) { return A->m + A->ncon; }
 
 int64_t orc_col(const orc_sys *A, int64_t s, int64_t r, int k)
 {
@@ -105,6 +117,12 @@ void orc_aprod1(const orc_sys *A, const double *x, double *y, double scale_y, in
             y[r] = (scale_y == 0.0 ? 0.0 : scale_y * y[r]) + acc;
         }
     }
+    for (int64_t i = 0; i < A->ncon; ++i) {
+        double acc = 0.0;
+        for (int64_t e = A->con_ptr[i]; e < A->con_ptr[i + 1]; ++e)
+            acc += A->con_val[e] * x[A->con_col[e]];
+        y[A->m + i] = (scale_y == 0.0 ? 0.0 : scale_y * y[A->m + i]) + acc;
+    }
 }
 
 /* Eq. (3): x <- scale_x * x + A^T y.  Every column is accumulated over the
@@ -126,6 +144,9 @@ int orc_aprod2(const orc_sys *A, const double *y, double *x, double scale_x, int
                 int64_t c = orc_col(A, s, r, k);
                 comp_add(&sum[c], &cmp[c], product(A, r, k, y[r], mode));
             }
+    for (int64_t i = 0; i < A->ncon; ++i)
+        for (int64_t e = A->con_ptr[i]; e < A->con_ptr[i + 1]; ++e)
+            comp_add(&sum[A->con_col[e]], &cmp[A->con_col[e]], A->con_val[e] * y[A->m + i]);
     for (int64_t c = 0; c < n; ++c)
         x[c] = (scale_x == 0.0 ? 0.0 : scale_x * x[c]) + (sum[c] + cmp[c]);
     free(sum);
@@ -133,7 +154,7 @@ int orc_aprod2(const orc_sys *A, const double *y, double *x, double scale_x, int
     return 0;
 }
 
-/* Euclidean norm of every column of A (compensated sum of squares). */
+/* Euclidean norm of every column of [A; C] (compensated sum of squares). */
 int orc_colnorms(const orc_sys *A, double *norms)
 {
     int64_t n = orc_n_unknowns(A);
@@ -152,6 +173,9 @@ int orc_colnorms(const orc_sys *A, double *norms)
                 int64_t c = orc_col(A, s, r, k);
                 comp_add(&sum[c], &cmp[c], a * a);
             }
+    for (int64_t i = 0; i < A->ncon; ++i)
+        for (int64_t e = A->con_ptr[i]; e < A->con_ptr[i + 1]; ++e)
+            comp_add(&sum[A->con_col[e]], &cmp[A->con_col[e]], A->con_val[e] * A->con_val[e]);
     for (int64_t c = 0; c < n; ++c)
         norms[c] = sqrt(sum[c] + cmp[c]);
     free(sum);
@@ -186,7 +210,8 @@ typedef struct {
  * aprod 1 / aprod 2 / variances / covariance vectors, de-precondition.
  *
  * Solves min || [A S; damp I] y - [r0; 0] || with r0 = b - A x0 (x0 = 0 when
- * NULL) and returns x = x0 + S y.  S = diag(1/||a_j||) when precond is set
+ * NULL) and returns x = x0 + S y.  With constraint rows, A is [A; C] and b
+ * has m + ncon entries.  S = diag(1/||a_j||) when precond is set
  * (1 for an empty column), else I.
  *
  * var (nullable): sum_i (S d_i)^2 with d_i = w_i / rho_i, the variances
@@ -198,7 +223,7 @@ int orc_lsqr(const orc_sys *A, const double *b, const double *x0, double *x, dou
              const int64_t *sel, int64_t k, double *dsel, double *scale_out,
              const orc_opts *o, orc_result *res)
 {
-    int64_t m = A->m, n = orc_n_unknowns(A);
+    int64_t m = orc_rows(A), n = orc_n_unknowns(A);
     double *u = malloc((size_t)m * sizeof(double));
     double *v = malloc((size_t)n * sizeof(double));
     double *w = malloc((size_t)n * sizeof(double));
@@ -398,7 +423,7 @@ int orc_lsqr_refine(const orc_sys *A, const double *b, const double *x0, double 
                     const orc_opts *inner, int32_t outer_max, double outer_tol,
                     int64_t *inner_total, int32_t *outer_steps, orc_result *last)
 {
-    int64_t m = A->m, n = orc_n_unknowns(A);
+    int64_t m = orc_rows(A), n = orc_n_unknowns(A);
     double *r = malloc((size_t)m * sizeof(double));
     double *nx = malloc((size_t)n * sizeof(double));
     double *dx = malloc((size_t)n * sizeof(double));
