@@ -176,6 +176,22 @@ int gsr_lsqr_refine(gsr_system *sys, const double *b, const double *x0, double *
                     const gsr_lsqr_opts *inner, gsr_lsqr_result *res, gsr_stream stream);
 
 /*
+ * Constraint equations (Sec. 2: a set of them makes the solution unique):
+ * ncon sparse rows C under A, with right-hand sides c, so that the LSQR
+ * solves of this handle minimise ||[A; C] x - [b; c]||.  Host arrays, copied:
+ *   ptr [ncon+1] (ptr[0] = 0), col [ptr[ncon]] in [0, n) strictly increasing
+ *   within a row, val [ptr[ncon]], rhs [ncon].  ncon = 0 removes them.
+ * They enter the LSQR products, norms, variances and covariances and the
+ * column scaling (norms of the columns of [A; C]); gsr_aprod1 / gsr_aprod2
+ * keep computing with A alone.  Solves with constraints run the fused
+ * iteration (FP64 products; see gsr_set_fused) and gsr_lsqr_refine refuses
+ * them.  Rows may be long (e.g. a condition over every star): each is cut
+ * into tiles of 8192 entries reduced by one workgroup each.
+ */
+int gsr_set_constraints(gsr_system *sys, int64_t ncon, const int64_t *ptr, const int64_t *col, const double *val,
+                        const double *rhs);
+
+/*
  * Covariances of Eq. (4) for a selected set of unknowns, read as
  * C = S_sel (sum_i d_i[sel] d_i[sel]^T) S_sel with d_i = w_i / rho_i.
  * gsr_cov_request attaches the selection to the handle for the next solves:

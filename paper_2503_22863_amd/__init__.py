@@ -83,6 +83,7 @@ _SIGS = {
     "gsr_timing_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "gsr_set_graphs": (C.c_int, [C.c_void_p, C.c_int32]),
     "gsr_set_fused": (C.c_int, [C.c_void_p, C.c_int32]),
+    "gsr_set_constraints": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "gsr_cov_export": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32]),
     "gsr_cov_export_status": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "gsr_cov_from_export": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_int64, C.c_int32, C.c_void_p,
@@ -426,6 +427,18 @@ class System:
 
     def set_graphs(self, on=True):
         _check(lib().gsr_set_graphs(self._h, int(bool(on))))
+
+    def set_constraints(self, ptr=None, col=None, val=None, rhs=None):
+        """Constraint rows (CSR, host arrays) under A with right-hand sides rhs; no arguments removes them."""
+        if ptr is None:
+            _check(lib().gsr_set_constraints(self._h, 0, None, None, None, None))
+            return
+        ptr = np.ascontiguousarray(ptr, dtype=np.int64)
+        col = np.ascontiguousarray(col, dtype=np.int64)
+        val = np.ascontiguousarray(val, dtype=np.float64)
+        rhs = np.ascontiguousarray(rhs, dtype=np.float64)
+        _check(lib().gsr_set_constraints(self._h, ptr.size - 1, ptr.ctypes.data, col.ctypes.data if col.size else None,
+                                         val.ctypes.data if val.size else None, rhs.ctypes.data))
 
     def set_fused(self, on=True):
         _check(lib().gsr_set_fused(self._h, int(bool(on))))

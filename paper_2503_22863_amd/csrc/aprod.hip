@@ -419,6 +419,8 @@ __global__ void __launch_bounds__(kBlock) k_tail(SysView s, AttView av, int att_
           if (off < 0 || off >= win) continue;
           for (int32_t q = av.bsub[b]; q < av.bsub[b + 1]; ++q) a += av.Q[((int64_t)q * 3 + axs) * win + off];
         }
+        a += acc[j];  // constraint rows, if any
+        acc[j] = 0.0;
       } else {
         a = acc[j];
         acc[j] = 0.0;
@@ -545,10 +547,10 @@ hipError_t launch_tail(const SysView& s, const AttView& av, int att_mode, double
 }
 
 hipError_t launch_tail_fused(const SysView& s, const AttView& av, int att_mode, double* x, double* acc,
-                             const double* S, const double* gA, Scalars* sc, Work w, hipStream_t st) {
+                             const double* S, const double* gA, Scalars* sc, Work w, hipStream_t st, int lsqr_stage) {
   const int64_t cols = s.n_astro + s.tail_len;
   int blocks = (int)std::min<int64_t>(kMaxPartials, std::max<int64_t>(1, (cols + kBlock - 1) / kBlock));
-  TailLsqr L{1, 0, gA};
+  TailLsqr L{lsqr_stage, 0, gA};
   hipLaunchKernelGGL(k_tail, dim3(blocks), dim3(kBlock), 0, st, s, av, att_mode, x, acc, S, 0.0, sc, w, L);
   return hipGetLastError();
 }

@@ -78,6 +78,10 @@ struct gsr_system {
   double* D = nullptr;
   double* Cacc = nullptr;
   int cov_precond = 0;
+  // constraint equations (rows under A; the LSQR u vector has m + ncon entries)
+  ConView con{};
+  double* con_rhs = nullptr;   // [ncon]
+  double* zvec = nullptr;      // [n] zeros (the x of the constrained solve's first pass)
   // covariances for a pair list instead of a dense block (sel = the pairs' distinct unknowns)
   int64_t npairs = 0;
   int32_t *pa = nullptr, *pb = nullptr;  // positions in sel
@@ -178,6 +182,15 @@ static void reshape(gsr_system* s) { s->sh = stream_shape(s->s, s->cus, s->waves
 
 static int att_mode(const gsr_system* s) { return att_mode_of(s->s, s->av, s->att_atomics); }
 
+static void con_free(gsr_system* s) {
+  for (const void* p : {(const void*)s->con.ptr, (const void*)s->con.col, (const void*)s->con.val,
+                        (const void*)s->con.tile_e, (const void*)s->con.tile_r, (const void*)s->con.tmp,
+                        (const void*)s->con_rhs})
+    dfree(const_cast<void*>(p));
+  s->con = ConView{};
+  s->con_rhs = nullptr;
+}
+
 static void release(gsr_system* s) {
   (void)hipDeviceSynchronize();
   dfree(s->sc);
@@ -195,6 +208,8 @@ static void release(gsr_system* s) {
   dfree(s->y);
   dfree(s->var);
   dfree(s->gA);
+  con_free(s);
+  dfree(s->zvec);
   dfree(s->pa);
   dfree(s->pb);
   dfree(s->Cp);
@@ -272,13 +287,13 @@ extern "C" int gsr_create(gsr_system** out, const gsr_dims* d, const void* vals,
   };
   if ((rc = dalloc(&s->sc, 1)) || (rc = dalloc(&s->wk.part_a, kMaxPartials)) ||
       (rc = dalloc(&s->wk.part_b, kMaxPartials)) || (rc = dalloc(&s->wk.part_c, kMaxPartials)) ||
-      (rc = dalloc(&s->wk.tickets, 8)) || (rc = dalloc(&s->acc, (size_t)v.tail_len)))
+      (rc = dalloc(&s->wk.tickets, kTickets)) || (rc = dalloc(&s->acc, (size_t)v.tail_len)))
     return bail(rc);
   if (hipHostMalloc((void**)&s->sc_host, sizeof(Scalars), hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
     return bail(fail(GSR_ENOMEM, "pinned host allocation failed"));
   }
-  if (hipMemsetAsync(s->wk.tickets, 0, 8 * sizeof(unsigned), st) != hipSuccess ||
+  if (hipMemsetAsync(s->wk.tickets, 0, kTickets * sizeof(unsigned), st) != hipSuccess ||
       hipMemsetAsync(s->acc, 0, (size_t)v.tail_len * sizeof(double), st) != hipSuccess)
     return bail(fail(GSR_EHIP, "workspace clear failed"));
 
@@ -485,6 +500,7 @@ static int ensure_scale(gsr_system* s, hipStream_t st) {
   if (!s->S) CHK(dalloc(&s->S, (size_t)s->s.n));
   // column sums of squares with the aprod 2 machinery, then 1/sqrt
   CHK(aprod2_raw(s, nullptr, s->S, 0.0, 0, 1, st));
+  HIPCHK(launch_con_sq(s->con, s->S, st));  // columns of [A; C]
   HIPCHK(launch_scale_from_sq(s->s.n, s->S, st));
   s->S_valid = 1;
   return GSR_OK;
@@ -512,7 +528,7 @@ static int check_opts(const gsr_lsqr_opts* o) {
 
 static int ensure_vectors(gsr_system* s) {
   const size_t m = (size_t)s->s.m, n = (size_t)s->s.n;
-  if (!s->u) CHK(dalloc(&s->u, m));
+  if (!s->u) CHK(dalloc(&s->u, m + (size_t)s->con.ncon));
   if (!s->v) CHK(dalloc(&s->v, n));
   if (!s->vg) CHK(dalloc(&s->vg, n));
   if (!s->w) CHK(dalloc(&s->w, n));
@@ -525,10 +541,12 @@ static int ensure_vectors(gsr_system* s) {
 
 // Whether an iteration runs as one pass over the rows (plus the attitude and
 // tail passes) instead of separate aprod 1 and aprod 2 passes.
-static int iteration_fused(const gsr_system* s) {
+static int fused_for(const gsr_system* s, int32_t pmode) {
   const int mode = att_mode(s);
-  return s->fused && s->pmode == 0 && (mode == 0 || mode == 3) && s->rix != nullptr;
+  return s->fused && pmode == 0 && (mode == 0 || mode == 3) && s->rix != nullptr;
 }
+
+static int iteration_fused(const gsr_system* s) { return fused_for(s, s->pmode); }
 
 static int lsqr_begin(gsr_system* s, const double* b, const double* x0, const gsr_lsqr_opts* o, int32_t product,
                       hipStream_t st) {
@@ -536,6 +554,9 @@ static int lsqr_begin(gsr_system* s, const double* b, const double* x0, const gs
   CHK(check_product(s, product));
   if (s->s.m > 0) NEED_DEV(b, "b");
   if (x0) NEED_DEV(x0, "x0");
+  if (s->con.ncon > 0 && !fused_for(s, product))
+    return fail(GSR_EINVAL, "constraint equations need the fused iteration (FP64 products, fused on, "
+                            "attitude in LDS or bucketed)");
   CHK(ensure_vectors(s));
   if (o->precond) CHK(ensure_scale(s, st));
   s->precond = o->precond;
@@ -561,6 +582,7 @@ static int lsqr_begin(gsr_system* s, const double* b, const double* x0, const gs
   h.itmax = o->itmax;
   h.nsel = s->nsel;
   h.dblock = s->dblock;
+  h.u_scale = 1.0;  // the constrained solve's first pass forms u' = 1*u + A 0
   *s->sc_host = h;
   HIPCHK(hipMemcpyAsync(s->sc, s->sc_host, sizeof(Scalars), hipMemcpyHostToDevice, st));
   if (s->nsel > 0) {
@@ -570,13 +592,35 @@ static int lsqr_begin(gsr_system* s, const double* b, const double* x0, const gs
       HIPCHK(launch_fill(s->Cacc, s->nsel * s->nsel, 0.0, st));
     s->cov_precond = o->precond;
   }
-  // r0 = b - A x0
+  // r0 = [b; c] - [A; C] x0
   HIPCHK(launch_copy(b, s->u, s->s.m, st));
+  double* uc = s->u + s->s.m;  // constraint rows of u
+  if (s->con.ncon > 0) HIPCHK(launch_copy(s->con_rhs, uc, s->con.ncon, st));
   if (x0 && s->s.m > 0)
     HIPCHK(launch_aprod1(s->s, s->sh, x0, s->u, 1.0, -1.0, 0, nullptr, s->wk, 0, st));
-  HIPCHK(launch_norm_init(s->u, s->s.m, s->sc, s->wk, st));
-  // alpha_1 v_1 = S A^T u_1
-  CHK(aprod2_launches(s, s->u, s->v, S, 0.0, product, 0, s->sc, 0, st));
+  if (x0) HIPCHK(launch_con_aprod1(s->con, x0, uc, 1.0, -1.0, nullptr, s->wk, st));
+  if (s->con.ncon > 0) {
+    // beta_1 u_1 = r0 and alpha_1 v_1 = S [A; C]^T u_1 through the iteration's own
+    // passes, with x = 0 (u' = u) and the init steps of the scalar recurrences
+    const int mode = att_mode(s);
+    if (!s->zvec) {
+      CHK(dalloc(&s->zvec, (size_t)s->s.n));
+      HIPCHK(launch_fill(s->zvec, s->s.n, 0.0, st));
+    }
+    HIPCHK(launch_att_interleave(s->s, s->zvec, s->x3, st));
+    HIPCHK(launch_con_aprod1(s->con, s->zvec, uc, 0.0, 1.0, s->sc, s->wk, st));
+    HIPCHK(launch_fused(s->s, s->sh, mode, s->zvec, s->x3, s->rix, s->u, s->gA, s->acc, s->sc, s->wk, st, 1));
+    if (mode == 3) {
+      HIPCHK(launch_partition(s->s, s->av, s->u, s->sc, st));
+      HIPCHK(launch_att_pass(s->s, s->av, 1.0, 0, 0, s->sc, st, 1));
+    }
+    HIPCHK(launch_con_aprod2(s->con, s->s.n_astro, uc, s->gA, s->acc, s->sc, st));
+    HIPCHK(launch_tail_fused(s->s, s->av, mode, s->v, s->acc, S, s->gA, s->sc, s->wk, st, 0));
+  } else {
+    HIPCHK(launch_norm_init(s->u, s->s.m, s->sc, s->wk, st));
+    // alpha_1 v_1 = S A^T u_1
+    CHK(aprod2_launches(s, s->u, s->v, S, 0.0, product, 0, s->sc, 0, st));
+  }
   HIPCHK(launch_init_vectors(s->s.n, s->v, s->vg, s->w, s->y, s->var, S, s->sc, st));
   if (iteration_fused(s)) HIPCHK(launch_att_interleave(s->s, o->precond ? s->vg : s->v, s->x3, st));
   s->in_session = 1;
@@ -625,6 +669,11 @@ static int enqueue_iteration(gsr_system* s, hipStream_t st) {
   }
   if (iteration_fused(s)) {
     const int mode = att_mode(s);
+    double* uc = s->u + s->s.m;
+    if (s->con.ncon > 0) {
+      TimeScope ts(s, 2, st);
+      HIPCHK(launch_con_aprod1(s->con, vg, uc, 0.0, 1.0, s->sc, s->wk, st));
+    }
     {
       TimeScope ts(s, 0, st);
       HIPCHK(launch_fused(s->s, s->sh, mode, vg, s->x3, s->rix, s->u, s->gA, s->acc, s->sc, s->wk, st));
@@ -633,6 +682,10 @@ static int enqueue_iteration(gsr_system* s, hipStream_t st) {
       TimeScope ts(s, 1, st);
       HIPCHK(launch_partition(s->s, s->av, s->u, s->sc, st));
       HIPCHK(launch_att_pass(s->s, s->av, 1.0, 0, 0, s->sc, st, 1));
+    }
+    if (s->con.ncon > 0) {
+      TimeScope ts(s, 2, st);
+      HIPCHK(launch_con_aprod2(s->con, s->s.n_astro, uc, s->gA, s->acc, s->sc, st));
     }
     {
       TimeScope ts(s, 2, st);
@@ -827,6 +880,7 @@ extern "C" int gsr_lsqr_refine(gsr_system* s, const double* b, const double* x0,
   CHK(check_handle(s));
   CHK(check_opts(o));
   if (s->s.value_type != GSR_F32) return fail(GSR_EINVAL, "gsr_lsqr_refine needs an FP32 system");
+  if (s->con.ncon > 0) return fail(GSR_EINVAL, "gsr_lsqr_refine does not take constraint equations");
   if (o->outer_max < 1 || !(o->outer_tol >= 0)) return fail(GSR_EINVAL, "outer_max >= 1, outer_tol >= 0");
   NEED_DEV(x, "x");
   if (s->s.m > 0) NEED_DEV(b, "b");
@@ -919,6 +973,75 @@ static int pair_index(const int64_t* pairs, int64_t P, int64_t n, std::vector<in
     (*a)[(size_t)p] = (int32_t)(std::lower_bound(U->begin(), U->end(), pairs[2 * p]) - U->begin());
     (*b)[(size_t)p] = (int32_t)(std::lower_bound(U->begin(), U->end(), pairs[2 * p + 1]) - U->begin());
   }
+  return GSR_OK;
+}
+
+extern "C" int gsr_set_constraints(gsr_system* s, int64_t ncon, const int64_t* ptr, const int64_t* col,
+                                   const double* val, const double* rhs) {
+  CHK(check_handle(s));
+  if (s->in_session) return fail(GSR_ESTATE, "gsr_set_constraints: a solve is in progress");
+  if (ncon < 0) return fail(GSR_EINVAL, "ncon < 0");
+  if (ncon > 0 && (!ptr || !rhs)) return fail(GSR_EINVAL, "ptr and rhs are needed");
+  if (ncon > 0 && (is_device_ptr(ptr) || is_device_ptr(rhs) || (col && is_device_ptr(col)) ||
+                   (val && is_device_ptr(val))))
+    return fail(GSR_EINVAL, "constraint arrays are host memory");
+  const int64_t nnz = ncon > 0 ? ptr[ncon] : 0;
+  if (ncon > 0) {
+    if (ptr[0] != 0) return fail(GSR_EINVAL, "ptr[0] must be 0");
+    if (nnz > 0 && (!col || !val)) return fail(GSR_EINVAL, "col and val are needed");
+    for (int64_t i = 0; i < ncon; ++i) {
+      if (ptr[i + 1] < ptr[i]) return fail(GSR_EINVAL, "ptr decreases at row %lld", (long long)i);
+      for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) {
+        if (col[e] < 0 || col[e] >= s->s.n) return fail(GSR_EINVAL, "col[%lld] out of range", (long long)e);
+        if (e > ptr[i] && col[e] <= col[e - 1])
+          return fail(GSR_EINVAL, "the columns of constraint row %lld must be strictly increasing", (long long)i);
+      }
+    }
+  }
+  (void)hipDeviceSynchronize();
+  drop_graph(s);
+  con_free(s);
+  dfree(s->u);  // its length is m + ncon
+  s->u = nullptr;
+  s->S_valid = 0;  // the column norms are those of [A; C]
+  if (ncon == 0) return GSR_OK;
+  // tiles of at most kConTile entries of one row
+  std::vector<int64_t> te, tr;
+  for (int64_t i = 0; i < ncon; ++i)
+    for (int64_t e = ptr[i]; e < ptr[i + 1]; e += kConTile) {
+      te.push_back(e);
+      tr.push_back(i);
+    }
+  const int64_t nt = (int64_t)tr.size();
+  te.push_back(nnz);
+  int64_t *dp = nullptr, *dc = nullptr, *dte = nullptr, *dtr = nullptr;
+  double *dv = nullptr, *dtmp = nullptr, *drhs = nullptr;
+  int rc = GSR_OK;
+  if ((rc = dalloc(&dp, (size_t)ncon + 1)) || (rc = dalloc(&dc, (size_t)std::max<int64_t>(nnz, 1))) ||
+      (rc = dalloc(&dv, (size_t)std::max<int64_t>(nnz, 1))) || (rc = dalloc(&dte, (size_t)nt + 1)) ||
+      (rc = dalloc(&dtr, (size_t)std::max<int64_t>(nt, 1))) || (rc = dalloc(&dtmp, (size_t)ncon)) ||
+      (rc = dalloc(&drhs, (size_t)ncon))) {
+    for (void* p : {(void*)dp, (void*)dc, (void*)dv, (void*)dte, (void*)dtr, (void*)dtmp, (void*)drhs}) dfree(p);
+    return rc;
+  }
+  s->con.ncon = ncon;
+  s->con.ptr = dp;
+  s->con.col = dc;
+  s->con.val = dv;
+  s->con.ntiles = nt;
+  s->con.tile_e = dte;
+  s->con.tile_r = dtr;
+  s->con.tmp = dtmp;
+  s->con_rhs = drhs;
+  HIPCHK(hipMemcpy(dp, ptr, sizeof(int64_t) * ((size_t)ncon + 1), hipMemcpyHostToDevice));
+  if (nnz > 0) {
+    HIPCHK(hipMemcpy(dc, col, sizeof(int64_t) * (size_t)nnz, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dv, val, sizeof(double) * (size_t)nnz, hipMemcpyHostToDevice));
+  }
+  HIPCHK(hipMemcpy(dte, te.data(), sizeof(int64_t) * te.size(), hipMemcpyHostToDevice));
+  if (nt > 0) HIPCHK(hipMemcpy(dtr, tr.data(), sizeof(int64_t) * (size_t)nt, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(drhs, rhs, sizeof(double) * (size_t)ncon, hipMemcpyHostToDevice));
+  HIPCHK(hipMemset(dtmp, 0, sizeof(double) * (size_t)ncon));
   return GSR_OK;
 }
 

@@ -57,7 +57,7 @@ template <typename VT, int ATT_MODE>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) k_fused(SysView s, int waves, const double* __restrict__ x,
                                                   const double* __restrict__ x3, const u4* __restrict__ rix,
                                                   double* __restrict__ u, double* __restrict__ gA,
-                                                  double* __restrict__ acc, Scalars* sc, Work wk) {
+                                                  double* __restrict__ acc, Scalars* sc, Work wk, int init) {
   constexpr int CPR = Geo<VT>::CPR;
   __shared__ u4 slabs[kWavesPerBlock][kWave * (CPR + 1)];
   __shared__ int64_t bnds[kWavesPerBlock][kWave];
@@ -256,14 +256,15 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
   if (last_block(wk.tickets + T_APROD1, &flag)) {
     const double tot = sum_partials(wk.part_a, gridDim.x, red);
     if (threadIdx.x == 0) {
-      epi_beta(sc, tot, 0);
+      epi_beta(sc, tot + sc->con_sumsq, init);
       ticket_reset(wk.tickets + T_APROD1);
     }
   }
 }
 
 hipError_t launch_fused(const SysView& s, StreamShape sh, int att_mode, const double* vg, const double* x3,
-                        const void* rix, double* u, double* gA, double* acc, Scalars* sc, Work w, hipStream_t st) {
+                        const void* rix, double* u, double* gA, double* acc, Scalars* sc, Work w, hipStream_t st,
+                        int init) {
   if ((att_mode != 0 && att_mode != 3) || !rix || s.n_instr + 1 > kLdsTailMax) return hipErrorInvalidValue;
   const int64_t hlen = att_mode == 0 ? s.tail_len : s.tail_len - 3 * s.n_att;
   const size_t lds = sizeof(double) * (size_t)(hlen + s.n_instr);
@@ -271,14 +272,14 @@ hipError_t launch_fused(const SysView& s, StreamShape sh, int att_mode, const do
   const u4* rx = reinterpret_cast<const u4*>(rix);
   if (s.value_type == GSR_F32) {
     if (att_mode == 0)
-      hipLaunchKernelGGL((k_fused<float, 0>), g, b, lds, st, s, sh.waves, vg, x3, rx, u, gA, acc, sc, w);
+      hipLaunchKernelGGL((k_fused<float, 0>), g, b, lds, st, s, sh.waves, vg, x3, rx, u, gA, acc, sc, w, init);
     else
-      hipLaunchKernelGGL((k_fused<float, 3>), g, b, lds, st, s, sh.waves, vg, x3, rx, u, gA, acc, sc, w);
+      hipLaunchKernelGGL((k_fused<float, 3>), g, b, lds, st, s, sh.waves, vg, x3, rx, u, gA, acc, sc, w, init);
   } else {
     if (att_mode == 0)
-      hipLaunchKernelGGL((k_fused<double, 0>), g, b, lds, st, s, sh.waves, vg, x3, rx, u, gA, acc, sc, w);
+      hipLaunchKernelGGL((k_fused<double, 0>), g, b, lds, st, s, sh.waves, vg, x3, rx, u, gA, acc, sc, w, init);
     else
-      hipLaunchKernelGGL((k_fused<double, 3>), g, b, lds, st, s, sh.waves, vg, x3, rx, u, gA, acc, sc, w);
+      hipLaunchKernelGGL((k_fused<double, 3>), g, b, lds, st, s, sh.waves, vg, x3, rx, u, gA, acc, sc, w, init);
   }
   return hipGetLastError();
 }

@@ -34,6 +34,7 @@ struct Scalars {
   double anorm2, ddnorm, res2, xnorm, rnorm, arnorm, acond, bnorm;
   // options
   double damp, atol, btol, ctol;
+  double con_sumsq;          // sum of squares of the constraint rows of u (added to beta^2)
   int64_t itn, itmax;
   int32_t istop;             // Paige-Saunders stop code
   int32_t done;              // 1 once the solve has stopped (any reason)
@@ -51,7 +52,11 @@ struct Work {
   unsigned* tickets;         // [8] last-workgroup tickets, one per kernel kind
 };
 
-enum Ticket { T_APROD1 = 0, T_APROD2 = 1, T_TAIL = 2, T_UPDATE = 3, T_INIT = 4, T_SYRK = 5, T_VALID = 6, T_GATHER = 7 };
+enum Ticket {
+  T_APROD1 = 0, T_APROD2 = 1, T_TAIL = 2, T_UPDATE = 3, T_INIT = 4, T_SYRK = 5, T_VALID = 6, T_GATHER = 7,
+  T_CON = 8,
+  kTickets = 16
+};
 
 // A borrowed view of the caller's system arrays plus the sizes derived from them.
 struct SysView {
@@ -133,9 +138,34 @@ hipError_t launch_att_pass(const SysView& s, const AttView& av, double inv_beta,
 // rows, the astrometric, instrumental and global parts of A^T u on the
 // unnormalised u (astrometric sums to gA, the others into acc; mode 0 also
 // the attitude part).
+// Constraint equations: ncon sparse rows C (CSR, entries sorted by row) under A.
+// Work is split into tiles of at most kConTile entries of one row.
+struct ConView {
+  int64_t ncon;
+  const int64_t* ptr;     // [ncon+1]
+  const int64_t* col;     // [nnz]
+  const double* val;      // [nnz]
+  int64_t ntiles;
+  const int64_t* tile_e;  // [ntiles+1] first entry of each tile
+  const int64_t* tile_r;  // [ntiles] row of each tile
+  double* tmp;            // [ncon] row sums (zero between uses)
+};
+constexpr int64_t kConTile = 8192;
+// y_C <- scale*y_C + ax*C x (sc != null: scale = sc->u_scale, skipped once done, and the
+// last workgroup stores sum(y_C^2) in sc->con_sumsq)
+hipError_t launch_con_aprod1(const ConView& c, const double* x, double* yc, double scale, double ax, Scalars* sc,
+                             Work w, hipStream_t st);
+// raw[j] += sum_i C_ij yc_i into gA (j < n_astro) or acc (j - n_astro), as the fused row pass does
+hipError_t launch_con_aprod2(const ConView& c, int64_t n_astro, const double* yc, double* gA, double* acc,
+                             Scalars* sc, hipStream_t st);
+// sq[j] += sum_i C_ij^2 (column norms of [A; C])
+hipError_t launch_con_sq(const ConView& c, double* sq, hipStream_t st);
+
 // rix: packed row indices from launch_pack_rows (required).
+// init = 1: the solve's first pass (u_scale = 1 and vg = 0 give u' = u; beta_1 with its init step)
 hipError_t launch_fused(const SysView& s, StreamShape sh, int att_mode, const double* vg, const double* x3,
-                        const void* rix, double* u, double* gA, double* acc, Scalars* sc, Work w, hipStream_t st);
+                        const void* rix, double* u, double* gA, double* acc, Scalars* sc, Work w, hipStream_t st,
+                        int init = 0);
 // rix[r] <- {att_start[r], instr_col[r][0..5] as 16-bit pairs} (16 bytes per row; needs n_instr <= 65536)
 hipError_t launch_pack_rows(const SysView& s, void* rix, hipStream_t st);
 // x3 <- attitude part of x with the three axes interleaved (the fused pass's copy of vg)
@@ -143,7 +173,8 @@ hipError_t launch_att_interleave(const SysView& s, const double* x, double* x3, 
 // Tail of the fused iteration: every column x_j <- v_scale*x_j + S_j * raw_j / beta (raw_j from gA, acc
 // or the attitude windows), then alpha_{i+1} and the rotations, as launch_tail.
 hipError_t launch_tail_fused(const SysView& s, const AttView& av, int att_mode, double* x, double* acc,
-                             const double* S, const double* gA, Scalars* sc, Work w, hipStream_t st);
+                             const double* S, const double* gA, Scalars* sc, Work w, hipStream_t st,
+                             int lsqr_stage = 1);
 // Covariance column of the iteration: D[p][dcount] = w[sel[p]] / rho_i for p < nsel (after the tail);
 // the last workgroup advances dcount.  Skipped once the solve has stopped or the block is full.
 hipError_t launch_cov_gather(int64_t nsel, const int64_t* sel, const double* w, double* D, Scalars* sc, Work wk,
