@@ -252,6 +252,9 @@ def main():
                          "then form covariances of --cov unknowns from the export")
     ap.add_argument("--pairs", type=int, default=0,
                     help="covariances of this many random index pairs (blocks of 64 iterations) during the run")
+    ap.add_argument("--constraints", action="store_true",
+                    help="add 6 constraint equations: the sums over all stars of astrometric unknowns 0-2 and "
+                         "the sums over each attitude axis")
     ap.add_argument("--syrk-bench", action="store_true",
                     help="time the covariance SYRK alone (k = 4000) and print its MFMA rate instead")
     args = ap.parse_args()
@@ -293,6 +296,15 @@ def main():
     if args.pairs > 0:
         rngp = np.random.default_rng(29)
         S.cov_request_pairs(rngp.integers(0, g.dims.n, size=(args.pairs, 2)), block=64)
+    if args.constraints:
+        d = g.dims
+        rows = [np.arange(k, d.n_astro, 5) for k in range(3)]
+        rows += [d.n_astro + a * d.n_att + np.arange(d.n_att) for a in range(3)]
+        ptr = np.cumsum([0] + [r.size for r in rows]).astype(np.int64)
+        col = np.concatenate(rows).astype(np.int64)
+        val = np.concatenate([np.full(r.size, np.sqrt(24.0 / r.size)) for r in rows])
+        rhs = np.array([val[ptr[i]:ptr[i + 1]] @ g.x_true[col[ptr[i]:ptr[i + 1]]] for i in range(6)])
+        S.set_constraints(ptr, col, val, rhs)
     dims = g.dims
     sel = None
     if args.cov > 0:
@@ -361,7 +373,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{workload}: {ns} stars x U[50,90] obs (m={m}), 3x{dims.n_att} attitude, "
                                f"{dims.n_instr} instr, {dims.n_glob} global (n={n}); unscaled FP64 LSQR, damp 0, "
-                               f"variances on" + (f", covariances of {args.cov} unknowns" if args.cov else ""),
+                               f"variances on" + (f", covariances of {args.cov} unknowns" if args.cov else "")
+                               + (", 6 constraint equations" if args.constraints else ""),
                    "global_batch": m, "seq_len": None, "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
