@@ -157,7 +157,8 @@ int gsr_lsqr_solve(gsr_system *sys, const double *b, const double *x0, double *x
  * (asynchronous; iterations after a stop are no-ops), status (synchronises
  * and reads the scalars), peek (current x = x0 + S y into device [n]),
  * end (flush covariances, write x / var, read the result; synchronous).
- * b and x0 must stay valid until end. */
+ * b and x0 must stay valid until end.  A begin while a solve is in progress
+ * drops that solve and starts a new one. */
 int gsr_lsqr_begin(gsr_system *sys, const double *b, const double *x0, const gsr_lsqr_opts *opts,
                    gsr_stream stream);
 int gsr_lsqr_iterate(gsr_system *sys, int64_t n_iter, gsr_stream stream);

@@ -1,7 +1,8 @@
 // C-ABI layer of libgsr: handles, argument checks, workspace management and
 // the host side of the device-resident LSQR driver.  All arithmetic of the
-// method runs in the kernels (aprod.hip, lsqr.hip, mlp.hip); this file only
-// validates, allocates and enqueues.
+// method runs in the kernels (aprod.hip, fused.hip, attitude.hip,
+// constraints.hip, lsqr.hip, mlp.hip); this file only validates, allocates
+// and enqueues.
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
