@@ -30,11 +30,28 @@ HBM_PEAK_GBS = 8000.0
 # column sums written.
 FUSED_B_ROW = 192 + 4 + 24 + 8 + 8
 FUSED_B_STAR = 40 + 40
+# the same with FP32 values (the FP32 forms)
+FUSED_B_ROW_F32 = 96 + 4 + 24 + 8 + 8
+# The pass over the copy regrouped by attitude window: per row the 24 coefficients,
+# the 16-byte row record, u read and u written; per star segment the star's 5 v read
+# and the 5 partial sums written; per workgroup its attitude window of sums written.
+FBLK_B_ROW = 192 + 16 + 8 + 8
+FBLK_B_ROW_F32 = 96 + 16 + 8 + 8
+FBLK_B_SEG = 40 + 40
+
+
+def pass_bytes(info, m, ns, f32=False):
+    """(kernel, algorithmic bytes per launch) of the iteration's row pass."""
+    if info and info.get("active"):
+        by = (FBLK_B_ROW_F32 if f32 else FBLK_B_ROW) * m + FBLK_B_SEG * info["segments"] + \
+            24 * (info["window"] + 3) * info["workgroups"]
+        return "k_fblk", by
+    return "k_fused", (FUSED_B_ROW_F32 if f32 else FUSED_B_ROW) * m + FUSED_B_STAR * ns
 
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("fused.hip", "row_tiles.h", "device_common.h", "internal.h"):
+    for f in ("fused.hip", "blocked.hip", "row_tiles.h", "device_common.h", "internal.h"):
         with open(os.path.join(ROOT, "paper_2503_22863_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -114,9 +131,34 @@ def _iters_to(S, b, x_ref, tol, cap, x0=None, **opts):
     return None
 
 
-def time_to_tolerance_fp32(gsr, g, tol=1e-10, label=""):
-    """FP64 LSQR vs FP32 storage + FP64 refinement on the same FP32-representable matrix.
-    Reference: the FP64 solve converged to atol = btol = 1e-14."""
+def _pass_rates(S, b, product, m, ns, f32, iters=10):
+    """Average row pass and second pass (bucketed attitude sums, or the segment
+    reduction of the regrouped pass) times (HIP events) over `iters` iterations of a
+    column-scaled solve with the given product mode, and the row pass's algorithmic
+    GB/s."""
+    import torch
+
+    S.lsqr_begin(b, atol=0.0, btol=0.0, itmax=iters + 3, precond=True, product=product)
+    S.lsqr_iterate(2)
+    S.timing_enable(True)
+    S.timing_get()
+    S.lsqr_iterate(iters)
+    torch.cuda.synchronize()
+    tm = S.timing_get()
+    S.timing_enable(False)
+    S.lsqr_end(want_var=False)
+    f_ms = tm["aprod1_ms"] / max(1, tm["aprod1_n"])
+    kname, by = pass_bytes(S.blocked_info(), m, ns, f32)
+    return {"row_pass": kname, "row_pass_ms": f_ms, "second_pass_ms": tm["aprod2_ms"] / max(1, tm["aprod2_n"]),
+            "row_pass_bytes": by, "row_pass_GBps": by / (f_ms * 1e-3) / 1e9}
+
+
+def time_to_tolerance_fp32(gsr, g, tol=1e-10, label="", inner_tol=1e-5):
+    """FP64 LSQR vs the FP32 forms on the same FP32-representable matrix: FP32 products
+    with FP64 iterative refinement (inner atol = btol = inner_tol, outer_tol 1e-11), and
+    FP32 storage with FP64 products.  Reference: the FP64 solve converged to
+    atol = btol = 1e-14; the FP64 and storage-only counts are the fewest iterations
+    that reach `tol` of it."""
     import numpy as np
     import torch
 
@@ -131,7 +173,7 @@ def time_to_tolerance_fp32(gsr, g, tol=1e-10, label=""):
     x_ref, _, rref = S64.lsqr_solve(b, atol=1e-14, btol=1e-14, itmax=5000, precond=True, want_var=False)
     n64 = _iters_to(S64, b, x_ref, tol, 2000, precond=True)
     t64 = _median_time(lambda: S64.lsqr_solve(b, atol=0, btol=0, itmax=n64, precond=True, want_var=False))
-    ropts = dict(atol=1e-6, btol=1e-6, itmax=2000, precond=True, outer_max=10, outer_tol=1e-11)
+    ropts = dict(atol=inner_tol, btol=inner_tol, itmax=2000, precond=True, outer_max=10, outer_tol=1e-11)
     xr, rr = S32.lsqr_refine(b, **ropts)
     err32 = _rel(xr, x_ref)
     t32 = _median_time(lambda: S32.lsqr_refine(b, **ropts))
@@ -139,13 +181,18 @@ def time_to_tolerance_fp32(gsr, g, tol=1e-10, label=""):
     nb = _iters_to(S32, b, x_ref, tol, 2000, precond=True, product="f64")
     tb = _median_time(lambda: S32.lsqr_solve(b, atol=0, btol=0, itmax=nb, precond=True, want_var=False,
                                              product="f64"))
+    m, ns = g.dims.m, g.dims.n_stars
+    rates = {"fp64": _pass_rates(S64, b, "f64", m, ns, False),
+             "fp32_products": _pass_rates(S32, b, "f32", m, ns, True),
+             "fp32_storage_fp64_products": _pass_rates(S32, b, "f64", m, ns, True)}
     S64.close()
     S32.close()
     return {"workload": label, "tol": tol, "fp64": {"iterations": n64, "seconds": t64},
-            "fp32_refine": {"outer": rr["outer_steps"], "inner_total": rr["inner_total"], "seconds": t32,
-                            "rel_err_vs_fp64": err32},
+            "fp32_refine": {"inner_tol": inner_tol, "outer": rr["outer_steps"], "inner_total": rr["inner_total"],
+                            "seconds": t32, "rel_err_vs_fp64": err32},
             "speedup": t64 / t32,
-            "fp32_storage_fp64_products": {"iterations": nb, "seconds": tb, "speedup": t64 / tb}}
+            "fp32_storage_fp64_products": {"iterations": nb, "seconds": tb, "speedup": t64 / tb},
+            "per_iteration": rates}
 
 
 def time_to_tolerance_warm(gsr, tol=1e-10, train_steps=1500):
@@ -255,6 +302,9 @@ def main():
     ap.add_argument("--constraints", action="store_true",
                     help="add 6 constraint equations: the sums over all stars of astrometric unknowns 0-2 and "
                          "the sums over each attitude axis")
+    ap.add_argument("--star-order", action="store_true",
+                    help="iterate on the rows in star order (bucketed attitude pass) instead of the copy "
+                         "regrouped by attitude window")
     ap.add_argument("--syrk-bench", action="store_true",
                     help="time the covariance SYRK alone (k = 4000) and print its MFMA rate instead")
     args = ap.parse_args()
@@ -289,6 +339,7 @@ def main():
     m, n, ns = g.dims.m, g.dims.n, g.dims.n_stars
     print(f"# generated m={m} n={n} in {time.time() - t:.1f}s", file=sys.stderr, flush=True)
     S = gsr.System.from_generated(g)
+    S.set_blocked(not args.star_order)
     if args.cov > 0:
         nst = (args.cov * 3 // 5) // 5
         S.cov_request(gsr_synth.covariance_selection(g.dims, nst, args.cov * 3 // 10 // 3, args.cov - 5 * nst
@@ -317,6 +368,7 @@ def main():
         S.cov_export(ehost, args.export)
     xt = torch.from_numpy(g.x_true).cuda()
     b = torch.from_numpy(g.noise).cuda()
+    g_share = None if args.no_ttt else g  # the FP32 forms are timed on the same system
     del g
     S.aprod1(xt, b, scale=1.0)  # b = A x_true + noise
     torch.cuda.synchronize()
@@ -350,11 +402,12 @@ def main():
     else:
         S.lsqr_end(want_var=False)
 
-    # timing scopes of an iteration: the fused row pass, the attitude passes
-    # (partition of u and the bucketed sums), the tail, the x / w / var update
+    # timing scopes of an iteration: the row pass, the second pass (segment
+    # reduction of the regrouped pass, or partition of u and the bucketed
+    # attitude sums), the tail, the x / w / var update
     f_ms = tm["aprod1_ms"] / max(1, tm["aprod1_n"])
     att_ms = tm["aprod2_ms"] / max(1, tm["aprod2_n"])
-    kname, by = "k_fused", FUSED_B_ROW * m + FUSED_B_STAR * ns
+    kname, by = pass_bytes(S.blocked_info(), m, ns)
     achieved = by / (f_ms * 1e-3) / 1e9
     workload = args.workload
     traffic = load_traffic(kname, workload)
@@ -379,9 +432,10 @@ def main():
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_launch": by, "avg_ms": f_ms},
-        "iteration_ms": {"fused_row_pass": f_ms, "attitude_passes": att_ms,
+        "iteration_ms": {"row_pass": f_ms, "second_pass": att_ms,
                          "tail": tm["tail_ms"] / max(1, tm["tail_n"]),
                          "update": tm["update_ms"] / max(1, tm["update_n"])},
+        "row_layout": S.blocked_info() if kname == "k_fblk" else "star order",
     }
     if args.export > 0:
         nb, lc = S.cov_export_status()
@@ -408,9 +462,8 @@ def main():
         import gsr_synth as _gs
 
         out["time_to_1e-10"] = {
-            "fp32_refine_tiny": time_to_tolerance_fp32(gsr, _gs.tiny(), label="tiny: 1,000 stars x 20 rows"),
-            "fp32_refine_share": time_to_tolerance_fp32(
-                gsr, _gs.share_1m(n_stars=args.stars // 4), label=f"{args.stars // 4} stars x U[50,90] rows"),
+            "fp32_forms_tiny": time_to_tolerance_fp32(gsr, _gs.tiny(), label="tiny: 1,000 stars x 20 rows"),
+            "fp32_forms_share": time_to_tolerance_fp32(gsr, g_share, label=f"{workload}: {ns} stars x U[50,90] rows"),
             "warm_start": time_to_tolerance_warm(gsr),
         }
     if not args.no_cpu:

@@ -125,7 +125,9 @@ typedef struct {
     int32_t precond;  /* 1: column scaling S = diag(1/||a_j||); 0: S = I */
     int32_t product;  /* GSR_PROD_F64 or GSR_PROD_F32 (FP32 systems) for the iteration products */
     int32_t outer_max;  /* gsr_lsqr_refine only: maximum outer steps (>= 1) */
-    double outer_tol;   /* gsr_lsqr_refine only: stop when ||dx|| <= outer_tol ||x|| */
+    double outer_tol;   /* gsr_lsqr_refine only: stop when ||dx|| <= outer_tol ||x||, or when
+                           the next correction predicted from the last two,
+                           ||dx_k||^2 / ||dx_k-1||, is at most outer_tol ||x|| */
 } gsr_lsqr_opts;
 
 typedef struct {
@@ -171,7 +173,9 @@ int gsr_lsqr_end(gsr_system *sys, double *x, double *var, gsr_lsqr_result *res, 
  * forms r = b - A x with FP64 products on the FP32 coefficients (exact
  * upcast), solves A dx ~ r with LSQR using `inner` (normally
  * product = GSR_PROD_F32 and loose atol/btol), and updates x += dx, until
- * ||dx|| <= outer_tol ||x|| or outer_max steps.  Arguments as gsr_lsqr_solve.
+ * the correction, or the next one predicted from the contraction between the
+ * last two, is at most outer_tol ||x||, or outer_max steps.  Arguments as
+ * gsr_lsqr_solve.
  */
 int gsr_lsqr_refine(gsr_system *sys, const double *b, const double *x0, double *x,
                     const gsr_lsqr_opts *inner, gsr_lsqr_result *res, gsr_stream stream);
@@ -283,11 +287,37 @@ int gsr_set_graphs(gsr_system *sys, int32_t on);
  * needs A v_i - alpha_i u_i and then A^T u_{i+1} (Sec. 2, Eq. 2 and Eq. 3);
  * with u kept unnormalised, A^T u_{i+1} = A^T(beta_{i+1} u_{i+1}) / beta_{i+1},
  * so both products read each row once and 1/beta_{i+1} is applied
- * afterwards.  Used with FP64 products when the attitude columns are summed
- * in LDS or by the bucketed pass; off, or otherwise, an iteration runs
- * gsr_aprod1 and gsr_aprod2 as separate passes.  Results agree up to the
- * rounding of the 1/beta scaling. */
+ * afterwards.  Used when the attitude columns are summed in LDS, by the
+ * regrouped copy (gsr_set_blocked) or by the bucketed pass; off, or
+ * otherwise, an iteration runs gsr_aprod1 and gsr_aprod2 as separate passes.
+ * Results agree up to the rounding of the 1/beta scaling (with FP32
+ * products: the FP32 operand of A^T u is the unnormalised u). */
 int gsr_set_fused(gsr_system *sys, int32_t on);
+
+/* Rows regrouped by attitude window (on by default; used by fused solves
+ * without constraint equations when the attitude block does not fit in LDS).
+ * At the first such solve the handle makes a device copy of the rows grouped
+ * by block g = att_start / Wb, star order inside a block, padded to 64-row
+ * tiles, with Wb the widest window whose 3 x (Wb + 3) sums fit in LDS (at
+ * most 4096 starts; max_window > 0 caps it, >= 4).  Each iteration is then
+ * one pass over that copy: A v, the attitude sums in the LDS window, and the
+ * star sums as per-segment partials added by the tail.  The copy takes about
+ * the bytes of A plus 28 bytes per row and is kept until gsr_destroy or a
+ * change of max_window.  Without memory for it, solves use the bucketed
+ * pass.  Results agree with the other forms up to summation order.  Fails
+ * with GSR_ESTATE during a solve. */
+int gsr_set_blocked(gsr_system *sys, int32_t on, int32_t max_window);
+
+typedef struct {
+    int32_t active;       /* 1 once the regrouped copy exists */
+    int32_t workgroups;   /* of its pass */
+    int64_t window;       /* Wb: attitude starts per block */
+    int64_t blocks;
+    int64_t padded_rows;  /* rows including the padding to 64-row tiles */
+    int64_t segments;     /* star segments (astrometric partial sums per pass) */
+    int64_t bytes;        /* device bytes held by the copy */
+} gsr_blocked_layout;
+int gsr_blocked_info(gsr_system *sys, gsr_blocked_layout *info);
 
 /* Per-kernel timing with HIP events on the solve's stream (off by default).
  * gsr_timing_get synchronises, returns the totals since the last get and

@@ -416,8 +416,11 @@ void orc_covariances(const double *dsel, int64_t itn, int64_t k, const double *s
  * coefficients.  Each outer step forms the residual r = b - A x with FP64
  * products on those coefficients (exact upcast), solves A dx ~ r with the
  * inner LSQR options (normally the FP32-product mode and a loose
- * tolerance), and updates x += dx.  Stops once ||dx|| <= outer_tol ||x||
- * or after outer_max steps.  x is overwritten (starts from x0 or zero).
+ * tolerance), and updates x += dx.  Stops once ||dx|| <= outer_tol ||x||,
+ * or once the next correction predicted from the observed contraction,
+ * ||dx_k||^2 / ||dx_{k-1}|| (when ||dx_k|| < ||dx_{k-1}||), is at most
+ * outer_tol ||x||, or after outer_max steps.  x is overwritten (starts from
+ * x0 or zero).
  */
 int orc_lsqr_refine(const orc_sys *A, const double *b, const double *x0, double *x,
                     const orc_opts *inner, int32_t outer_max, double outer_tol,
@@ -436,6 +439,7 @@ int orc_lsqr_refine(const orc_sys *A, const double *b, const double *x0, double 
         x[j] = x0 ? x0[j] : 0.0;
     *inner_total = 0;
     *outer_steps = 0;
+    double prev = 0.0;  /* ||dx|| of the previous step */
     for (int32_t it = 0; it < outer_max; ++it) {
         memcpy(r, b, (size_t)m * sizeof(double));
         for (int64_t j = 0; j < n; ++j)
@@ -449,8 +453,10 @@ int orc_lsqr_refine(const orc_sys *A, const double *b, const double *x0, double 
             x[j] += dx[j];
         *inner_total += last->itn;
         *outer_steps = it + 1;
-        if (nrm2(dx, n) <= outer_tol * nrm2(x, n))
+        double d = nrm2(dx, n), lim = outer_tol * nrm2(x, n);
+        if (d <= lim || (it > 0 && d < prev && d * (d / prev) <= lim))
             break;
+        prev = d;
     }
 out:
     free(r);

@@ -47,6 +47,14 @@ class LsqrResult(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class BlockedInfo(C.Structure):
+    _fields_ = [("active", C.c_int32), ("workgroups", C.c_int32), ("window", C.c_int64), ("blocks", C.c_int64),
+                ("padded_rows", C.c_int64), ("segments", C.c_int64), ("bytes", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Timing(C.Structure):
     _fields_ = [("aprod1_ms", C.c_double), ("aprod2_ms", C.c_double), ("tail_ms", C.c_double),
                 ("update_ms", C.c_double), ("syrk_ms", C.c_double), ("aprod1_n", C.c_int64),
@@ -83,6 +91,8 @@ _SIGS = {
     "gsr_timing_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "gsr_set_graphs": (C.c_int, [C.c_void_p, C.c_int32]),
     "gsr_set_fused": (C.c_int, [C.c_void_p, C.c_int32]),
+    "gsr_set_blocked": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "gsr_blocked_info": (C.c_int, [C.c_void_p, C.c_void_p]),
     "gsr_set_constraints": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "gsr_cov_export": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32]),
     "gsr_cov_export_status": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -442,6 +452,14 @@ class System:
 
     def set_fused(self, on=True):
         _check(lib().gsr_set_fused(self._h, int(bool(on))))
+
+    def set_blocked(self, on=True, max_window=0):
+        _check(lib().gsr_set_blocked(self._h, int(bool(on)), int(max_window)))
+
+    def blocked_info(self):
+        i = BlockedInfo()
+        _check(lib().gsr_blocked_info(self._h, C.byref(i)))
+        return i.as_dict()
 
     def timing_enable(self, on=True):
         _check(lib().gsr_timing_enable(self._h, int(bool(on))))

@@ -555,6 +555,21 @@ hipError_t launch_tail_fused(const SysView& s, const AttView& av, int att_mode, 
   return hipGetLastError();
 }
 
+hipError_t launch_tail_blk(const SysView& s, const BlkView& bv, double* x, double* acc, const double* S,
+                           const double* gA, Scalars* sc, Work w, hipStream_t st, int lsqr_stage) {
+  const int64_t cols = s.n_astro + s.tail_len;
+  int blocks = (int)std::min<int64_t>(kMaxPartials, std::max<int64_t>(1, (cols + kBlock - 1) / kBlock));
+  // the workgroup windows take the place of the bucketed pass's windows
+  AttView av{};
+  av.Wb = bv.Wb;
+  av.nb = bv.nb;
+  av.bsub = bv.bsub;
+  av.Q = bv.Q;
+  TailLsqr L{lsqr_stage, 0, gA};
+  hipLaunchKernelGGL(k_tail, dim3(blocks), dim3(kBlock), 0, st, s, av, 3, x, acc, S, 0.0, sc, w, L);
+  return hipGetLastError();
+}
+
 hipError_t launch_validate(const SysView& s, unsigned long long* bad, hipStream_t st) {
   int64_t n = std::max(s.m, s.n_stars);
   int blocks = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (n + kBlock - 1) / kBlock));

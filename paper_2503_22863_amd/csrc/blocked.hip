@@ -1,0 +1,493 @@
+// One pass over the rows per LSQR iteration when the attitude block does not
+// fit in LDS (Sec. 2, Eq. 2 and Eq. 3 on the bidiagonalisation of Paige &
+// Saunders).
+//
+// A row touches five columns of its star and twelve attitude columns (three
+// axes, four consecutive starts from att_start).  In star order the star
+// columns are local and the attitude columns random; the bucketed attitude
+// pass pays for that with a second read of the attitude coefficients every
+// iteration.  Here the library keeps one copy of the rows regrouped by
+// attitude block g = att_start / Wb, star order inside a block, with Wb chosen
+// so that a block's window of 3 x (Wb + 3) sums fits in LDS.  Every
+// workgroup streams a tile range of one block: A v and u' = u_scale u + A v,
+// then a_r u'_r into the window (LDS atomics), the instrumental and global
+// sums, and the star sums.  A star's rows inside a wave's range are
+// consecutive (a segment); each segment's five sums are written once to P
+// and a reduction pass adds the segments of each star (about one per block).
+// The attitude windows go to Q and the tail adds the windows that cover a
+// column.
+//
+// The copy stores each 64-row tile chunk-major: 16-byte chunk j of the 64 rows
+// is one contiguous kilobyte, so the wave's load of chunk j puts row `lane`'s
+// chunk j straight into lane `lane` (no LDS transposition).  Blocks are
+// padded with zero rows to whole tiles, so every tile is full.
+#include <stdio.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "row_tiles.h"
+
+namespace gsr {
+
+constexpr int kBlkThreads = kBlkWaves * kWave;
+// static LDS of the pass: the attitude-window regroup buffers and the reduction slots
+constexpr size_t kBlkStaticLds = sizeof(double) * 2 * kBlkWaves * kWave * 7 + sizeof(double) * kBlkWaves + 64;
+
+// Row records: star id, attitude start within the block's window (12 bits),
+// six instrumental columns (11 bits each) and the end-of-segment bit.
+__device__ __forceinline__ void rec_pack(uint32_t* R, int64_t pos, uint32_t star, uint32_t off, const int* ic,
+                                         uint32_t end) {
+  const uint64_t A = (uint64_t)star | ((uint64_t)off << 32) | ((uint64_t)ic[0] << 44) | ((uint64_t)end << 63);
+  const uint64_t B = (uint64_t)ic[1] | ((uint64_t)ic[2] << 11) | ((uint64_t)ic[3] << 22) | ((uint64_t)ic[4] << 33) |
+                     ((uint64_t)ic[5] << 44);
+  u4 v = {(unsigned)A, (unsigned)(A >> 32), (unsigned)B, (unsigned)(B >> 32)};
+  reinterpret_cast<u4*>(R)[pos] = v;
+}
+
+// Builds the chunk-major coefficient tiles and the row records.  se[pos]:
+// star | end << 31.
+template <typename VT>
+__global__ void k_blk_rows(SysView s, BlkView bv, const uint32_t* __restrict__ se) {
+  constexpr int CPR = Geo<VT>::CPR;
+  const u4* src = reinterpret_cast<const u4*>(s.vals);
+  u4* T = reinterpret_cast<u4*>(bv.T);
+  for (int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pos < bv.mp;
+       pos += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = bv.perm[pos];
+    const int64_t tile = pos / kWave, lane = pos - tile * kWave;
+    u4* dst = T + tile * CPR * kWave + lane;
+    int ic[6] = {0, 0, 0, 0, 0, 0};
+    uint32_t off = 0;
+    if (r >= 0) {
+#pragma unroll
+      for (int j = 0; j < CPR; ++j) dst[j * kWave] = src[r * CPR + j];
+      off = (uint32_t)(s.att_start[r] % bv.Wb);
+#pragma unroll
+      for (int q = 0; q < 6; ++q) ic[q] = s.instr_col[6 * r + q];
+    } else {
+#pragma unroll
+      for (int j = 0; j < CPR; ++j) dst[j * kWave] = u4{0u, 0u, 0u, 0u};
+    }
+    const uint32_t e = se[pos];
+    rec_pack(bv.R, pos, e & 0x7FFFFFFFu, off, ic, e >> 31);
+  }
+}
+
+__global__ void k_blk_permute(BlkView bv, const double* __restrict__ src) {
+  for (int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pos < bv.mp;
+       pos += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t r = bv.perm[pos];
+    bv.ub[pos] = r >= 0 ? src[r] : 0.0;
+  }
+}
+
+// The iteration's pass.  Workgroup b streams tiles of block wg_block[b]; its
+// waves take consecutive sub-ranges.  The tile mechanics follow the star-order
+// pass: the next tile's loads are issued once the current tile's gathers are
+// out, and the current tile's stores wait for the start of the next one.
+template <typename VT, int PM>
+__global__ void __launch_bounds__(kBlkThreads) __attribute__((amdgpu_waves_per_eu(2)))
+k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __restrict__ x3, double* __restrict__ acc,
+       Scalars* sc, Work wk, int init) {
+  constexpr int CPR = Geo<VT>::CPR;
+  __shared__ dd2u rg[kBlkWaves][kWave * 7];
+  __shared__ double red[kBlkWaves];
+  __shared__ int flag;
+  extern __shared__ double dyn[];  // window [3][W3], instrumental + global sums, instrumental x
+  if (sc->done) return;
+  const double scale = sc->u_scale;
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int64_t W3 = bv.Wb + 3;
+  const int64_t ntl = s.n_instr + s.n_glob;
+  double* win = dyn;
+  double* tl = dyn + 3 * W3;
+  double* xil = tl + ntl;
+  const int64_t NI = s.n_astro + 3 * s.n_att;
+  for (int64_t j = threadIdx.x; j < 3 * W3 + ntl; j += kBlkThreads) dyn[j] = 0.0;
+  for (int64_t j = threadIdx.x; j < s.n_instr; j += kBlkThreads) xil[j] = x[NI + j];
+  __syncthreads();
+
+  const int64_t g = bv.wg_block[blockIdx.x];
+  const double* xw = x3 + 3 * g * bv.Wb;  // interleaved x of the block's window
+  const int64_t w = (int64_t)blockIdx.x * kBlkWaves + wid;
+  const int64_t T0 = bv.wave_tile[w], T1 = bv.wave_tile[w + 1];
+  double sumsq = 0.0, gsum = 0.0;
+  if (T0 < T1) {
+    const double xg = s.n_glob ? x[NI + s.n_instr] : 0.0;
+    const int64_t xa_last = 5 * s.n_stars - 1;
+    const u4* cb = reinterpret_cast<const u4*>(bv.T);
+    const u4* rb = reinterpret_cast<const u4*>(bv.R);
+    u4 tmp[CPR];
+    u4 rec;
+    double uo;
+    auto fetch = [&](int64_t t) {
+      const int64_t tt = min(t, T1 - 1);  // past the range: re-read its last tile (the registers are not used)
+      const u4* base = cb + tt * CPR * kWave + lane;
+#pragma unroll
+      for (int j = 0; j < CPR; ++j) tmp[j] = ld_stream(base + j * kWave);
+      rec = ld_stream(rb + tt * kWave + lane);
+      uo = bv.ub[tt * kWave + lane];
+    };
+    double carry[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    int carry_valid = 0;
+    int64_t nstart = bv.seg_base[w];  // segments begun before the current tile
+    int64_t r_out = -1, c_out = -1;
+    double u_out = 0.0;
+    double g_out[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    fetch(T0);
+#pragma unroll 1
+    for (int64_t t = T0; t < T1; ++t) {
+      const uint64_t A = (uint64_t)rec.x | ((uint64_t)rec.y << 32);
+      const uint64_t B = (uint64_t)rec.z | ((uint64_t)rec.w << 32);
+      const int64_t star = (int64_t)(uint32_t)A;
+      const int aoff = (int)((A >> 32) & 0xFFFu);
+      const int ic[6] = {(int)((A >> 44) & 0x7FFu), (int)(B & 0x7FFu),         (int)((B >> 11) & 0x7FFu),
+                         (int)((B >> 22) & 0x7FFu), (int)((B >> 33) & 0x7FFu), (int)((B >> 44) & 0x7FFu)};
+      const bool end = (A >> 63) != 0;
+      const double uo_c = (scale == 0.0) ? 0.0 : scale * uo;
+      if (r_out >= 0) bv.ub[r_out] = u_out;
+      if (c_out >= 0) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) bv.P[c_out + k] = g_out[k];
+      }
+      // gathers of x for this tile, issued before the next tile's loads
+      const int64_t s0 = __shfl(star, 0, kWave);
+      const int64_t ds = star - s0;
+      const bool far = __ballot(ds >= 12) != 0;  // more than 12 stars in the tile: per-lane gathers
+      const double xs = x[min(5 * s0 + lane, xa_last)];
+      dd2u cw[6];  // piece j*64 + lane of the tile's attitude windows
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        const int c = j * kWave + lane, i = c / 6, q = c - 6 * i;
+        const int ao = __shfl(aoff, i, kWave);
+        cw[j] = *reinterpret_cast<const dd2u*>(xw + 3 * ao + 2 * q);
+      }
+      u4 cur[CPR];
+#pragma unroll
+      for (int j = 0; j < CPR; ++j) cur[j] = tmp[j];
+      order_point();
+      fetch(t + 1);
+      order_point();
+      VT a[kSlots];
+      __builtin_memcpy(a, cur, sizeof(a));
+      // u'_r = u_scale * u_r + (A x)_r
+      double ax = 0.0;
+      {
+        const int base = far ? 0 : 5 * (int)ds;
+        double xa5[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) xa5[k] = __shfl(xs, base + k, kWave);
+        if (far) {
+#pragma unroll
+          for (int k = 0; k < 5; ++k) xa5[k] = x[5 * star + k];
+        }
+#pragma unroll
+        for (int k = 0; k < 5; ++k) ax += prod<PM>(a[k], xa5[k]);
+      }
+      {
+        // regroup the attitude windows per row; element e = 3j + axis is column start+j of that axis
+        dd2u* wl = rg[wid];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+          const int c = j * kWave + lane, i = c / 6, q = c - 6 * i;
+          wl[i * 7 + q] = cw[j];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+          const dd2u pq = wl[lane * 7 + q];
+          const int e0 = 2 * q, e1 = 2 * q + 1;
+          ax += prod<PM>(a[5 + 4 * (e0 % 3) + e0 / 3], pq.x);
+          ax += prod<PM>(a[5 + 4 * (e1 % 3) + e1 / 3], pq.y);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+      }
+#pragma unroll
+      for (int q = 0; q < 6; ++q) ax += prod<PM>(a[17 + q], xil[ic[q]]);
+      if (s.n_glob) ax += prod<PM>(a[23], xg);
+      const double un = uo_c + ax;
+      r_out = t * kWave + lane;
+      u_out = un;
+      sumsq += un * un;
+      // a_r * u'_r into the window, the instrumental and global sums, and the star sums
+#pragma unroll
+      for (int axs = 0; axs < 3; ++axs)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) atomicAdd(win + axs * W3 + aoff + j, prod<PM>(a[5 + 4 * axs + j], un));
+#pragma unroll
+      for (int q = 0; q < 6; ++q) atomicAdd(tl + ic[q], prod<PM>(a[17 + q], un));
+      if (s.n_glob) gsum += prod<PM>(a[23], un);
+      double p[5];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) p[k] = prod<PM>(a[k], un);
+      if (carry_valid && lane == 0) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) p[k] += carry[k];
+      }
+      // segment starts: lane 0 unless the previous tile's last segment goes on, else after an end
+      const bool prev_end = __shfl_up(end ? 1 : 0, 1, kWave) != 0;
+      const bool start = (lane == 0) ? !carry_valid : prev_end;
+      const uint64_t starts = __ballot(start);
+      const uint64_t le = (lane == kWave - 1) ? ~0ull : ((2ull << lane) - 1);
+      const uint64_t mine = starts & le;
+      const int seg0 = mine ? 63 - __clzll(mine) : 0;
+#pragma unroll
+      for (int off = 1; off < kWave; off <<= 1) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+          const double o = __shfl_up(p[k], off, kWave);
+          if (lane - off >= seg0) p[k] += o;
+        }
+      }
+      const int64_t sidx = nstart - 1 + __popcll(mine);
+      c_out = end ? 5 * sidx : -1;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) g_out[k] = p[k];
+      nstart += __popcll(starts);
+      const int lend = __shfl(end ? 1 : 0, kWave - 1, kWave);
+#pragma unroll
+      for (int k = 0; k < 5; ++k) carry[k] = __shfl(p[k], kWave - 1, kWave);
+      carry_valid = !lend;
+    }
+    if (r_out >= 0) bv.ub[r_out] = u_out;
+    if (c_out >= 0) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) bv.P[c_out + k] = g_out[k];
+    }
+  }
+  if (s.n_glob) {
+    const double gs = wave_sum(gsum);
+    if (lane == 0) atomicAdd(tl + s.n_instr, gs);
+  }
+  __syncthreads();
+  double* q = bv.Q + (int64_t)blockIdx.x * 3 * W3;
+  for (int64_t k = threadIdx.x; k < 3 * W3; k += kBlkThreads) q[k] = win[k];
+  for (int64_t j = threadIdx.x; j < ntl; j += kBlkThreads) {
+    const double v = tl[j];
+    if (v != 0.0) atomicAdd(acc + 3 * s.n_att + j, v);
+  }
+  const double bs = block_sum<kBlkThreads>(sumsq, red);
+  if (threadIdx.x == 0) publish(wk.part_a + blockIdx.x, bs);
+  if (last_block(wk.tickets + T_APROD1, &flag)) {
+    const double tot = sum_partials<kBlkThreads>(wk.part_a, gridDim.x, red);
+    if (threadIdx.x == 0) {
+      epi_beta(sc, tot + sc->con_sumsq, init);
+      ticket_reset(wk.tickets + T_APROD1);
+    }
+  }
+}
+
+hipError_t launch_fblk(const SysView& s, const BlkView& bv, int pmode, const double* vg, const double* x3,
+                       double* acc, Scalars* sc, Work w, hipStream_t st, int init) {
+  if (!bv.ready || bv.G < 1 || bv.G > kMaxPartials) return hipErrorInvalidValue;
+  if (pmode == 1 && s.value_type != GSR_F32) return hipErrorInvalidValue;
+  const dim3 g(bv.G), b(kBlkThreads);
+  if (s.value_type == GSR_F32 && pmode == 1)
+    hipLaunchKernelGGL((k_fblk<float, 1>), g, b, bv.lds, st, s, bv, vg, x3, acc, sc, w, init);
+  else if (s.value_type == GSR_F32)
+    hipLaunchKernelGGL((k_fblk<float, 0>), g, b, bv.lds, st, s, bv, vg, x3, acc, sc, w, init);
+  else
+    hipLaunchKernelGGL((k_fblk<double, 0>), g, b, bv.lds, st, s, bv, vg, x3, acc, sc, w, init);
+  return hipGetLastError();
+}
+
+// One star per thread: its segment ids are consecutive in seg_list and, for
+// neighbouring stars, the i-th segments are neighbours in P (same block), so
+// the loads of a wave stay contiguous.  Ids are fetched eight at a time
+// before the sums, to keep the two dependent loads from serialising.
+__global__ void __launch_bounds__(kBlock) k_seg_reduce(SysView s, BlkView bv, double* __restrict__ gA, Scalars* sc) {
+  if (sc && (sc->done || !sc->do_v)) return;
+  for (int64_t st = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; st < s.n_stars;
+       st += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t q0 = bv.seg_ptr[st], q1 = bv.seg_ptr[st + 1];
+    double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int32_t q = q0; q < q1; q += 8) {
+      int32_t id[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) id[i] = (q + i < q1) ? bv.seg_list[q + i] : -1;
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        if (id[i] >= 0) {
+          const double* p = bv.P + 5 * (int64_t)id[i];
+#pragma unroll
+          for (int k = 0; k < 5; ++k) a[k] += p[k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) gA[5 * st + k] = a[k];
+  }
+}
+
+hipError_t launch_seg_reduce(const SysView& s, const BlkView& bv, double* gA, Scalars* sc, hipStream_t st) {
+  if (s.n_stars == 0) return hipSuccess;
+  const int blocks = (int)std::min<int64_t>(16384, (s.n_stars + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_seg_reduce, dim3(blocks), dim3(kBlock), 0, st, s, bv, gA, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_blk_permute(const BlkView& bv, const double* src, hipStream_t st) {
+  const int blocks = (int)std::min<int64_t>(8192, (bv.mp + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_blk_permute, dim3(std::max(blocks, 1)), dim3(kBlock), 0, st, bv, src);
+  return hipGetLastError();
+}
+
+void blk_free(BlkView* bv) {
+  for (void* p : {(void*)bv->T, (void*)bv->R, (void*)bv->perm, (void*)bv->wg_block, (void*)bv->wave_tile,
+                  (void*)bv->seg_base, (void*)bv->bsub, (void*)bv->seg_ptr, (void*)bv->seg_list, (void*)bv->P,
+                  (void*)bv->Q, (void*)bv->ub})
+    if (p) (void)hipFree(p);
+  *bv = BlkView{};
+}
+
+// ------------------------------------------------------------------ build
+// The regrouping (positions, workgroup and wave ranges, segments) is laid out
+// on the host from att_start and star_row_ptr; the copy itself is made on the
+// device.
+int blk_build(const SysView& s, BlkView* bv, int cus, int max_window, int lds_max, char* err, size_t errlen,
+              hipStream_t st) {
+  *bv = BlkView{};
+  auto failed = [&](int code, const char* what) {
+    snprintf(err, errlen, "%s", what);
+    blk_free(bv);
+    return code;
+  };
+  const int64_t m = s.m, S = s.n_stars;
+  if (m <= 0 || s.n_att < 8 || s.n_instr > 2047 || S >= ((int64_t)1 << 31) || m >= ((int64_t)1 << 31))
+    return failed(GSR_EINVAL, "system outside the regrouped pass's limits");
+  // window width: the largest that fits the LDS budget (at most 4096 starts: 12-bit offsets)
+  const int64_t budget = (int64_t)lds_max - (int64_t)kBlkStaticLds - 8 * (2 * s.n_instr + s.n_glob);
+  int64_t wmax = std::min<int64_t>(budget / 24 - 3, 4096);
+  if (max_window > 0) wmax = std::min<int64_t>(wmax, max_window);
+  if (wmax < 4) return failed(GSR_EINVAL, "not enough LDS for an attitude window");
+  const int64_t nstarts = s.n_att - 3;
+  const int64_t nb = (nstarts + wmax - 1) / wmax;
+  const int64_t Wb = (nstarts + nb - 1) / nb;
+  bv->Wb = Wb;
+  bv->nb = nb;
+  bv->lds = sizeof(double) * (size_t)(3 * (Wb + 3) + 2 * s.n_instr + s.n_glob);
+
+  std::vector<int32_t> att((size_t)m);
+  std::vector<int64_t> rp((size_t)S + 1);
+  if (hipMemcpy(att.data(), s.att_start, sizeof(int32_t) * (size_t)m, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(rp.data(), s.row_ptr, sizeof(int64_t) * (size_t)(S + 1), hipMemcpyDeviceToHost) != hipSuccess)
+    return failed(GSR_EHIP, "reading the row indices failed");
+  std::vector<int64_t> cnt((size_t)nb, 0), tb((size_t)nb + 1, 0);
+  for (int64_t r = 0; r < m; ++r) ++cnt[(size_t)(att[(size_t)r] / Wb)];
+  for (int64_t g = 0; g < nb; ++g) tb[(size_t)g + 1] = tb[(size_t)g] + (cnt[(size_t)g] + kWave - 1) / kWave;
+  const int64_t ntiles = tb[(size_t)nb], mp = ntiles * kWave;
+  if (mp >= ((int64_t)1 << 31)) return failed(GSR_EINVAL, "too many rows for the regrouped pass");
+  bv->ntiles = ntiles;
+  bv->mp = mp;
+
+  // positions: block-major, star order inside a block; padding repeats the block's last star
+  std::vector<int32_t> perm((size_t)mp, -1);
+  std::vector<uint32_t> se((size_t)mp, 0);
+  {
+    std::vector<int64_t> fill((size_t)nb);
+    for (int64_t g = 0; g < nb; ++g) fill[(size_t)g] = tb[(size_t)g] * kWave;
+    for (int64_t st_ = 0; st_ < S; ++st_)
+      for (int64_t r = rp[(size_t)st_]; r < rp[(size_t)st_ + 1]; ++r) {
+        const int64_t pos = fill[(size_t)(att[(size_t)r] / Wb)]++;
+        perm[(size_t)pos] = (int32_t)r;
+        se[(size_t)pos] = (uint32_t)st_;
+      }
+    for (int64_t g = 0; g < nb; ++g)
+      for (int64_t pos = fill[(size_t)g]; pos < tb[(size_t)g + 1] * kWave; ++pos) se[(size_t)pos] = se[(size_t)pos - 1];
+  }
+
+  // workgroups per block in proportion to its tiles (at least one per non-empty block)
+  const int64_t gt = std::max<int64_t>(1, 2 * (int64_t)cus);
+  std::vector<int32_t> wg_block, bsub((size_t)nb + 1, 0), wave_tile;
+  for (int64_t g = 0; g < nb; ++g) {
+    const int64_t Tg = tb[(size_t)g + 1] - tb[(size_t)g];
+    int64_t Gg = Tg > 0 ? std::max<int64_t>(1, (gt * Tg + ntiles / 2) / ntiles) : 0;
+    Gg = std::min(Gg, Tg);
+    bsub[(size_t)g] = (int32_t)wg_block.size();
+    for (int64_t k = 0; k < Gg; ++k) {
+      const int64_t a = tb[(size_t)g] + Tg * k / Gg, b = tb[(size_t)g] + Tg * (k + 1) / Gg;
+      wg_block.push_back((int32_t)g);
+      for (int i = 0; i < kBlkWaves; ++i) wave_tile.push_back((int32_t)(a + (b - a) * i / kBlkWaves));
+    }
+  }
+  bsub[(size_t)nb] = (int32_t)wg_block.size();
+  wave_tile.push_back((int32_t)ntiles);
+  const int64_t G = (int64_t)wg_block.size();
+  if (G < 1 || G > kMaxPartials) return failed(GSR_EINVAL, "workgroup count outside the partial slots");
+  bv->G = (int32_t)G;
+
+  // segments: maximal runs of one star inside a wave's range
+  const int64_t W = G * kBlkWaves;
+  std::vector<int32_t> seg_base((size_t)W);
+  std::vector<int32_t> seg_star;
+  for (int64_t w = 0; w < W; ++w) {
+    seg_base[(size_t)w] = (int32_t)seg_star.size();
+    const int64_t p0 = (int64_t)wave_tile[(size_t)w] * kWave, p1 = (int64_t)wave_tile[(size_t)w + 1] * kWave;
+    for (int64_t pos = p0; pos < p1; ++pos) {
+      const uint32_t sp = se[(size_t)pos];
+      if (pos == p0 || sp != (se[(size_t)pos - 1] & 0x7FFFFFFFu)) {
+        seg_star.push_back((int32_t)sp);
+        if (seg_star.size() >= ((size_t)1 << 31) / 5) return failed(GSR_EINVAL, "too many star segments");
+      }
+      const bool end = pos == p1 - 1 || se[(size_t)pos + 1] != sp;
+      if (end) se[(size_t)pos] = sp | 0x80000000u;
+    }
+  }
+  const int64_t nseg = (int64_t)seg_star.size();
+  bv->nseg = nseg;
+  std::vector<int32_t> seg_ptr((size_t)S + 1, 0), seg_list((size_t)std::max<int64_t>(nseg, 1));
+  for (int64_t q = 0; q < nseg; ++q) ++seg_ptr[(size_t)seg_star[(size_t)q] + 1];
+  for (int64_t i = 0; i < S; ++i) seg_ptr[(size_t)i + 1] += seg_ptr[(size_t)i];
+  {
+    std::vector<int32_t> fill(seg_ptr.begin(), seg_ptr.end() - 1);
+    for (int64_t q = 0; q < nseg; ++q) seg_list[(size_t)fill[(size_t)seg_star[(size_t)q]]++] = (int32_t)q;
+  }
+
+  const int cpr = s.value_type == GSR_F32 ? Geo<float>::CPR : Geo<double>::CPR;
+  uint32_t* se_d = nullptr;
+  auto dalloc_ = [](void** p, size_t bytes) { return hipMalloc(p, std::max<size_t>(bytes, 16)) == hipSuccess; };
+  if (!dalloc_(&bv->T, (size_t)mp * cpr * 16) || !dalloc_((void**)&bv->R, (size_t)mp * 16) ||
+      !dalloc_((void**)&bv->perm, (size_t)mp * 4) || !dalloc_((void**)&bv->wg_block, (size_t)G * 4) ||
+      !dalloc_((void**)&bv->wave_tile, (size_t)(W + 1) * 4) || !dalloc_((void**)&bv->seg_base, (size_t)W * 4) ||
+      !dalloc_((void**)&bv->bsub, (size_t)(nb + 1) * 4) || !dalloc_((void**)&bv->seg_ptr, (size_t)(S + 1) * 4) ||
+      !dalloc_((void**)&bv->seg_list, seg_list.size() * 4) || !dalloc_((void**)&bv->P, (size_t)nseg * 40) ||
+      !dalloc_((void**)&bv->Q, (size_t)G * 3 * (Wb + 3) * 8) || !dalloc_((void**)&bv->ub, (size_t)mp * 8) ||
+      !dalloc_((void**)&se_d, (size_t)mp * 4)) {
+    (void)hipGetLastError();
+    if (se_d) (void)hipFree(se_d);
+    return failed(GSR_ENOMEM, "device memory for the regrouped copy");
+  }
+  bool ok = hipMemcpyAsync(bv->perm, perm.data(), (size_t)mp * 4, hipMemcpyHostToDevice, st) == hipSuccess &&
+            hipMemcpyAsync(se_d, se.data(), (size_t)mp * 4, hipMemcpyHostToDevice, st) == hipSuccess &&
+            hipMemcpyAsync(bv->wg_block, wg_block.data(), (size_t)G * 4, hipMemcpyHostToDevice, st) == hipSuccess &&
+            hipMemcpyAsync(bv->wave_tile, wave_tile.data(), (size_t)(W + 1) * 4, hipMemcpyHostToDevice, st) ==
+                hipSuccess &&
+            hipMemcpyAsync(bv->seg_base, seg_base.data(), (size_t)W * 4, hipMemcpyHostToDevice, st) == hipSuccess &&
+            hipMemcpyAsync(bv->bsub, bsub.data(), (size_t)(nb + 1) * 4, hipMemcpyHostToDevice, st) == hipSuccess &&
+            hipMemcpyAsync(bv->seg_ptr, seg_ptr.data(), (size_t)(S + 1) * 4, hipMemcpyHostToDevice, st) ==
+                hipSuccess &&
+            hipMemcpyAsync(bv->seg_list, seg_list.data(), seg_list.size() * 4, hipMemcpyHostToDevice, st) ==
+                hipSuccess;
+  if (ok) {
+    const int blocks = (int)std::min<int64_t>(8192, (mp + kBlock - 1) / kBlock);
+    if (s.value_type == GSR_F32)
+      hipLaunchKernelGGL(k_blk_rows<float>, dim3(blocks), dim3(kBlock), 0, st, s, *bv, se_d);
+    else
+      hipLaunchKernelGGL(k_blk_rows<double>, dim3(blocks), dim3(kBlock), 0, st, s, *bv, se_d);
+    ok = hipGetLastError() == hipSuccess && hipStreamSynchronize(st) == hipSuccess;
+  }
+  (void)hipFree(se_d);
+  if (!ok) return failed(GSR_EHIP, "building the regrouped copy failed");
+  // allow the dynamic LDS size beyond 64 KB (where the runtime asks for it)
+  (void)hipFuncSetAttribute((const void*)k_fblk<double, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bv->lds);
+  (void)hipFuncSetAttribute((const void*)k_fblk<float, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bv->lds);
+  (void)hipFuncSetAttribute((const void*)k_fblk<float, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bv->lds);
+  (void)hipGetLastError();
+  bv->ready = 1;
+  return GSR_OK;
+}
+
+}  // namespace gsr

@@ -70,6 +70,12 @@ struct gsr_system {
   double* x3 = nullptr;  // attitude part of vg, axes interleaved, for the fused pass
   void* rix = nullptr;   // packed row indices for the fused pass (16 B per row); null: no fused pass
   int fused = 1;         // one pass over the rows per iteration (FP64 products, attitude mode 0 or 3)
+  // rows regrouped by attitude window (one pass per iteration where the attitude block exceeds LDS)
+  BlkView blk{};
+  int blocked = 1;       // use the regrouped copy when it applies
+  int blk_maxw = 0;      // cap on its window width (0: as large as LDS allows)
+  int blk_failed = 0;    // the copy could not be built (memory or limits): not tried again
+  int use_blk = 0;       // the current solve runs on it
   // refinement buffers
   double *r = nullptr, *xr = nullptr, *dx = nullptr, *nrm2 = nullptr;
   // covariances
@@ -166,6 +172,13 @@ static int is_device_ptr(const void* p) {
     if (!is_device_ptr(p)) return fail(GSR_EINVAL, "%s must be a device pointer", name);            \
   } while (0)
 
+static int device_lds() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 65536;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0) return 65536;
+  return v;
+}
+
 int gsr::device_cus() {
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 256;
@@ -228,6 +241,7 @@ static void release(gsr_system* s) {
   dfree(s->D);
   dfree(s->Cacc);
   att_free(&s->av);
+  blk_free(&s->blk);
   if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
   for (auto e : s->gev)
     if (e) (void)hipEventDestroy(e);
@@ -379,6 +393,41 @@ extern "C" int gsr_set_fused(gsr_system* s, int32_t on) {
   CHK(check_handle(s));
   if (s->in_session) return fail(GSR_ESTATE, "gsr_set_fused: a solve is in progress");
   s->fused = on != 0;
+  return GSR_OK;
+}
+
+static void drop_graph(gsr_system* s);
+
+extern "C" int gsr_set_blocked(gsr_system* s, int32_t on, int32_t max_window) {
+  CHK(check_handle(s));
+  if (s->in_session) return fail(GSR_ESTATE, "gsr_set_blocked: a solve is in progress");
+  if (max_window != 0 && max_window < 4) return fail(GSR_EINVAL, "max_window must be 0 or >= 4");
+  if (max_window != s->blk_maxw) {
+    (void)hipDeviceSynchronize();
+    blk_free(&s->blk);  // rebuilt with the new width when next used
+    s->blk_failed = 0;
+    drop_graph(s);
+  }
+  s->blocked = on != 0;
+  s->blk_maxw = max_window;
+  return GSR_OK;
+}
+
+extern "C" int gsr_blocked_info(gsr_system* s, gsr_blocked_layout* info) {
+  CHK(check_handle(s));
+  if (!info) return fail(GSR_EINVAL, "info is null");
+  memset(info, 0, sizeof *info);
+  const BlkView& b = s->blk;
+  if (!b.ready) return GSR_OK;
+  const int64_t cpr = s->s.value_type == GSR_F32 ? 6 : 12;
+  info->active = 1;
+  info->workgroups = b.G;
+  info->window = b.Wb;
+  info->blocks = b.nb;
+  info->padded_rows = b.mp;
+  info->segments = b.nseg;
+  info->bytes = b.mp * (16 * cpr + 16 + 4 + 8) + b.nseg * (40 + 4) + (s->s.n_stars + 1) * 4 +
+                (int64_t)b.G * (3 * (b.Wb + 3) * 8 + 4 + 8 * kBlkWaves);
   return GSR_OK;
 }
 
@@ -544,10 +593,16 @@ static int ensure_vectors(gsr_system* s) {
 // tail passes) instead of separate aprod 1 and aprod 2 passes.
 static int fused_for(const gsr_system* s, int32_t pmode) {
   const int mode = att_mode(s);
-  return s->fused && pmode == 0 && (mode == 0 || mode == 3) && s->rix != nullptr;
+  return s->fused && (mode == 0 || mode == 3) && s->rix != nullptr;
 }
 
 static int iteration_fused(const gsr_system* s) { return fused_for(s, s->pmode); }
+
+// Whether a solve runs on the copy regrouped by attitude window.
+static int blk_applies(const gsr_system* s) {
+  return s->blocked && s->fused && !s->blk_failed && s->s.m > 0 && s->s.tail_len > kLdsTailMax &&
+         s->s.n_instr + 1 <= kLdsTailMax && s->con.ncon == 0;
+}
 
 static int lsqr_begin(gsr_system* s, const double* b, const double* x0, const gsr_lsqr_opts* o, int32_t product,
                       hipStream_t st) {
@@ -555,11 +610,22 @@ static int lsqr_begin(gsr_system* s, const double* b, const double* x0, const gs
   CHK(check_product(s, product));
   if (s->s.m > 0) NEED_DEV(b, "b");
   if (x0) NEED_DEV(x0, "x0");
-  if (s->con.ncon > 0 && !fused_for(s, product))
+  if (s->con.ncon > 0 && (product != GSR_PROD_F64 || !fused_for(s, product)))
     return fail(GSR_EINVAL, "constraint equations need the fused iteration (FP64 products, fused on, "
                             "attitude in LDS or bucketed)");
   CHK(ensure_vectors(s));
   if (o->precond) CHK(ensure_scale(s, st));
+  s->use_blk = 0;
+  if (blk_applies(s)) {
+    if (!s->blk.ready) {
+      char msg[256] = "";
+      HIPCHK(hipStreamSynchronize(st));
+      const int rc = blk_build(s->s, &s->blk, s->cus, s->blk_maxw, device_lds(), msg, sizeof msg, st);
+      if (rc == GSR_EHIP) return fail(rc, "regrouped copy: %s", msg);
+      if (rc != GSR_OK) s->blk_failed = 1;  // no memory for it, or outside its limits: the bucketed pass
+    }
+    s->use_blk = s->blk.ready;
+  }
   s->precond = o->precond;
   s->pmode = product;
   s->x0 = x0;
@@ -600,7 +666,19 @@ static int lsqr_begin(gsr_system* s, const double* b, const double* x0, const gs
   if (x0 && s->s.m > 0)
     HIPCHK(launch_aprod1(s->s, s->sh, x0, s->u, 1.0, -1.0, 0, nullptr, s->wk, 0, st));
   if (x0) HIPCHK(launch_con_aprod1(s->con, x0, uc, 1.0, -1.0, nullptr, s->wk, st));
-  if (s->con.ncon > 0) {
+  if (s->use_blk) {
+    // r0 in the regrouped order; then beta_1 and alpha_1 v_1 by the iteration's
+    // own pass with x = 0 (u' = u) and the init steps of the scalar recurrences
+    if (!s->zvec) {
+      CHK(dalloc(&s->zvec, (size_t)s->s.n));
+      HIPCHK(launch_fill(s->zvec, s->s.n, 0.0, st));
+    }
+    HIPCHK(launch_blk_permute(s->blk, s->u, st));
+    HIPCHK(launch_att_interleave(s->s, s->zvec, s->x3, st));
+    HIPCHK(launch_fblk(s->s, s->blk, product, s->zvec, s->x3, s->acc, s->sc, s->wk, st, 1));
+    HIPCHK(launch_seg_reduce(s->s, s->blk, s->gA, s->sc, st));
+    HIPCHK(launch_tail_blk(s->s, s->blk, s->v, s->acc, S, s->gA, s->sc, s->wk, st, 0));
+  } else if (s->con.ncon > 0) {
     // beta_1 u_1 = r0 and alpha_1 v_1 = S [A; C]^T u_1 through the iteration's own
     // passes, with x = 0 (u' = u) and the init steps of the scalar recurrences
     const int mode = att_mode(s);
@@ -610,7 +688,7 @@ static int lsqr_begin(gsr_system* s, const double* b, const double* x0, const gs
     }
     HIPCHK(launch_att_interleave(s->s, s->zvec, s->x3, st));
     HIPCHK(launch_con_aprod1(s->con, s->zvec, uc, 0.0, 1.0, s->sc, s->wk, st));
-    HIPCHK(launch_fused(s->s, s->sh, mode, s->zvec, s->x3, s->rix, s->u, s->gA, s->acc, s->sc, s->wk, st, 1));
+    HIPCHK(launch_fused(s->s, s->sh, mode, 0, s->zvec, s->x3, s->rix, s->u, s->gA, s->acc, s->sc, s->wk, st, 1));
     if (mode == 3) {
       HIPCHK(launch_partition(s->s, s->av, s->u, s->sc, st));
       HIPCHK(launch_att_pass(s->s, s->av, 1.0, 0, 0, s->sc, st, 1));
@@ -623,7 +701,7 @@ static int lsqr_begin(gsr_system* s, const double* b, const double* x0, const gs
     CHK(aprod2_launches(s, s->u, s->v, S, 0.0, product, 0, s->sc, 0, st));
   }
   HIPCHK(launch_init_vectors(s->s.n, s->v, s->vg, s->w, s->y, s->var, S, s->sc, st));
-  if (iteration_fused(s)) HIPCHK(launch_att_interleave(s->s, o->precond ? s->vg : s->v, s->x3, st));
+  if (s->use_blk || iteration_fused(s)) HIPCHK(launch_att_interleave(s->s, o->precond ? s->vg : s->v, s->x3, st));
   s->in_session = 1;
   return GSR_OK;
 }
@@ -668,7 +746,20 @@ static int enqueue_iteration(gsr_system* s, hipStream_t st) {
     const int h = (int)((s->enq / s->eblock) & 1);
     if (s->eissued[h]) HIPCHK(hipStreamWaitEvent(st, s->eev[h], 0));
   }
-  if (iteration_fused(s)) {
+  if (s->use_blk) {
+    {
+      TimeScope ts(s, 0, st);
+      HIPCHK(launch_fblk(s->s, s->blk, s->pmode, vg, s->x3, s->acc, s->sc, s->wk, st));
+    }
+    {
+      TimeScope ts(s, 1, st);
+      HIPCHK(launch_seg_reduce(s->s, s->blk, s->gA, s->sc, st));
+    }
+    {
+      TimeScope ts(s, 2, st);
+      HIPCHK(launch_tail_blk(s->s, s->blk, s->v, s->acc, S, s->gA, s->sc, s->wk, st));
+    }
+  } else if (iteration_fused(s)) {
     const int mode = att_mode(s);
     double* uc = s->u + s->s.m;
     if (s->con.ncon > 0) {
@@ -677,12 +768,12 @@ static int enqueue_iteration(gsr_system* s, hipStream_t st) {
     }
     {
       TimeScope ts(s, 0, st);
-      HIPCHK(launch_fused(s->s, s->sh, mode, vg, s->x3, s->rix, s->u, s->gA, s->acc, s->sc, s->wk, st));
+      HIPCHK(launch_fused(s->s, s->sh, mode, s->pmode, vg, s->x3, s->rix, s->u, s->gA, s->acc, s->sc, s->wk, st));
     }
     if (mode == 3) {
       TimeScope ts(s, 1, st);
       HIPCHK(launch_partition(s->s, s->av, s->u, s->sc, st));
-      HIPCHK(launch_att_pass(s->s, s->av, 1.0, 0, 0, s->sc, st, 1));
+      HIPCHK(launch_att_pass(s->s, s->av, 1.0, s->pmode, 0, s->sc, st, 1));
     }
     if (s->con.ncon > 0) {
       TimeScope ts(s, 2, st);
@@ -707,7 +798,7 @@ static int enqueue_iteration(gsr_system* s, hipStream_t st) {
     TimeScope ts(s, 3, st);
     HIPCHK(launch_update(s->s.n, s->v, vg, s->w, s->y, s->var, S, s->sc, s->wk, st, s->eblock ? s->ering : nullptr,
                          s->eblock ? s->eblock : 1));
-    if (iteration_fused(s)) HIPCHK(launch_att_interleave(s->s, vg, s->x3, st));
+    if (s->use_blk || iteration_fused(s)) HIPCHK(launch_att_interleave(s->s, vg, s->x3, st));
   }
   s->enq += 1;
   if (s->nsel > 0 && s->enq % s->dblock == 0) {
@@ -733,7 +824,7 @@ static void drop_graph(gsr_system* s) {
 static int graph_block(gsr_system* s, int64_t G, hipStream_t st) {
   const uint64_t key = ((uint64_t)s->precond << 0) | ((uint64_t)s->pmode << 1) | ((uint64_t)(s->nsel > 0) << 2) |
                        ((uint64_t)G << 3) | ((uint64_t)s->att_atomics << 40) | ((uint64_t)s->waves_per_cu << 41) |
-                       ((uint64_t)s->fused << 56);
+                       ((uint64_t)s->fused << 56) | ((uint64_t)s->use_blk << 57);
   if (!s->gstream) {
     HIPCHK(hipStreamCreateWithFlags(&s->gstream, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&s->gev[0], hipEventDisableTiming));
@@ -903,6 +994,7 @@ extern "C" int gsr_lsqr_refine(gsr_system* s, const double* b, const double* x0,
   s->eblock = 0;
   int64_t total = 0;
   int32_t steps = 0;
+  double prev = 0.0;  // ||dx|| of the previous outer step
   gsr_lsqr_result last{};
   int rc = GSR_OK;
   for (int32_t it = 0; it < o->outer_max; ++it) {
@@ -927,7 +1019,11 @@ extern "C" int gsr_lsqr_refine(gsr_system* s, const double* b, const double* x0,
       rc = fail(GSR_EHIP, "reading norms failed");
       break;
     }
-    if (sqrt(h2[0]) <= o->outer_tol * sqrt(h2[1])) break;
+    // stop on a small correction, or when the next one, predicted from the
+    // contraction between the last two, is small
+    const double d = sqrt(h2[0]), lim = o->outer_tol * sqrt(h2[1]);
+    if (d <= lim || (it > 0 && d < prev && d * (d / prev) <= lim)) break;
+    prev = d;
   }
   s->nsel = keep_sel;
   s->eblock = keep_eblock;

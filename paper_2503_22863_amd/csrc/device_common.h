@@ -74,8 +74,9 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Sum of one double per thread over a kBlock-thread workgroup, fixed order.
-// Every thread gets the result.  Uses `red` (kWavesPerBlock doubles of LDS).
+// Sum of one double per thread over an NT-thread workgroup, fixed order.
+// Every thread gets the result.  Uses `red` (NT / 64 doubles of LDS).
+template <int NT = kBlock>
 __device__ __forceinline__ double block_sum(double v, double* red) {
   v = wave_sum(v);
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
@@ -84,7 +85,7 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   __syncthreads();
   double t = 0.0;
 #pragma unroll
-  for (int i = 0; i < kWavesPerBlock; ++i) t += red[i];
+  for (int i = 0; i < NT / kWave; ++i) t += red[i];
   return t;
 }
 
@@ -115,11 +116,12 @@ __device__ __forceinline__ bool last_block(unsigned* ticket, int* flag_lds) {
   return *flag_lds != 0;
 }
 
-// Fixed-order sum of `n` partials by the whole workgroup.
+// Fixed-order sum of `n` partials by the whole (NT-thread) workgroup.
+template <int NT = kBlock>
 __device__ __forceinline__ double sum_partials(const double* p, int n, double* red) {
   double v = 0.0;
-  for (int i = threadIdx.x; i < n; i += kBlock) v += __hip_atomic_load(p + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return block_sum(v, red);
+  for (int i = threadIdx.x; i < n; i += NT) v += __hip_atomic_load(p + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return block_sum<NT>(v, red);
 }
 
 // ---- LSQR scalar steps (run by one thread) --------------------------------

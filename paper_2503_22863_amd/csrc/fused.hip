@@ -53,7 +53,9 @@ __global__ void k_att_interleave(SysView s, const double* __restrict__ x, double
 // Row indices come from the packed records; the instrumental x (at most
 // kLdsTailMax - 1 columns) from an LDS copy.
 // Two waves per SIMD: the register budget is held to 256 (it fits without spills).
-template <typename VT, int ATT_MODE>
+// PM = 1 (FP32 systems): each product a * x is formed in FP32 and summed in
+// FP64, the inner products of the FP32 form.
+template <typename VT, int ATT_MODE, int PM>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) k_fused(SysView s, int waves, const double* __restrict__ x,
                                                   const double* __restrict__ x3, const u4* __restrict__ rix,
                                                   double* __restrict__ u, double* __restrict__ gA,
@@ -158,7 +160,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
           for (int k = 0; k < 5; ++k) xa5[k] = x[5 * st + k];
         }
 #pragma unroll
-        for (int k = 0; k < 5; ++k) ax += (double)a[k] * xa5[k];
+        for (int k = 0; k < 5; ++k) ax += prod<PM>(a[k], xa5[k]);
       }
       {
         // regroup the attitude windows per row through the (now free) slab;
@@ -176,15 +178,15 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
         for (int q = 0; q < 6; ++q) {
           const dd2u pq = wl[lane * 7 + q];
           const int e0 = 2 * q, e1 = 2 * q + 1;
-          ax += (double)a[5 + 4 * (e0 % 3) + e0 / 3] * pq.x;
-          ax += (double)a[5 + 4 * (e1 % 3) + e1 / 3] * pq.y;
+          ax += prod<PM>(a[5 + 4 * (e0 % 3) + e0 / 3], pq.x);
+          ax += prod<PM>(a[5 + 4 * (e1 % 3) + e1 / 3], pq.y);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
       }
 #pragma unroll
-      for (int q = 0; q < 6; ++q) ax += (double)a[17 + q] * xil[ic[q]];
-      if (s.n_glob) ax += (double)a[23] * xg;
+      for (int q = 0; q < 6; ++q) ax += prod<PM>(a[17 + q], xil[ic[q]]);
+      if (s.n_glob) ax += prod<PM>(a[23], xg);
       const double un = uo_c + ax;
       r_out = valid ? r : -1;
       u_out = un;
@@ -193,17 +195,17 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
       sumsq += t * t;
       double p[5];
 #pragma unroll
-      for (int k = 0; k < 5; ++k) p[k] = (double)a[k] * t;
+      for (int k = 0; k < 5; ++k) p[k] = prod<PM>(a[k], t);
       if (valid) {
         if (ATT_MODE == 0) {
 #pragma unroll
           for (int axs = 0; axs < 3; ++axs)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) atomicAdd(hist + axs * s.n_att + at_c + j, (double)a[5 + 4 * axs + j] * t);
+            for (int j = 0; j < 4; ++j) atomicAdd(hist + axs * s.n_att + at_c + j, prod<PM>(a[5 + 4 * axs + j], t));
         }
 #pragma unroll
-        for (int q = 0; q < 6; ++q) atomicAdd(hist + (3 * s.n_att - hoff) + ic[q], (double)a[17 + q] * t);
-        if (s.n_glob) gsum += (double)a[23] * t;
+        for (int q = 0; q < 6; ++q) atomicAdd(hist + (3 * s.n_att - hoff) + ic[q], prod<PM>(a[17 + q], t));
+        if (s.n_glob) gsum += prod<PM>(a[23], t);
       }
       if (carry_valid && lane == 0) {
 #pragma unroll
@@ -262,24 +264,30 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
   }
 }
 
-hipError_t launch_fused(const SysView& s, StreamShape sh, int att_mode, const double* vg, const double* x3,
+hipError_t launch_fused(const SysView& s, StreamShape sh, int att_mode, int pmode, const double* vg, const double* x3,
                         const void* rix, double* u, double* gA, double* acc, Scalars* sc, Work w, hipStream_t st,
                         int init) {
   if ((att_mode != 0 && att_mode != 3) || !rix || s.n_instr + 1 > kLdsTailMax) return hipErrorInvalidValue;
+  if (pmode == 1 && s.value_type != GSR_F32) return hipErrorInvalidValue;
   const int64_t hlen = att_mode == 0 ? s.tail_len : s.tail_len - 3 * s.n_att;
   const size_t lds = sizeof(double) * (size_t)(hlen + s.n_instr);
   const dim3 g(sh.blocks), b(kBlock);
   const u4* rx = reinterpret_cast<const u4*>(rix);
-  if (s.value_type == GSR_F32) {
+  if (s.value_type == GSR_F32 && pmode == 1) {
     if (att_mode == 0)
-      hipLaunchKernelGGL((k_fused<float, 0>), g, b, lds, st, s, sh.waves, vg, x3, rx, u, gA, acc, sc, w, init);
+      hipLaunchKernelGGL((k_fused<float, 0, 1>), g, b, lds, st, s, sh.waves, vg, x3, rx, u, gA, acc, sc, w, init);
     else
-      hipLaunchKernelGGL((k_fused<float, 3>), g, b, lds, st, s, sh.waves, vg, x3, rx, u, gA, acc, sc, w, init);
+      hipLaunchKernelGGL((k_fused<float, 3, 1>), g, b, lds, st, s, sh.waves, vg, x3, rx, u, gA, acc, sc, w, init);
+  } else if (s.value_type == GSR_F32) {
+    if (att_mode == 0)
+      hipLaunchKernelGGL((k_fused<float, 0, 0>), g, b, lds, st, s, sh.waves, vg, x3, rx, u, gA, acc, sc, w, init);
+    else
+      hipLaunchKernelGGL((k_fused<float, 3, 0>), g, b, lds, st, s, sh.waves, vg, x3, rx, u, gA, acc, sc, w, init);
   } else {
     if (att_mode == 0)
-      hipLaunchKernelGGL((k_fused<double, 0>), g, b, lds, st, s, sh.waves, vg, x3, rx, u, gA, acc, sc, w, init);
+      hipLaunchKernelGGL((k_fused<double, 0, 0>), g, b, lds, st, s, sh.waves, vg, x3, rx, u, gA, acc, sc, w, init);
     else
-      hipLaunchKernelGGL((k_fused<double, 3>), g, b, lds, st, s, sh.waves, vg, x3, rx, u, gA, acc, sc, w, init);
+      hipLaunchKernelGGL((k_fused<double, 3, 0>), g, b, lds, st, s, sh.waves, vg, x3, rx, u, gA, acc, sc, w, init);
   }
   return hipGetLastError();
 }

@@ -105,6 +105,37 @@ struct AttView {
   void* sv;             // [m][12] astrometric, instrumental, global coefficients in row order (value type)
 };
 
+// Rows regrouped by attitude window, a library-owned copy for the one-pass
+// iteration when the attitude block does not fit in LDS.  Rows are grouped
+// by block g = att_start / Wb and keep star order inside a block; each block
+// is padded with zero rows to whole 64-row tiles.  A tile's coefficients are
+// stored chunk-major (chunk j of its 64 rows is 1 KB), so a wave loads its
+// rows coalesced straight into registers.  Each workgroup streams a tile range
+// of one block with that block's attitude window (3 x (Wb + 3) sums) in LDS;
+// a star's rows inside one wave's range form a segment whose five
+// astrometric sums go to P, and the tail adds the segments of each star.
+struct BlkView {
+  int ready;            // 1 once built
+  int64_t Wb, nb;       // attitude starts per block, blocks
+  int64_t ntiles, mp;   // 64-row tiles, rows including the padding (64 * ntiles)
+  int32_t G;            // workgroups of the pass (kBlkWaves waves each)
+  int64_t nseg;         // star segments
+  size_t lds;           // dynamic LDS bytes of the pass
+  void* T;              // [ntiles][CPR][64] 16-byte chunks of the coefficients
+  uint32_t* R;          // [mp][4] row records: star | att_start - g*Wb << 32 | instr (11 bits each) | end bit
+  int32_t* perm;        // [mp] original row of each position (-1: padding)
+  int32_t* wg_block;    // [G] block of each workgroup
+  int32_t* wave_tile;   // [kBlkWaves*G + 1] first tile of each wave
+  int32_t* seg_base;    // [kBlkWaves*G] segments before each wave's range
+  int32_t* bsub;        // [nb + 1] first workgroup of each block
+  int32_t* seg_ptr;     // [n_stars + 1] segments of each star in seg_list
+  int32_t* seg_list;    // [nseg]
+  double* P;            // [nseg][5] astrometric sums of each segment
+  double* Q;            // [G][3][Wb + 3] attitude window sums of each workgroup
+  double* ub;           // [mp] u in this order
+};
+constexpr int kBlkWaves = 8;  // waves per workgroup of the regrouped pass
+
 // LSQR epilogue arguments of the tail pass.
 struct TailLsqr {
   int lsqr_stage;       // 0 init, 1 iteration
@@ -163,7 +194,7 @@ hipError_t launch_con_sq(const ConView& c, double* sq, hipStream_t st);
 
 // rix: packed row indices from launch_pack_rows (required).
 // init = 1: the solve's first pass (u_scale = 1 and vg = 0 give u' = u; beta_1 with its init step)
-hipError_t launch_fused(const SysView& s, StreamShape sh, int att_mode, const double* vg, const double* x3,
+hipError_t launch_fused(const SysView& s, StreamShape sh, int att_mode, int pmode, const double* vg, const double* x3,
                         const void* rix, double* u, double* gA, double* acc, Scalars* sc, Work w, hipStream_t st,
                         int init = 0);
 // rix[r] <- {att_start[r], instr_col[r][0..5] as 16-bit pairs} (16 bytes per row; needs n_instr <= 65536)
@@ -175,6 +206,23 @@ hipError_t launch_att_interleave(const SysView& s, const double* x, double* x3, 
 hipError_t launch_tail_fused(const SysView& s, const AttView& av, int att_mode, double* x, double* acc,
                              const double* S, const double* gA, Scalars* sc, Work w, hipStream_t st,
                              int lsqr_stage = 1);
+// The same after the regrouped pass: attitude sums from its workgroup windows (gA from launch_seg_reduce).
+hipError_t launch_tail_blk(const SysView& s, const BlkView& bv, double* x, double* acc, const double* S,
+                           const double* gA, Scalars* sc, Work w, hipStream_t st, int lsqr_stage = 1);
+// gA[5s + k] <- sum of star s's segment sums P[seg][k] (block order); skipped once the solve has stopped
+hipError_t launch_seg_reduce(const SysView& s, const BlkView& bv, double* gA, Scalars* sc, hipStream_t st);
+
+// Regrouped one-pass iteration (blocked.hip).  blk_build makes the copy
+// (max_window > 0 caps Wb; lds_max: the device's LDS bytes per workgroup);
+// GSR_EINVAL if the system does not qualify, GSR_ENOMEM without memory for it.
+int blk_build(const SysView& s, BlkView* bv, int cus, int max_window, int lds_max, char* err, size_t errlen,
+              hipStream_t st);
+void blk_free(BlkView* bv);
+// ub <- src (rows in the caller's order) permuted to the regrouped order, zero on padding
+hipError_t launch_blk_permute(const BlkView& bv, const double* src, hipStream_t st);
+// The iteration's pass as launch_fused, on the regrouped copy (u in bv.ub).
+hipError_t launch_fblk(const SysView& s, const BlkView& bv, int pmode, const double* vg, const double* x3,
+                       double* acc, Scalars* sc, Work w, hipStream_t st, int init = 0);
 // Covariance column of the iteration: D[p][dcount] = w[sel[p]] / rho_i for p < nsel (after the tail);
 // the last workgroup advances dcount.  Skipped once the solve has stopped or the block is full.
 hipError_t launch_cov_gather(int64_t nsel, const int64_t* sel, const double* w, double* D, Scalars* sc, Work wk,
