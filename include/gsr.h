@@ -295,7 +295,7 @@ int gsr_set_graphs(gsr_system *sys, int32_t on);
 int gsr_set_fused(gsr_system *sys, int32_t on);
 
 /* Rows regrouped by attitude window (on by default; used by fused solves
- * without constraint equations when the attitude block does not fit in LDS).
+ * when the attitude block does not fit in LDS).
  * At the first such solve the handle makes a device copy of the rows grouped
  * by block g = att_start / Wb, star order inside a block, padded to 64-row
  * tiles, with Wb the widest window whose 3 x (Wb + 3) sums fit in LDS (at

@@ -83,9 +83,9 @@ __global__ void k_blk_permute(BlkView bv, const double* __restrict__ src) {
 }
 
 // The iteration's pass.  Workgroup b streams tiles of block wg_block[b]; its
-// waves take consecutive sub-ranges.  The tile mechanics follow the star-order
-// pass: the next tile's loads are issued once the current tile's gathers are
-// out, and the current tile's stores wait for the start of the next one.
+// waves take consecutive sub-ranges.  The next tile's loads are issued once
+// the current tile's gathers are out, and a tile's stores wait until the next
+// tile's gathers have arrived.
 template <typename VT, int PM>
 __global__ void __launch_bounds__(kBlkThreads) __attribute__((amdgpu_waves_per_eu(2)))
 k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __restrict__ x3, double* __restrict__ acc,
@@ -146,11 +146,6 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
                          (int)((B >> 22) & 0x7FFu), (int)((B >> 33) & 0x7FFu), (int)((B >> 44) & 0x7FFu)};
       const bool end = (A >> 63) != 0;
       const double uo_c = (scale == 0.0) ? 0.0 : scale * uo;
-      if (r_out >= 0) bv.ub[r_out] = u_out;
-      if (c_out >= 0) {
-#pragma unroll
-        for (int k = 0; k < 5; ++k) bv.P[c_out + k] = g_out[k];
-      }
       // gathers of x for this tile, issued before the next tile's loads
       const int64_t s0 = __shfl(star, 0, kWave);
       const int64_t ds = star - s0;
@@ -174,16 +169,24 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
       // u'_r = u_scale * u_r + (A x)_r
       double ax = 0.0;
       {
-        const int base = far ? 0 : 5 * (int)ds;
-        double xa5[5];
+        // every lane takes its star's x from the shuffle window (used on every
+        // path, so the load stays where it was issued); lanes whose star lies
+        // past the window gather per lane, consumed inside the branch: a load
+        // still pending where the paths join would make the compiler wait for
+        // the next tile's loads too
+        const int base = 5 * (int)min<int64_t>(ds, 11);
+        double axa = 0.0;
 #pragma unroll
-        for (int k = 0; k < 5; ++k) xa5[k] = __shfl(xs, base + k, kWave);
-        if (far) {
+        for (int k = 0; k < 5; ++k) axa += prod<PM>(a[k], __shfl(xs, base + k, kWave));
+        if (far && ds >= 12) {
+          double xa5[5];
 #pragma unroll
           for (int k = 0; k < 5; ++k) xa5[k] = x[5 * star + k];
-        }
+          axa = 0.0;
 #pragma unroll
-        for (int k = 0; k < 5; ++k) ax += prod<PM>(a[k], xa5[k]);
+          for (int k = 0; k < 5; ++k) axa += prod<PM>(a[k], xa5[k]);
+        }
+        ax += axa;
       }
       {
         // regroup the attitude windows per row; element e = 3j + axis is column start+j of that axis
@@ -205,6 +208,17 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
+      }
+      // the previous tile's stores, issued once this tile's gathers are in: vector
+      // memory counts stores and loads in one in-order counter, and the P stores
+      // are conditional, so the next wait on loads also waits for them; here they
+      // have this tile's arithmetic to complete (nothing that uses a gathered
+      // value may move below them)
+      order_point();
+      if (r_out >= 0) bv.ub[r_out] = u_out;
+      if (c_out >= 0) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) bv.P[c_out + k] = g_out[k];
       }
 #pragma unroll
       for (int q = 0; q < 6; ++q) ax += prod<PM>(a[17 + q], xil[ic[q]]);

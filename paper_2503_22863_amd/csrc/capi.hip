@@ -601,7 +601,7 @@ static int iteration_fused(const gsr_system* s) { return fused_for(s, s->pmode);
 // Whether a solve runs on the copy regrouped by attitude window.
 static int blk_applies(const gsr_system* s) {
   return s->blocked && s->fused && !s->blk_failed && s->s.m > 0 && s->s.tail_len > kLdsTailMax &&
-         s->s.n_instr + 1 <= kLdsTailMax && s->con.ncon == 0;
+         s->s.n_instr + 1 <= kLdsTailMax;
 }
 
 static int lsqr_begin(gsr_system* s, const double* b, const double* x0, const gsr_lsqr_opts* o, int32_t product,
@@ -610,9 +610,9 @@ static int lsqr_begin(gsr_system* s, const double* b, const double* x0, const gs
   CHK(check_product(s, product));
   if (s->s.m > 0) NEED_DEV(b, "b");
   if (x0) NEED_DEV(x0, "x0");
-  if (s->con.ncon > 0 && (product != GSR_PROD_F64 || !fused_for(s, product)))
+  if (s->con.ncon > 0 && (product != GSR_PROD_F64 || !(fused_for(s, product) || blk_applies(s))))
     return fail(GSR_EINVAL, "constraint equations need the fused iteration (FP64 products, fused on, "
-                            "attitude in LDS or bucketed)");
+                            "attitude in LDS, regrouped or bucketed)");
   CHK(ensure_vectors(s));
   if (o->precond) CHK(ensure_scale(s, st));
   s->use_blk = 0;
@@ -626,6 +626,9 @@ static int lsqr_begin(gsr_system* s, const double* b, const double* x0, const gs
     }
     s->use_blk = s->blk.ready;
   }
+  if (s->con.ncon > 0 && !s->use_blk && !fused_for(s, product))
+    return fail(GSR_EINVAL, "constraint equations need the fused iteration (no memory for the regrouped copy "
+                            "and no bucketed attitude view)");
   s->precond = o->precond;
   s->pmode = product;
   s->x0 = x0;
@@ -675,8 +678,11 @@ static int lsqr_begin(gsr_system* s, const double* b, const double* x0, const gs
     }
     HIPCHK(launch_blk_permute(s->blk, s->u, st));
     HIPCHK(launch_att_interleave(s->s, s->zvec, s->x3, st));
+    // constraint rows of u stay after the m rows of s->u (uc)
+    if (s->con.ncon > 0) HIPCHK(launch_con_aprod1(s->con, s->zvec, uc, 0.0, 1.0, s->sc, s->wk, st));
     HIPCHK(launch_fblk(s->s, s->blk, product, s->zvec, s->x3, s->acc, s->sc, s->wk, st, 1));
     HIPCHK(launch_seg_reduce(s->s, s->blk, s->gA, s->sc, st));
+    if (s->con.ncon > 0) HIPCHK(launch_con_aprod2(s->con, s->s.n_astro, uc, s->gA, s->acc, s->sc, st));
     HIPCHK(launch_tail_blk(s->s, s->blk, s->v, s->acc, S, s->gA, s->sc, s->wk, st, 0));
   } else if (s->con.ncon > 0) {
     // beta_1 u_1 = r0 and alpha_1 v_1 = S [A; C]^T u_1 through the iteration's own
@@ -747,6 +753,11 @@ static int enqueue_iteration(gsr_system* s, hipStream_t st) {
     if (s->eissued[h]) HIPCHK(hipStreamWaitEvent(st, s->eev[h], 0));
   }
   if (s->use_blk) {
+    double* uc = s->u + s->s.m;  // constraint rows of u
+    if (s->con.ncon > 0) {
+      TimeScope ts(s, 2, st);
+      HIPCHK(launch_con_aprod1(s->con, vg, uc, 0.0, 1.0, s->sc, s->wk, st));
+    }
     {
       TimeScope ts(s, 0, st);
       HIPCHK(launch_fblk(s->s, s->blk, s->pmode, vg, s->x3, s->acc, s->sc, s->wk, st));
@@ -754,6 +765,10 @@ static int enqueue_iteration(gsr_system* s, hipStream_t st) {
     {
       TimeScope ts(s, 1, st);
       HIPCHK(launch_seg_reduce(s->s, s->blk, s->gA, s->sc, st));
+    }
+    if (s->con.ncon > 0) {
+      TimeScope ts(s, 2, st);
+      HIPCHK(launch_con_aprod2(s->con, s->s.n_astro, uc, s->gA, s->acc, s->sc, st));
     }
     {
       TimeScope ts(s, 2, st);

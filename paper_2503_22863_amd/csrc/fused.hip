@@ -151,16 +151,25 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
       // u'_r = u_scale * u_r + (A x)_r, each gathered x consumed as it is formed
       double ax = 0.0;
       {
-        const int base = valid ? 5 * (int)min<int64_t>(st - sf, 12) : 0;
-        double xa5[5];
+        // every lane takes its star's x from the shuffle window (used on every
+        // path, so the load stays where it was issued); with many short stars
+        // in the tile, lanes past the window gather per lane, consumed inside
+        // the branch (a load still pending where the paths join would make the
+        // compiler wait for the next tile's loads too)
+        const int64_t dst = valid ? st - sf : 0;
+        const int base = 5 * (int)min<int64_t>(dst, 11);
+        double axa = 0.0;
 #pragma unroll
-        for (int k = 0; k < 5; ++k) xa5[k] = __shfl(xs, base + k, kWave);
-        if (span > 12) {  // many short stars in this tile: per-lane gathers
+        for (int k = 0; k < 5; ++k) axa += prod<PM>(a[k], __shfl(xs, base + k, kWave));
+        if (span > 12 && dst >= 12) {
+          double xa5[5];
 #pragma unroll
           for (int k = 0; k < 5; ++k) xa5[k] = x[5 * st + k];
-        }
+          axa = 0.0;
 #pragma unroll
-        for (int k = 0; k < 5; ++k) ax += prod<PM>(a[k], xa5[k]);
+          for (int k = 0; k < 5; ++k) axa += prod<PM>(a[k], xa5[k]);
+        }
+        ax += axa;
       }
       {
         // regroup the attitude windows per row through the (now free) slab;

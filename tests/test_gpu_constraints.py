@@ -56,16 +56,20 @@ def _sens(oracle_lib, g, o, b, **kw):
     return r1, sx, sv
 
 
-@pytest.mark.parametrize("n_stars,n_att,precond,itmax", [(300, 32, True, 15), (300, 1000, True, 25),
-                                                         (3000, 1000, True, 20), (300, 1000, False, 6)])
-def test_constrained_lsqr_matches_oracle(dev, oracle_lib, n_stars, n_att, precond, itmax):
-    print(f"[con] stars={n_stars} n_att={n_att} precond={precond} itmax={itmax}", flush=True)
+# maxw: None runs the star-order passes (bucketed attitude sums when n_att is large);
+# 0 / 64 the copy regrouped by attitude window at full / capped window width
+@pytest.mark.parametrize("n_stars,n_att,precond,itmax,maxw", [
+    (300, 32, True, 15, None), (300, 1000, True, 25, None), (3000, 1000, True, 20, None),
+    (300, 1000, False, 6, None), (300, 1000, True, 25, 64), (3000, 1000, True, 20, 0), (300, 1000, False, 6, 64)])
+def test_constrained_lsqr_matches_oracle(dev, oracle_lib, n_stars, n_att, precond, itmax, maxw):
+    print(f"[con] stars={n_stars} n_att={n_att} precond={precond} itmax={itmax} maxw={maxw}", flush=True)
     g = gsr_synth.make_system(n_stars, (10, 20), n_att, 16, 1, seed=61)
     con = _constraints(g.dims, seed=62)
     o = oracle_lib.OSystem(g, constraints=con)
     bfull = oracle_lib.known_terms(o, g.x_true, g.noise)
     ref, sx, sv = _sens(oracle_lib, g, o, bfull, atol=0, btol=0, itmax=itmax, precond=precond)
     S = dev.System.from_generated(g)
+    S.set_blocked(maxw is not None, maxw or 0)
     S.set_constraints(*con, rhs=bfull[g.dims.m:])
     if precond:
         sc = S.column_scale().cpu().numpy()
@@ -76,6 +80,7 @@ def test_constrained_lsqr_matches_oracle(dev, oracle_lib, n_stars, n_att, precon
     ex, ev = _rel(x.cpu().numpy(), ref["x"]), _rel(var.cpu().numpy(), ref["var"])
     print(f"  x {ex:.2e} (sens {sx:.1e})  var {ev:.2e} (sens {sv:.1e})", flush=True)
     assert r["itn"] == itmax
+    assert S.blocked_info()["active"] == (maxw is not None)
     assert ex <= max(1e-12, 10 * sx) and ev <= max(1e-10, 10 * sv)
     for k in ("rnorm", "anorm", "xnorm", "bnorm"):
         assert abs(r[k] - ref[k]) <= 1e-10 * abs(ref[k]), k
