@@ -121,21 +121,50 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
     u4 tmp[CPR];
     u4 rec;
     double uo;
+    // the record first: the next tile's gathers need only it
     auto fetch = [&](int64_t t) {
       const int64_t tt = min(t, T1 - 1);  // past the range: re-read its last tile (the registers are not used)
+      rec = ld_stream(rb + tt * kWave + lane);
       const u4* base = cb + tt * CPR * kWave + lane;
 #pragma unroll
       for (int j = 0; j < CPR; ++j) tmp[j] = ld_stream(base + j * kWave);
-      rec = ld_stream(rb + tt * kWave + lane);
       uo = bv.ub[tt * kWave + lane];
+    };
+    // x for the tile whose record is in `rec`: the astrometric x of the 12.8
+    // stars from its first (one contiguous load, shuffled per row later) and
+    // its 64 attitude windows of 96 bytes, loaded cooperatively (piece
+    // j*64 + lane of the tile's windows in cw[j]; consecutive lanes take
+    // consecutive 16-byte pieces of one window) and regrouped through LDS.
+    // Issued a tile ahead, right after that tile's record arrives.
+    double xs;
+    dd2u cw[6];
+    auto gathers = [&]() {
+      const int64_t st0 = __shfl((int64_t)rec.x, 0, kWave);
+      xs = x[min(5 * st0 + lane, xa_last)];
+      const int ao_l = (int)(rec.y & 0xFFFu);
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        const int c = j * kWave + lane, i = c / 6, q = c - 6 * i;
+        const int ao = __shfl(ao_l, i, kWave);
+        cw[j] = *reinterpret_cast<const dd2u*>(xw + 3 * ao + 2 * q);
+      }
     };
     double carry[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     int carry_valid = 0;
     int64_t nstart = bv.seg_base[w];  // segments begun before the current tile
-    int64_t r_out = -1, c_out = -1;
+    // Targets of the previous tile's stores.  Every lane stores on every tile, so
+    // that the in-order memory counter can be tracked exactly (a conditional
+    // store makes the compiler wait for everything at the next use of a load);
+    // before the first tile and for lanes that close no segment the targets are
+    // this wave's dummy slots (the lanes writing the dummy line merge into one
+    // request).
+    double* const du = bv.dummy + w * kBlkDummy;
+    double* u_dst = du + lane;
+    double* p_dst = du + kWave;
     double u_out = 0.0;
     double g_out[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     fetch(T0);
+    gathers();
 #pragma unroll 1
     for (int64_t t = T0; t < T1; ++t) {
       const uint64_t A = (uint64_t)rec.x | ((uint64_t)rec.y << 32);
@@ -146,18 +175,9 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
                          (int)((B >> 22) & 0x7FFu), (int)((B >> 33) & 0x7FFu), (int)((B >> 44) & 0x7FFu)};
       const bool end = (A >> 63) != 0;
       const double uo_c = (scale == 0.0) ? 0.0 : scale * uo;
-      // gathers of x for this tile, issued before the next tile's loads
       const int64_t s0 = __shfl(star, 0, kWave);
       const int64_t ds = star - s0;
       const bool far = __ballot(ds >= 12) != 0;  // more than 12 stars in the tile: per-lane gathers
-      const double xs = x[min(5 * s0 + lane, xa_last)];
-      dd2u cw[6];  // piece j*64 + lane of the tile's attitude windows
-#pragma unroll
-      for (int j = 0; j < 6; ++j) {
-        const int c = j * kWave + lane, i = c / 6, q = c - 6 * i;
-        const int ao = __shfl(aoff, i, kWave);
-        cw[j] = *reinterpret_cast<const dd2u*>(xw + 3 * ao + 2 * q);
-      }
       u4 cur[CPR];
 #pragma unroll
       for (int j = 0; j < CPR; ++j) cur[j] = tmp[j];
@@ -209,22 +229,18 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
       }
-      // the previous tile's stores, issued once this tile's gathers are in: vector
-      // memory counts stores and loads in one in-order counter, and the P stores
-      // are conditional, so the next wait on loads also waits for them; here they
-      // have this tile's arithmetic to complete (nothing that uses a gathered
-      // value may move below them)
+      // the previous tile's stores, issued once this tile's gathers are in (vector
+      // memory counts stores and loads in one in-order counter): here they have
+      // this tile's arithmetic to complete
       order_point();
-      if (r_out >= 0) bv.ub[r_out] = u_out;
-      if (c_out >= 0) {
+      *u_dst = u_out;
 #pragma unroll
-        for (int k = 0; k < 5; ++k) bv.P[c_out + k] = g_out[k];
-      }
+      for (int k = 0; k < 5; ++k) p_dst[k] = g_out[k];
 #pragma unroll
       for (int q = 0; q < 6; ++q) ax += prod<PM>(a[17 + q], xil[ic[q]]);
       if (s.n_glob) ax += prod<PM>(a[23], xg);
       const double un = uo_c + ax;
-      r_out = t * kWave + lane;
+      u_dst = bv.ub + t * kWave + lane;
       u_out = un;
       sumsq += un * un;
       // a_r * u'_r into the window, the instrumental and global sums, and the star sums
@@ -258,7 +274,7 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
         }
       }
       const int64_t sidx = nstart - 1 + __popcll(mine);
-      c_out = end ? 5 * sidx : -1;
+      p_dst = end ? bv.P + 5 * sidx : du + kWave;
 #pragma unroll
       for (int k = 0; k < 5; ++k) g_out[k] = p[k];
       nstart += __popcll(starts);
@@ -266,12 +282,11 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
 #pragma unroll
       for (int k = 0; k < 5; ++k) carry[k] = __shfl(p[k], kWave - 1, kWave);
       carry_valid = !lend;
+      gathers();  // the next tile's (rec now holds its record)
     }
-    if (r_out >= 0) bv.ub[r_out] = u_out;
-    if (c_out >= 0) {
+    *u_dst = u_out;
 #pragma unroll
-      for (int k = 0; k < 5; ++k) bv.P[c_out + k] = g_out[k];
-    }
+    for (int k = 0; k < 5; ++k) p_dst[k] = g_out[k];
   }
   if (s.n_glob) {
     const double gs = wave_sum(gsum);
@@ -309,36 +324,51 @@ hipError_t launch_fblk(const SysView& s, const BlkView& bv, int pmode, const dou
   return hipGetLastError();
 }
 
-// One star per thread: its segment ids are consecutive in seg_list and, for
-// neighbouring stars, the i-th segments are neighbours in P (same block), so
-// the loads of a wave stay contiguous.  Ids are fetched eight at a time
-// before the sums, to keep the two dependent loads from serialising.
+// One wave per group of 64 consecutive stars, one star per lane: entry i of
+// the group's list holds, lane by lane, the id of each star's i-th segment
+// (block order; padding points at the zero entry P[nseg]).  Neighbouring stars'
+// i-th segments are neighbours in P (same block), so both the id loads and the
+// P loads of a wave are contiguous; ids are taken four entries at a time so
+// that the two dependent loads overlap across entries.
 __global__ void __launch_bounds__(kBlock) k_seg_reduce(SysView s, BlkView bv, double* __restrict__ gA, Scalars* sc) {
   if (sc && (sc->done || !sc->do_v)) return;
-  for (int64_t st = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; st < s.n_stars;
-       st += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t q0 = bv.seg_ptr[st], q1 = bv.seg_ptr[st + 1];
+  const int lane = threadIdx.x & (kWave - 1);
+  for (int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; grp < bv.ngroups;
+       grp += (int64_t)gridDim.x * blockDim.x / kWave) {
+    const int32_t* L = bv.grp_list + bv.grp_base[grp] + lane;
+    const int32_t cnt = bv.grp_cnt[grp];
     double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int32_t q = q0; q < q1; q += 8) {
-      int32_t id[8];
+    int32_t i = 0;
+    for (; i + 4 <= cnt; i += 4) {
+      int32_t id[4];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) id[i] = (q + i < q1) ? bv.seg_list[q + i] : -1;
+      for (int e = 0; e < 4; ++e) id[e] = L[(int64_t)(i + e) * kWave];
+      double v[4][5];
 #pragma unroll
-      for (int i = 0; i < 8; ++i)
-        if (id[i] >= 0) {
-          const double* p = bv.P + 5 * (int64_t)id[i];
+      for (int e = 0; e < 4; ++e)
 #pragma unroll
-          for (int k = 0; k < 5; ++k) a[k] += p[k];
-        }
+        for (int k = 0; k < 5; ++k) v[e][k] = bv.P[5 * (int64_t)id[e] + k];
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int k = 0; k < 5; ++k) a[k] += v[e][k];
     }
+    for (; i < cnt; ++i) {
+      const int32_t id = L[(int64_t)i * kWave];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) gA[5 * st + k] = a[k];
+      for (int k = 0; k < 5; ++k) a[k] += bv.P[5 * (int64_t)id + k];
+    }
+    const int64_t st = grp * kWave + lane;
+    if (st < s.n_stars) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) gA[5 * st + k] = a[k];
+    }
   }
 }
 
 hipError_t launch_seg_reduce(const SysView& s, const BlkView& bv, double* gA, Scalars* sc, hipStream_t st) {
   if (s.n_stars == 0) return hipSuccess;
-  const int blocks = (int)std::min<int64_t>(16384, (s.n_stars + kBlock - 1) / kBlock);
+  const int blocks = (int)std::min<int64_t>(16384, (bv.ngroups * kWave + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_seg_reduce, dim3(blocks), dim3(kBlock), 0, st, s, bv, gA, sc);
   return hipGetLastError();
 }
@@ -351,8 +381,8 @@ hipError_t launch_blk_permute(const BlkView& bv, const double* src, hipStream_t 
 
 void blk_free(BlkView* bv) {
   for (void* p : {(void*)bv->T, (void*)bv->R, (void*)bv->perm, (void*)bv->wg_block, (void*)bv->wave_tile,
-                  (void*)bv->seg_base, (void*)bv->bsub, (void*)bv->seg_ptr, (void*)bv->seg_list, (void*)bv->P,
-                  (void*)bv->Q, (void*)bv->ub})
+                  (void*)bv->seg_base, (void*)bv->bsub, (void*)bv->grp_base, (void*)bv->grp_cnt,
+                  (void*)bv->grp_list, (void*)bv->P, (void*)bv->Q, (void*)bv->ub, (void*)bv->dummy})
     if (p) (void)hipFree(p);
   *bv = BlkView{};
 }
@@ -452,12 +482,28 @@ int blk_build(const SysView& s, BlkView* bv, int cus, int max_window, int lds_ma
   }
   const int64_t nseg = (int64_t)seg_star.size();
   bv->nseg = nseg;
-  std::vector<int32_t> seg_ptr((size_t)S + 1, 0), seg_list((size_t)std::max<int64_t>(nseg, 1));
-  for (int64_t q = 0; q < nseg; ++q) ++seg_ptr[(size_t)seg_star[(size_t)q] + 1];
-  for (int64_t i = 0; i < S; ++i) seg_ptr[(size_t)i + 1] += seg_ptr[(size_t)i];
+  // per group of 64 stars: entry i, lane l = id of star 64g+l's i-th segment (in
+  // block order, since segments are numbered block-major), padded with nseg
+  std::vector<int32_t> nper((size_t)S, 0);
+  for (int64_t q = 0; q < nseg; ++q) ++nper[(size_t)seg_star[(size_t)q]];
+  const int64_t ngroups = (S + kWave - 1) / kWave;
+  bv->ngroups = ngroups;
+  std::vector<int64_t> grp_base((size_t)ngroups + 1, 0);
+  std::vector<int32_t> grp_cnt((size_t)ngroups, 0);
+  for (int64_t g = 0; g < ngroups; ++g) {
+    int32_t c = 0;
+    for (int64_t st_ = g * kWave; st_ < std::min<int64_t>(S, (g + 1) * kWave); ++st_) c = std::max(c, nper[(size_t)st_]);
+    grp_cnt[(size_t)g] = c;
+    grp_base[(size_t)g + 1] = grp_base[(size_t)g] + (int64_t)c * kWave;
+  }
+  bv->nlist = grp_base[(size_t)ngroups];
+  std::vector<int32_t> grp_list((size_t)std::max<int64_t>(bv->nlist, 1), (int32_t)nseg);
   {
-    std::vector<int32_t> fill(seg_ptr.begin(), seg_ptr.end() - 1);
-    for (int64_t q = 0; q < nseg; ++q) seg_list[(size_t)fill[(size_t)seg_star[(size_t)q]]++] = (int32_t)q;
+    std::vector<int32_t> fill((size_t)S, 0);
+    for (int64_t q = 0; q < nseg; ++q) {
+      const int64_t st_ = seg_star[(size_t)q], g = st_ / kWave;
+      grp_list[(size_t)(grp_base[(size_t)g] + (int64_t)fill[(size_t)st_]++ * kWave + (st_ - g * kWave))] = (int32_t)q;
+    }
   }
 
   const int cpr = s.value_type == GSR_F32 ? Geo<float>::CPR : Geo<double>::CPR;
@@ -466,9 +512,12 @@ int blk_build(const SysView& s, BlkView* bv, int cus, int max_window, int lds_ma
   if (!dalloc_(&bv->T, (size_t)mp * cpr * 16) || !dalloc_((void**)&bv->R, (size_t)mp * 16) ||
       !dalloc_((void**)&bv->perm, (size_t)mp * 4) || !dalloc_((void**)&bv->wg_block, (size_t)G * 4) ||
       !dalloc_((void**)&bv->wave_tile, (size_t)(W + 1) * 4) || !dalloc_((void**)&bv->seg_base, (size_t)W * 4) ||
-      !dalloc_((void**)&bv->bsub, (size_t)(nb + 1) * 4) || !dalloc_((void**)&bv->seg_ptr, (size_t)(S + 1) * 4) ||
-      !dalloc_((void**)&bv->seg_list, seg_list.size() * 4) || !dalloc_((void**)&bv->P, (size_t)nseg * 40) ||
+      !dalloc_((void**)&bv->bsub, (size_t)(nb + 1) * 4) ||
+      !dalloc_((void**)&bv->grp_base, (size_t)(ngroups + 1) * 8) ||
+      !dalloc_((void**)&bv->grp_cnt, (size_t)ngroups * 4) || !dalloc_((void**)&bv->grp_list, grp_list.size() * 4) ||
+      !dalloc_((void**)&bv->P, (size_t)(nseg + 1) * 40) ||
       !dalloc_((void**)&bv->Q, (size_t)G * 3 * (Wb + 3) * 8) || !dalloc_((void**)&bv->ub, (size_t)mp * 8) ||
+      !dalloc_((void**)&bv->dummy, (size_t)W * kBlkDummy * 8) ||
       !dalloc_((void**)&se_d, (size_t)mp * 4)) {
     (void)hipGetLastError();
     if (se_d) (void)hipFree(se_d);
@@ -481,10 +530,13 @@ int blk_build(const SysView& s, BlkView* bv, int cus, int max_window, int lds_ma
                 hipSuccess &&
             hipMemcpyAsync(bv->seg_base, seg_base.data(), (size_t)W * 4, hipMemcpyHostToDevice, st) == hipSuccess &&
             hipMemcpyAsync(bv->bsub, bsub.data(), (size_t)(nb + 1) * 4, hipMemcpyHostToDevice, st) == hipSuccess &&
-            hipMemcpyAsync(bv->seg_ptr, seg_ptr.data(), (size_t)(S + 1) * 4, hipMemcpyHostToDevice, st) ==
+            hipMemcpyAsync(bv->grp_base, grp_base.data(), (size_t)(ngroups + 1) * 8, hipMemcpyHostToDevice, st) ==
                 hipSuccess &&
-            hipMemcpyAsync(bv->seg_list, seg_list.data(), seg_list.size() * 4, hipMemcpyHostToDevice, st) ==
-                hipSuccess;
+            hipMemcpyAsync(bv->grp_cnt, grp_cnt.data(), (size_t)ngroups * 4, hipMemcpyHostToDevice, st) ==
+                hipSuccess &&
+            hipMemcpyAsync(bv->grp_list, grp_list.data(), grp_list.size() * 4, hipMemcpyHostToDevice, st) ==
+                hipSuccess &&
+            hipMemsetAsync(bv->P + 5 * nseg, 0, 40, st) == hipSuccess;
   if (ok) {
     const int blocks = (int)std::min<int64_t>(8192, (mp + kBlock - 1) / kBlock);
     if (s.value_type == GSR_F32)

@@ -426,8 +426,8 @@ extern "C" int gsr_blocked_info(gsr_system* s, gsr_blocked_layout* info) {
   info->blocks = b.nb;
   info->padded_rows = b.mp;
   info->segments = b.nseg;
-  info->bytes = b.mp * (16 * cpr + 16 + 4 + 8) + b.nseg * (40 + 4) + (s->s.n_stars + 1) * 4 +
-                (int64_t)b.G * (3 * (b.Wb + 3) * 8 + 4 + 8 * kBlkWaves);
+  info->bytes = b.mp * (16 * cpr + 16 + 4 + 8) + (b.nseg + 1) * 40 + b.nlist * 4 + b.ngroups * 12 +
+                (int64_t)b.G * (3 * (b.Wb + 3) * 8 + 4 + 8 * kBlkWaves + 8 * kBlkWaves * kBlkDummy);
   return GSR_OK;
 }
 

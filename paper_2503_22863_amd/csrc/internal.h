@@ -128,13 +128,18 @@ struct BlkView {
   int32_t* wave_tile;   // [kBlkWaves*G + 1] first tile of each wave
   int32_t* seg_base;    // [kBlkWaves*G] segments before each wave's range
   int32_t* bsub;        // [nb + 1] first workgroup of each block
-  int32_t* seg_ptr;     // [n_stars + 1] segments of each star in seg_list
-  int32_t* seg_list;    // [nseg]
-  double* P;            // [nseg][5] astrometric sums of each segment
+  int64_t ngroups;      // groups of 64 consecutive stars
+  int64_t nlist;        // entries of grp_list
+  int64_t* grp_base;    // [ngroups + 1] start of each group's ids in grp_list
+  int32_t* grp_cnt;     // [ngroups] most segments of a star in the group
+  int32_t* grp_list;    // segment ids, per group [grp_cnt][64] (star = lane), padded with nseg
+  double* P;            // [nseg + 1][5] astrometric sums of each segment (the last entry stays zero)
   double* Q;            // [G][3][Wb + 3] attitude window sums of each workgroup
   double* ub;           // [mp] u in this order
+  double* dummy;        // [kBlkWaves*G][72] per-wave store targets of lanes with nothing to store
 };
 constexpr int kBlkWaves = 8;  // waves per workgroup of the regrouped pass
+constexpr int kBlkDummy = 72; // doubles per wave in BlkView::dummy: 64 for u, 8 (one 64-byte line) for P
 
 // LSQR epilogue arguments of the tail pass.
 struct TailLsqr {
