@@ -299,7 +299,7 @@ int gsr_set_fused(gsr_system *sys, int32_t on);
  * At the first such solve the handle makes a device copy of the rows grouped
  * by block g = att_start / Wb, star order inside a block, padded to 64-row
  * tiles, with Wb the widest window whose 3 x (Wb + 3) sums fit in LDS (at
- * most 4096 starts; max_window > 0 caps it, >= 4).  Each iteration is then
+ * most 8192 starts; max_window > 0 caps it, >= 4).  Each iteration is then
  * one pass over that copy: A v, the attitude sums in the LDS window, and the
  * star sums as per-segment partials added by the tail.  The copy takes about
  * the bytes of A plus 28 bytes per row and is kept until gsr_destroy or a

@@ -32,13 +32,13 @@ namespace gsr {
 
 constexpr int kBlkThreads = kBlkWaves * kWave;
 // static LDS of the pass: the attitude-window regroup buffers and the reduction slots
-constexpr size_t kBlkStaticLds = sizeof(double) * 2 * kBlkWaves * kWave * 7 + sizeof(double) * kBlkWaves + 64;
+constexpr size_t kBlkStaticLds = sizeof(double) * 2 * kBlkWaves * (kWave / 2) * 7 + sizeof(double) * kBlkWaves + 64;
 
-// Row records: star id, attitude start within the block's window (12 bits),
+// Row records: star id, attitude start within the block's window (13 bits),
 // six instrumental columns (11 bits each) and the end-of-segment bit.
 __device__ __forceinline__ void rec_pack(uint32_t* R, int64_t pos, uint32_t star, uint32_t off, const int* ic,
                                          uint32_t end) {
-  const uint64_t A = (uint64_t)star | ((uint64_t)off << 32) | ((uint64_t)ic[0] << 44) | ((uint64_t)end << 63);
+  const uint64_t A = (uint64_t)star | ((uint64_t)off << 32) | ((uint64_t)ic[0] << 45) | ((uint64_t)end << 63);
   const uint64_t B = (uint64_t)ic[1] | ((uint64_t)ic[2] << 11) | ((uint64_t)ic[3] << 22) | ((uint64_t)ic[4] << 33) |
                      ((uint64_t)ic[5] << 44);
   u4 v = {(unsigned)A, (unsigned)(A >> 32), (unsigned)B, (unsigned)(B >> 32)};
@@ -91,7 +91,7 @@ __global__ void __launch_bounds__(kBlkThreads) __attribute__((amdgpu_waves_per_e
 k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __restrict__ x3, double* __restrict__ acc,
        Scalars* sc, Work wk, int init) {
   constexpr int CPR = Geo<VT>::CPR;
-  __shared__ dd2u rg[kBlkWaves][kWave * 7];
+  __shared__ dd2u rg[kBlkWaves][(kWave / 2) * 7];
   __shared__ double red[kBlkWaves];
   __shared__ int flag;
   extern __shared__ double dyn[];  // window [3][W3], instrumental + global sums, instrumental x
@@ -141,7 +141,7 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
     auto gathers = [&]() {
       const int64_t st0 = __shfl((int64_t)rec.x, 0, kWave);
       xs = x[min(5 * st0 + lane, xa_last)];
-      const int ao_l = (int)(rec.y & 0xFFFu);
+      const int ao_l = (int)(rec.y & 0x1FFFu);
 #pragma unroll
       for (int j = 0; j < 6; ++j) {
         const int c = j * kWave + lane, i = c / 6, q = c - 6 * i;
@@ -170,8 +170,8 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
       const uint64_t A = (uint64_t)rec.x | ((uint64_t)rec.y << 32);
       const uint64_t B = (uint64_t)rec.z | ((uint64_t)rec.w << 32);
       const int64_t star = (int64_t)(uint32_t)A;
-      const int aoff = (int)((A >> 32) & 0xFFFu);
-      const int ic[6] = {(int)((A >> 44) & 0x7FFu), (int)(B & 0x7FFu),         (int)((B >> 11) & 0x7FFu),
+      const int aoff = (int)((A >> 32) & 0x1FFFu);
+      const int ic[6] = {(int)((A >> 45) & 0x7FFu), (int)(B & 0x7FFu),         (int)((B >> 11) & 0x7FFu),
                          (int)((B >> 22) & 0x7FFu), (int)((B >> 33) & 0x7FFu), (int)((B >> 44) & 0x7FFu)};
       const bool end = (A >> 63) != 0;
       const double uo_c = (scale == 0.0) ? 0.0 : scale * uo;
@@ -209,25 +209,36 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
         ax += axa;
       }
       {
-        // regroup the attitude windows per row; element e = 3j + axis is column start+j of that axis
+        // regroup the attitude windows per row through LDS, 32 rows per round
+        // (pieces 0..191 hold rows 0..31, pieces 192..383 rows 32..63; a padded
+        // row stride of 7 pieces keeps the row reads free of bank conflicts);
+        // element e = 3j + axis is column start+j of that axis
         dd2u* wl = rg[wid];
+        const int half = lane >> 5, rl = lane & 31;
+        double axh = ax;
 #pragma unroll
-        for (int j = 0; j < 6; ++j) {
-          const int c = j * kWave + lane, i = c / 6, q = c - 6 * i;
-          wl[i * 7 + q] = cw[j];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int h = 0; h < 2; ++h) {
 #pragma unroll
-        for (int q = 0; q < 6; ++q) {
-          const dd2u pq = wl[lane * 7 + q];
-          const int e0 = 2 * q, e1 = 2 * q + 1;
-          ax += prod<PM>(a[5 + 4 * (e0 % 3) + e0 / 3], pq.x);
-          ax += prod<PM>(a[5 + 4 * (e1 % 3) + e1 / 3], pq.y);
+          for (int j = 3 * h; j < 3 * h + 3; ++j) {
+            const int c = j * kWave + lane, ri = c / 6, q = c - 6 * ri;
+            wl[(ri - 32 * h) * 7 + q] = cw[j];
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          double d = ax;
+#pragma unroll
+          for (int q = 0; q < 6; ++q) {
+            const dd2u pq = wl[rl * 7 + q];
+            const int e0 = 2 * q, e1 = 2 * q + 1;
+            d += prod<PM>(a[5 + 4 * (e0 % 3) + e0 / 3], pq.x);
+            d += prod<PM>(a[5 + 4 * (e1 % 3) + e1 / 3], pq.y);
+          }
+          if (half == h) axh = d;
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
+        ax = axh;
       }
       // the previous tile's stores, issued once this tile's gathers are in (vector
       // memory counts stores and loads in one in-order counter): here they have
@@ -402,9 +413,9 @@ int blk_build(const SysView& s, BlkView* bv, int cus, int max_window, int lds_ma
   const int64_t m = s.m, S = s.n_stars;
   if (m <= 0 || s.n_att < 8 || s.n_instr > 2047 || S >= ((int64_t)1 << 31) || m >= ((int64_t)1 << 31))
     return failed(GSR_EINVAL, "system outside the regrouped pass's limits");
-  // window width: the largest that fits the LDS budget (at most 4096 starts: 12-bit offsets)
+  // window width: the largest that fits the LDS budget (at most 8192 starts: 13-bit offsets)
   const int64_t budget = (int64_t)lds_max - (int64_t)kBlkStaticLds - 8 * (2 * s.n_instr + s.n_glob);
-  int64_t wmax = std::min<int64_t>(budget / 24 - 3, 4096);
+  int64_t wmax = std::min<int64_t>(budget / 24 - 3, 8192);
   if (max_window > 0) wmax = std::min<int64_t>(wmax, max_window);
   if (wmax < 4) return failed(GSR_EINVAL, "not enough LDS for an attitude window");
   const int64_t nstarts = s.n_att - 3;

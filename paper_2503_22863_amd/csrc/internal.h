@@ -122,7 +122,7 @@ struct BlkView {
   int64_t nseg;         // star segments
   size_t lds;           // dynamic LDS bytes of the pass
   void* T;              // [ntiles][CPR][64] 16-byte chunks of the coefficients
-  uint32_t* R;          // [mp][4] row records: star | att_start - g*Wb << 32 | instr (11 bits each) | end bit
+  uint32_t* R;          // [mp][4] row records: star | att_start - g*Wb (13 bits) << 32 | instr (11 bits each) | end bit
   int32_t* perm;        // [mp] original row of each position (-1: padding)
   int32_t* wg_block;    // [G] block of each workgroup
   int32_t* wave_tile;   // [kBlkWaves*G + 1] first tile of each wave

@@ -193,3 +193,49 @@ def test_blocked_toggle_and_limits(dev):
     S.lsqr_end(want_var=False)
     assert S.blocked_info()["active"] == 0
     S.close()
+
+
+def test_blocked_graphs_export_and_pairs(dev, oracle_lib):
+    """On the regrouped copy: blocks of iterations replayed from a captured graph and
+    direct launches both meet the oracle's bar; the exported d_i (version 1 of the
+    covariance pipeline) match the oracle's; covariances of an index-pair list
+    (version 2) match the oracle's dense covariances of the pairs' unknowns."""
+    print("[blocked] graphs, export, pairs", flush=True)
+    g = _system(CASES["many_windows"])
+    o = oracle_lib.OSystem(g)
+    bn = oracle_lib.known_terms(o, g.x_true, g.noise)
+    n, itmax, block = g.dims.n, 25, 8
+    ref, sx, sv = _sensitivity(oracle_lib, g, o, bn, atol=0, btol=0, itmax=itmax, precond=True)
+    tol_x, tol_v = max(1e-12, 10 * sx), max(1e-10, 10 * sv)
+    S = dev.System.from_generated(g)
+    S.set_blocked(True, 40)
+    b = torch.from_numpy(bn).cuda()
+    for graphs in (True, False, True):
+        S.set_graphs(graphs)
+        x, var, r = S.lsqr_solve(b, atol=0, btol=0, itmax=itmax, precond=True)
+        ex, ev = _rel(x.cpu().numpy(), ref["x"]), _rel(var.cpu().numpy(), ref["var"])
+        print(f"  graphs={graphs}: x {ex:.2e} var {ev:.2e}", flush=True)
+        assert r["itn"] == itmax and ex <= tol_x and ev <= tol_v
+    rng = np.random.default_rng(41)
+    pairs = rng.integers(0, n, size=(300, 2))
+    pairs[:10, 1] = pairs[:10, 0]
+    U, inv = np.unique(pairs.reshape(-1), return_inverse=True)
+    inv = inv.reshape(-1, 2)
+    refp = oracle_lib.lsqr(o, bn, atol=0, btol=0, itmax=itmax, precond=True, sel=np.arange(n))
+    host = torch.empty((8, block, n), dtype=torch.float64).pin_memory()
+    S.cov_export(host, block)
+    S.cov_request_pairs(pairs, block=block)
+    try:
+        x, var, r = S.lsqr_solve(b, atol=0, btol=0, itmax=itmax, precond=True)
+        nb, lc = S.cov_export_status()
+        assert (nb - 1) * block + lc == itmax
+        D = host[:nb].reshape(-1, n)[:itmax].numpy()
+        ed = _rel(D, refp["dsel"])
+        Cref = oracle_lib.covariances(refp["dsel"][:, U], refp["scale"][U])[inv[:, 0], inv[:, 1]]
+        ep = _rel(S.cov_get_pairs().cpu().numpy(), Cref)
+        print(f"  exported d_i {ed:.2e}  pair covariances {ep:.2e}", flush=True)
+        assert ed <= max(1e-10, 10 * sv) and ep <= max(1e-10, 10 * sv)
+    finally:
+        S.cov_export(None)
+        S.cov_request_pairs([], block=64)
+    S.close()
