@@ -56,6 +56,7 @@ struct gsr_system {
   int cus = 256;
   int waves_per_cu = 32;
   int att_atomics = 0;  // 1: attitude sums by device atomics instead of the bucketed pass
+  int att_tried = 0;    // the bucketed attitude view was built (or could not be) at its first use
   StreamShape sh{};
   AttView av{};
   Scalars* sc = nullptr;
@@ -196,6 +197,21 @@ static void reshape(gsr_system* s) { s->sh = stream_shape(s->s, s->cus, s->waves
 
 static int att_mode(const gsr_system* s) { return att_mode_of(s->s, s->av, s->att_atomics); }
 
+// The attitude-bucketed copy used by the star-order passes when the attitude
+// block does not fit in LDS, built at its first use (standalone aprod 2, solves
+// that do not run on the regrouped copy).  Without memory for it those passes
+// sum the attitude columns with device atomics.
+static int ensure_att(gsr_system* s, hipStream_t st) {
+  if (s->att_tried || s->s.tail_len <= kLdsTailMax || s->s.m == 0) return GSR_OK;
+  s->att_tried = 1;
+  HIPCHK(hipStreamSynchronize(st));
+  char msg[256] = "";
+  const int rc = att_build(s->s, &s->av, s->cus, msg, sizeof msg, st);
+  if (rc == GSR_ENOMEM) return GSR_OK;  // att_mode falls back to atomics (view not ready)
+  if (rc != GSR_OK) return fail(rc, "attitude view: %s", msg);
+  return GSR_OK;
+}
+
 static void con_free(gsr_system* s) {
   for (const void* p : {(const void*)s->con.ptr, (const void*)s->con.col, (const void*)s->con.val,
                         (const void*)s->con.tile_e, (const void*)s->con.tile_r, (const void*)s->con.tmp,
@@ -333,16 +349,6 @@ extern "C" int gsr_create(gsr_system** out, const gsr_dims* d, const void* vals,
   if (hb[0] != ~0ull) return bail(fail(GSR_EINVAL, "att_start / instr_col out of range at row %llu", hb[0]));
   v.has_empty_stars = hb[2] != 0;
   reshape(s);
-  if (v.tail_len > kLdsTailMax && v.m > 0) {
-    // attitude block too large for LDS: build the attitude-bucketed copy
-    char msg[256] = "";
-    rc = att_build(v, &s->av, s->cus, msg, sizeof msg, st);
-    if (rc == GSR_ENOMEM) {
-      s->att_atomics = 1;  // not enough memory for the copy: device atomics
-    } else if (rc != GSR_OK) {
-      return bail(fail(rc, "attitude view: %s", msg));
-    }
-  }
   if (v.m > 0 && v.n_instr <= 65536) {
     // packed row indices for the fused iteration pass; without memory for them
     // iterations run as separate aprod 1 / aprod 2 passes
@@ -378,7 +384,7 @@ extern "C" int gsr_set_tuning(gsr_system* s, int32_t waves_per_cu, int32_t att_a
   if (waves_per_cu < 1 || waves_per_cu > 256 || (att_atomics != 0 && att_atomics != 1))
     return fail(GSR_EINVAL, "waves_per_cu in [1,256], att_atomics in {0,1}");
   s->waves_per_cu = waves_per_cu;
-  s->att_atomics = att_atomics || !s->av.ready;
+  s->att_atomics = att_atomics;
   reshape(s);
   return GSR_OK;
 }
@@ -516,6 +522,9 @@ extern "C" int gsr_aprod1(gsr_system* s, const double* x, double* y, double scal
 // aprod 2 in LSQR form (sc != nullptr: scale / 1/beta from the device scalars) or standalone.
 static int aprod2_launches(gsr_system* s, const double* y, double* x, const double* S, double scale, int32_t product,
                            int square, Scalars* sc, int lsqr_stage, hipStream_t st) {
+  // the column norms (square) are taken once: without the bucketed view they use
+  // device atomics rather than build it for that alone
+  if (!square) CHK(ensure_att(s, st));
   const int mode = att_mode(s);
   {
     TimeScope ts(s, 1, st);
@@ -610,6 +619,7 @@ static int lsqr_begin(gsr_system* s, const double* b, const double* x0, const gs
   CHK(check_product(s, product));
   if (s->s.m > 0) NEED_DEV(b, "b");
   if (x0) NEED_DEV(x0, "x0");
+  if (!blk_applies(s)) CHK(ensure_att(s, st));
   if (s->con.ncon > 0 && (product != GSR_PROD_F64 || !(fused_for(s, product) || blk_applies(s))))
     return fail(GSR_EINVAL, "constraint equations need the fused iteration (FP64 products, fused on, "
                             "attitude in LDS, regrouped or bucketed)");
@@ -626,6 +636,7 @@ static int lsqr_begin(gsr_system* s, const double* b, const double* x0, const gs
     }
     s->use_blk = s->blk.ready;
   }
+  if (!s->use_blk) CHK(ensure_att(s, st));
   if (s->con.ncon > 0 && !s->use_blk && !fused_for(s, product))
     return fail(GSR_EINVAL, "constraint equations need the fused iteration (no memory for the regrouped copy "
                             "and no bucketed attitude view)");
