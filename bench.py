@@ -305,6 +305,9 @@ def main():
     ap.add_argument("--star-order", action="store_true",
                     help="iterate on the rows in star order (bucketed attitude pass) instead of the copy "
                          "regrouped by attitude window")
+    ap.add_argument("--stream-probe", action="store_true",
+                    help="run the memory-system calibration (the row pass's byte stream with its u store in "
+                         "several forms) and print its results")
     ap.add_argument("--syrk-bench", action="store_true",
                     help="time the covariance SYRK alone (k = 4000) and print its MFMA rate instead")
     args = ap.parse_args()
@@ -312,6 +315,19 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU row split is not built.",
               file=sys.stderr)
         sys.exit(2)
+    if args.stream_probe:
+        # a child process of its own, started before this one touches the GPU
+        import subprocess
+
+        probe = os.path.join(ROOT, "paper_2503_22863_amd", "stream_probe")
+        if not os.path.exists(probe):
+            raise SystemExit("stream_probe is not built (run the package build first)")
+        r = subprocess.run([probe], capture_output=True, text=True, timeout=600)
+        if r.returncode != 0:
+            raise SystemExit(f"stream_probe failed ({r.returncode}): {r.stderr.strip()}")
+        rows = [json.loads(line) for line in r.stdout.splitlines() if line.startswith("{")]
+        print(json.dumps({"stream_probe": rows}), flush=True)
+        return
 
     import numpy as np
     import torch

@@ -43,11 +43,26 @@ def _compile(src: str) -> str:
     return obj
 
 
+PROBE = os.path.join(HERE, "stream_probe")
+
+
+def _build_probe() -> str:
+    """The memory-system calibration program (a standalone executable, not part of libgsr)."""
+    cmd = [HIPCC, *FLAGS, os.path.join(CSRC, "stream_probe.hip"), "-o", PROBE + ".tmp"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for stream_probe.hip:\n{r.stdout}\n{r.stderr}")
+    os.replace(PROBE + ".tmp", PROBE)
+    return PROBE
+
+
 def build() -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    with cf.ThreadPoolExecutor(len(srcs)) as ex:
+    with cf.ThreadPoolExecutor(len(srcs) + 1) as ex:
+        probe = ex.submit(_build_probe)
         objs = list(ex.map(_compile, srcs))
+        probe.result()
     tmp = OUT + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)

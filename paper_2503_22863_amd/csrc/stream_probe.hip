@@ -1,0 +1,160 @@
+// Memory-system calibration for the row pass (a standalone program, not part
+// of libgsr): streams exactly the regrouped pass's per-row bytes — 64-row tiles
+// of 12 chunk-major 16-byte chunks, a 16-byte record and an 8-byte u per row,
+// one tile prefetched, 8 waves per workgroup and one workgroup per CU (the
+// pass's LDS footprint) — with the per-row u store in several forms, to show
+// what a pass that must write u can reach on this chip.
+//
+//   stream_probe [rows]      (default 70,004,736: the 10^6-star share)
+//
+// One JSON object per line: {"store": ..., "ms": ..., "read_GBps": ...}.
+#include <hip/hip_runtime.h>
+#include <stdio.h>
+#include <stdlib.h>
+
+typedef unsigned u4 __attribute__((ext_vector_type(4)));
+
+#define CHK(x)                                                                        \
+  do {                                                                                \
+    hipError_t e_ = (x);                                                              \
+    if (e_ != hipSuccess) {                                                           \
+      fprintf(stderr, "stream_probe: %s at line %d\n", hipGetErrorString(e_), __LINE__); \
+      exit(1);                                                                        \
+    }                                                                                 \
+  } while (0)
+
+constexpr int kChunks = 12;    // 16-byte chunks per row (24 FP64 coefficients)
+constexpr int kWaves = 8;      // waves per workgroup
+constexpr int kStage = 16;     // tiles per burst in the LDS-staged form
+
+// Store forms: 0 none, 1 plain, 2 nontemporal, 3 into a 1 MB wrap-around buffer
+// (never reaches HBM), 4 from every fourth wave only, 5 staged in LDS and
+// written kStage tiles at a time.
+template <int STORE>
+__global__ void __launch_bounds__(kWaves * 64) k_stream(const u4* __restrict__ T, const u4* __restrict__ R,
+                                                         double* __restrict__ u, long ntiles, double* sink) {
+  extern __shared__ double lds[];  // sized to leave one workgroup per CU
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const long W = (long)gridDim.x * kWaves, w = (long)blockIdx.x * kWaves + wid;
+  const long t0 = ntiles * w / W, t1 = ntiles * (w + 1) / W;
+  double acc = 0.0;
+  if (t0 < t1) {
+    u4 tmp[kChunks];
+    u4 rec;
+    double uo;
+    auto fetch = [&](long t) {
+      const long tt = t < t1 ? t : t0;  // past the range: re-read its first tile (unused)
+      const u4* base = T + tt * kChunks * 64 + lane;
+#pragma unroll
+      for (int j = 0; j < kChunks; ++j) tmp[j] = __builtin_nontemporal_load(base + j * 64);
+      rec = __builtin_nontemporal_load(R + tt * 64 + lane);
+      uo = u[tt * 64 + lane];
+    };
+    fetch(t0);
+    long r_out = -1;
+    double u_out = 0.0;
+    for (long t = t0; t < t1; ++t) {
+      u4 cur[kChunks];
+#pragma unroll
+      for (int j = 0; j < kChunks; ++j) cur[j] = tmp[j];
+      const u4 rc = rec;
+      const double uc = uo;
+      __builtin_amdgcn_sched_barrier(0);
+      fetch(t + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      if (r_out >= 0) {
+        if (STORE == 1) u[r_out] = u_out;
+        if (STORE == 2) __builtin_nontemporal_store(u_out, u + r_out);
+        if (STORE == 3) u[r_out & ((1 << 17) - 1)] = u_out;
+        if (STORE == 4 && (w & 3) == 0) u[r_out] = u_out;
+        if (STORE == 5) {
+          double* st = lds + wid * kStage * 64;
+          const long k = (t - 1 - t0) % kStage;
+          st[k * 64 + lane] = u_out;
+          if (k == kStage - 1) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const long base = r_out - lane - (kStage - 1) * 64;
+#pragma unroll
+            for (int q = 0; q < kStage; ++q) u[base + q * 64 + lane] = st[q * 64 + lane];
+          }
+        }
+      }
+      double s = uc + (double)rc.x;
+#pragma unroll
+      for (int j = 0; j < kChunks; ++j) {
+        const double2 d = *reinterpret_cast<const double2*>(&cur[j]);
+        s += d.x * 1.0000001 + d.y;
+      }
+      r_out = t * 64 + lane;
+      u_out = s;
+      acc += s;
+    }
+    if ((STORE == 1 || STORE == 2) && r_out >= 0) u[r_out] = u_out;
+  }
+  if (acc == 1.2345) sink[0] = acc;  // keeps the sums live
+}
+
+template <int STORE>
+static void run(const char* name, const u4* T, const u4* R, double* u, long ntiles, double* sink, int blocks,
+                size_t lds) {
+  (void)hipFuncSetAttribute((const void*)k_stream<STORE>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  (void)hipGetLastError();
+  hipEvent_t a, b;
+  CHK(hipEventCreate(&a));
+  CHK(hipEventCreate(&b));
+  for (int i = 0; i < 2; ++i)
+    hipLaunchKernelGGL(k_stream<STORE>, dim3(blocks), dim3(kWaves * 64), lds, 0, T, R, u, ntiles, sink);
+  CHK(hipGetLastError());
+  const int reps = 10;
+  CHK(hipEventRecord(a));
+  for (int i = 0; i < reps; ++i)
+    hipLaunchKernelGGL(k_stream<STORE>, dim3(blocks), dim3(kWaves * 64), lds, 0, T, R, u, ntiles, sink);
+  CHK(hipEventRecord(b));
+  CHK(hipEventSynchronize(b));
+  float ms = 0.0f;
+  CHK(hipEventElapsedTime(&ms, a, b));
+  ms /= reps;
+  const double read = (double)ntiles * 64 * (kChunks * 16 + 16 + 8);
+  printf("{\"store\": \"%s\", \"rows\": %ld, \"ms\": %.4f, \"read_GBps\": %.1f}\n", name, ntiles * 64, ms,
+         read / (ms * 1e-3) / 1e9);
+  fflush(stdout);
+  CHK(hipEventDestroy(a));
+  CHK(hipEventDestroy(b));
+}
+
+int main(int argc, char** argv) {
+  const long rows = argc > 1 ? atol(argv[1]) : 70004736L;
+  const long ntiles = (rows + 63) / 64;
+  if (ntiles < 1) return 1;
+  int dev = 0, cus = 256, lmax = 65536;
+  CHK(hipGetDevice(&dev));
+  CHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  CHK(hipDeviceGetAttribute(&lmax, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  // more than half of a CU's LDS per workgroup: one workgroup of 8 waves per CU
+  const size_t lds = (size_t)lmax * 3 / 4;
+  if (lds < sizeof(double) * kWaves * kStage * 64) return 1;
+  u4 *T, *R;
+  double *u, *sink;
+  CHK(hipMalloc(&T, (size_t)ntiles * 64 * kChunks * 16));
+  CHK(hipMalloc(&R, (size_t)ntiles * 64 * 16));
+  CHK(hipMalloc(&u, (size_t)ntiles * 64 * 8));
+  CHK(hipMalloc(&sink, 64));
+  CHK(hipMemset(T, 0, (size_t)ntiles * 64 * kChunks * 16));
+  CHK(hipMemset(R, 0, (size_t)ntiles * 64 * 16));
+  CHK(hipMemset(u, 0, (size_t)ntiles * 64 * 8));
+  CHK(hipDeviceSynchronize());
+  const int blocks = 2 * cus;
+  run<0>("none", T, R, u, ntiles, sink, blocks, lds);
+  run<1>("plain", T, R, u, ntiles, sink, blocks, lds);
+  run<2>("nontemporal", T, R, u, ntiles, sink, blocks, lds);
+  run<3>("1 MB wrap-around buffer", T, R, u, ntiles, sink, blocks, lds);
+  run<4>("every fourth wave only", T, R, u, ntiles, sink, blocks, lds);
+  run<5>("LDS-staged, 16 tiles per burst", T, R, u, ntiles, sink, blocks, lds);
+  CHK(hipFree(T));
+  CHK(hipFree(R));
+  CHK(hipFree(u));
+  CHK(hipFree(sink));
+  return 0;
+}
