@@ -71,6 +71,29 @@ def load_traffic(kernel: str, workload: str):
     return e.get("bytes_per_launch")
 
 
+def stream_copy_gbps(nbytes: int = 1 << 31, reps: int = 5) -> float:
+    """Device-to-device copy of nbytes (read + written), HIP events: the measured
+    stream-copy rate that a read-and-write pass can be held against."""
+    import torch
+
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+    a.fill_(1.0)
+    c = torch.empty_like(a)
+    for _ in range(2):
+        c.copy_(a)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(reps):
+        c.copy_(a)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / reps
+    del a, c
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(full_m: int, budget_s: float = 15.0):
     """The oracle, as it stands, on a bounded sample: a 20,000-star system of the same
     construction (same attitude / instrumental sizes, same distributions)."""
@@ -425,6 +448,7 @@ def main():
     att_ms = tm["aprod2_ms"] / max(1, tm["aprod2_n"])
     kname, by = pass_bytes(S.blocked_info(), m, ns)
     achieved = by / (f_ms * 1e-3) / 1e9
+    copy_gbps = stream_copy_gbps()
     workload = args.workload
     traffic = load_traffic(kname, workload)
     out = {
@@ -447,7 +471,8 @@ def main():
                    "global_batch": m, "seq_len": None, "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "bytes_per_launch": by, "avg_ms": f_ms},
+                     "bytes_per_launch": by, "avg_ms": f_ms,
+                     "stream_copy_GBps": copy_gbps, "frac_of_stream_copy": achieved / copy_gbps},
         "iteration_ms": {"row_pass": f_ms, "second_pass": att_ms,
                          "tail": tm["tail_ms"] / max(1, tm["tail_n"]),
                          "update": tm["update_ms"] / max(1, tm["update_n"])},
