@@ -83,9 +83,11 @@ __global__ void k_blk_permute(BlkView bv, const double* __restrict__ src) {
 }
 
 // The iteration's pass.  Workgroup b streams tiles of block wg_block[b]; its
-// waves take consecutive sub-ranges.  The next tile's loads are issued once
-// the current tile's gathers are out, and a tile's stores wait until the next
-// tile's gathers have arrived.
+// waves take consecutive sub-ranges.  Per tile a wave waits for the tile's
+// record, chunks and u (loaded one tile ahead) and for its x gathers (issued
+// at the end of the previous tile), issues the next tile's loads, forms the
+// products, stores the previous tile's u and segment sums once the gathered
+// values are in, and ends by issuing the next tile's gathers.
 template <typename VT, int PM>
 __global__ void __launch_bounds__(kBlkThreads) __attribute__((amdgpu_waves_per_eu(2)))
 k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __restrict__ x3, double* __restrict__ acc,

@@ -234,3 +234,22 @@ def test_fp32_refinement_reaches_fp64_solution(oracle_lib):
     ref_out = oracle_lib.lsqr_refine(o, b, inner_atol=1e-6, inner_btol=1e-6, outer_max=10, outer_tol=1e-11)
     assert ref_out["outer_steps"] >= 2
     assert _rel(ref_out["x"], ref["x"]) < 1e-10
+
+
+@pytest.mark.parametrize("inner_tol", [1e-5, 1e-6, 1e-7])
+def test_refinement_stop_rule_predicts_the_next_correction(oracle_lib, inner_tol):
+    """The refinement stops when the correction, or the next one predicted from the
+    contraction between the last two, is at most outer_tol ||x||.  Pin of that rule:
+    one more outer step taken by hand (residual with FP64 products, inner FP32-product
+    LSQR, as the loop does) gives a correction within 10 outer_tol ||x||."""
+    g = gsr_synth.tiny().as_f32()
+    o = oracle_lib.OSystem(g)
+    b = oracle_lib.known_terms(o, g.x_true, g.noise)
+    tol = 1e-11
+    out = oracle_lib.lsqr_refine(o, b, inner_atol=inner_tol, inner_btol=inner_tol, outer_max=10, outer_tol=tol)
+    x = out["x"]
+    r = b - oracle_lib.aprod1(o, x)
+    dx = oracle_lib.lsqr(o, r, atol=inner_tol, btol=inner_tol, itmax=1000, precond=True, mode=oracle_lib.P32)["x"]
+    nxt = np.linalg.norm(dx) / np.linalg.norm(x)
+    assert out["outer_steps"] < 10  # stopped by the rule, not by outer_max
+    assert nxt <= 10 * tol, nxt
