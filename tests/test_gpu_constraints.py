@@ -127,3 +127,28 @@ def test_constraints_need_the_fused_iteration(dev):
     with pytest.raises(dev.GsrError):  # columns must be strictly increasing
         S.set_constraints(np.array([0, 2]), np.array([3, 3]), np.array([1.0, 1.0]), rhs=np.array([0.0]))
     S.close()
+
+
+def test_constrained_fp32_storage_on_regrouped_copy(dev, oracle_lib):
+    """FP32-stored coefficients with FP64 products and constraint equations, on the
+    copy regrouped by attitude window, against the FP64 oracle on the same values."""
+    print("[con] FP32 storage, regrouped copy", flush=True)
+    g32 = gsr_synth.make_system(300, (10, 20), 1000, 16, 1, seed=64).as_f32()
+    g64 = gsr_synth.make_system(300, (10, 20), 1000, 16, 1, seed=64)
+    g64.vals = g32.vals.astype(np.float64)
+    con = _constraints(g64.dims, seed=65)
+    o = oracle_lib.OSystem(g64, constraints=con)
+    bfull = oracle_lib.known_terms(o, g64.x_true, g64.noise)
+    ref, sx, sv = _sens(oracle_lib, g64, o, bfull, atol=0, btol=0, itmax=25, precond=True)
+    S = dev.System.from_generated(g32)
+    S.set_blocked(True, 64)
+    S.set_constraints(*con, rhs=bfull[g64.dims.m:])
+    x, var, r = S.lsqr_solve(torch.from_numpy(bfull[: g64.dims.m]).cuda(), atol=0, btol=0, itmax=25, precond=True,
+                             product="f64")
+    assert S.blocked_info()["active"] == 1 and r["itn"] == 25
+    ex, ev = _rel(x.cpu().numpy(), ref["x"]), _rel(var.cpu().numpy(), ref["var"])
+    print(f"  x {ex:.2e} (sens {sx:.1e})  var {ev:.2e} (sens {sv:.1e})", flush=True)
+    assert ex <= max(1e-12, 10 * sx) and ev <= max(1e-10, 10 * sv)
+    with pytest.raises(dev.GsrError):  # FP32 products with constraint equations are refused
+        S.lsqr_solve(torch.from_numpy(bfull[: g64.dims.m]).cuda(), itmax=3, product="f32")
+    S.close()
