@@ -109,7 +109,6 @@ __global__ void __launch_bounds__(kBlock) k_aprod1(SysView s, int waves, const d
       // stars of the tile (valid when the last row's star is among the 64 boundaries)
       const int64_t span = __popcll(__ballot(bv_c <= t0 + nrow - 1)) + 1;
       scur = tile_next(s, bv_c, t0, sf);
-      if (r_out >= 0) y[r_out] = y_out;
       // gathers of x for this tile, issued before the next tile's loads
       const double xs = x[min(5 * sf + lane, xa_last)];
       double gx[kSlots];
@@ -127,6 +126,10 @@ __global__ void __launch_bounds__(kBlock) k_aprod1(SysView s, int waves, const d
       order_point();
       fetch(t0 + kWave);
       order_point();
+      // the previous tile's store, after the next tile's loads: loads and stores
+      // share one in-order counter and this store is conditional, so the next wait
+      // on loads also waits for it; here the tile's arithmetic covers its latency
+      if (r_out >= 0) y[r_out] = y_out;
       u4 mine[CPR];
       lds_get<CPR>(nrow, slabs[wid], lane, mine);
       const int64_t st = tile_star(s, t0, lane, bnds[wid], sf);
@@ -134,18 +137,28 @@ __global__ void __launch_bounds__(kBlock) k_aprod1(SysView s, int waves, const d
       __builtin_memcpy(a, mine, sizeof(a));
 #pragma unroll
       for (int q = 0; q < 6; ++q) gx[17 + q] = xil[ic[q]];
-      {
-        const int base = valid ? 5 * (int)min<int64_t>(st - sf, 12) : 0;
-#pragma unroll
-        for (int k = 0; k < 5; ++k) gx[k] = __shfl(xs, base + k, kWave);
-      }
-      if (span > 12) {  // many short stars in this tile: per-lane gathers
-#pragma unroll
-        for (int k = 0; k < 5; ++k) gx[k] = x[5 * st + k];
-      }
       double acc = 0.0;
+      {
+        // every lane takes its star's x from the shuffle window (used on every
+        // path, so the load stays where it was issued); with many short stars in
+        // the tile, lanes past the window gather per lane, consumed inside the
+        // branch (a load still pending where the paths join would make the
+        // compiler wait for the next tile's loads too)
+        const int64_t dst = valid ? st - sf : 0;
+        const int base = 5 * (int)min<int64_t>(dst, 11);
 #pragma unroll
-      for (int k = 0; k < 23; ++k) acc += prod<PM>(a[k], gx[k]);
+        for (int k = 0; k < 5; ++k) acc += prod<PM>(a[k], __shfl(xs, base + k, kWave));
+        if (span > 12 && dst >= 12) {
+          double xa5[5];
+#pragma unroll
+          for (int k = 0; k < 5; ++k) xa5[k] = x[5 * st + k];
+          acc = 0.0;
+#pragma unroll
+          for (int k = 0; k < 5; ++k) acc += prod<PM>(a[k], xa5[k]);
+        }
+      }
+#pragma unroll
+      for (int k = 5; k < 23; ++k) acc += prod<PM>(a[k], gx[k]);
       if (s.n_glob) acc += prod<PM>(a[23], xg);
       const double yn = yo_c + ax * acc;
       r_out = valid ? t0 + lane : -1;
@@ -246,10 +259,6 @@ __global__ void __launch_bounds__(kBlock) k_aprod2(SysView s, int waves, const v
       // stars of the tile (valid when the last row's star is among the 64 boundaries)
       const int64_t span = __popcll(__ballot(bv_c <= t0 + nrow - 1)) + 1;
       scur = tile_next(s, bv_c, t0, sf);
-      if (c_out >= 0) {
-#pragma unroll
-        for (int k = 0; k < 5; ++k) x[c_out + k] = x_out[k];
-      }
       // old x and column scales of the tile's stars, one contiguous load each
       const int64_t ia = min(5 * sf + lane, xa_last);
       const double xo_l = x[ia];
@@ -259,6 +268,12 @@ __global__ void __launch_bounds__(kBlock) k_aprod2(SysView s, int waves, const v
       order_point();
       fetch(t0 + kWave);
       order_point();
+      // the previous tile's finished star, stored after the next tile's loads (see
+      // k_aprod1; it is a star before this tile's, so no load of this tile reads it)
+      if (c_out >= 0) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) x[c_out + k] = x_out[k];
+      }
       u4 mine[CPR];
       lds_get<CPR>(nrow, slabs[wid], lane, mine);
       int64_t rbeg, rend;
@@ -311,30 +326,35 @@ __global__ void __launch_bounds__(kBlock) k_aprod2(SysView s, int waves, const v
         }
       }
       const bool ends_here = valid && (r == rend - 1);
-      // old x and scale of the lane's star
-      double xo[5], so[5];
+      // new x of the lane's star from its old x and scale: from the shuffle window
+      // (used on every path), or, with many short stars in the tile, from per-lane
+      // loads consumed inside the branch (see k_aprod1)
+      double xn[5];
       {
-        const int base = valid ? 5 * (int)min<int64_t>(st - sf, 12) : 0;
+        const int64_t dst = valid ? st - sf : 0;
+        const int base = 5 * (int)min<int64_t>(dst, 11);
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
-          xo[k] = __shfl(xo_l, base + k, kWave);
-          so[k] = __shfl(so_l, base + k, kWave);
+          const double xo = __shfl(xo_l, base + k, kWave), so = __shfl(so_l, base + k, kWave);
+          xn[k] = ((scale == 0.0) ? 0.0 : scale * xo) + (S ? so : 1.0) * p[k];
         }
-      }
-      if (span > 12) {  // many short stars in this tile: per-lane loads
+        if (span > 12 && dst >= 12) {
+          double xo[5], so[5];
 #pragma unroll
-        for (int k = 0; k < 5; ++k) {
-          xo[k] = x[5 * st + k];
-          so[k] = Sx[5 * st + k];
+          for (int k = 0; k < 5; ++k) {
+            xo[k] = x[5 * st + k];
+            so[k] = Sx[5 * st + k];
+          }
+#pragma unroll
+          for (int k = 0; k < 5; ++k) xn[k] = ((scale == 0.0) ? 0.0 : scale * xo[k]) + (S ? so[k] : 1.0) * p[k];
         }
       }
       c_out = ends_here ? 5 * st : -1;
       if (ends_here) {
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
-          const double xn = ((scale == 0.0) ? 0.0 : scale * xo[k]) + (S ? so[k] : 1.0) * p[k];
-          x_out[k] = xn;
-          sumsq += xn * xn;
+          x_out[k] = xn[k];
+          sumsq += xn[k] * xn[k];
         }
       }
       // carry the last run of the tile if its star continues
