@@ -85,11 +85,15 @@ const char *gsr_version(void);
  */
 int gsr_create(gsr_system **out, const gsr_dims *d, const void *vals, const int64_t *star_row_ptr,
                const int32_t *att_start, const int32_t *instr_col, gsr_stream stream);
-/* When 3*n_att + n_instr + n_glob exceeds 2048 (the attitude block does not fit
- * in LDS), gsr_create also builds a library-owned copy of the 12 attitude
- * coefficients of every row grouped by attitude start (12 values + 12 bytes of
- * index data per row, e.g. 7 GB for 7e7 FP64 rows) so that aprod 2 needs no
- * global atomics; if that allocation fails the handle falls back to atomics. */
+/* gsr_create also packs the instrumental columns and attitude start of each
+ * row (16 bytes per row) for the one-pass iteration.  When 3*n_att + n_instr +
+ * n_glob exceeds 2048 (the attitude block does not fit in LDS) the handle makes
+ * further library-owned copies at their first use: the rows regrouped by
+ * attitude window for LSQR solves (gsr_set_blocked), and, for gsr_aprod2 and
+ * solves not on that copy, the 12 attitude coefficients of every row grouped
+ * by attitude start plus the other 12 in row order (about 200 bytes per FP64
+ * row), so that aprod 2 needs no global atomics.  If an allocation fails the
+ * handle falls back to the star-order passes, or to atomics. */
 /* Free the handle's workspaces (synchronises the device first).  NULL is a no-op. */
 int gsr_destroy(gsr_system *sys);
 
@@ -270,10 +274,10 @@ int gsr_cov_from_export(const double *blocks, int64_t n, int32_t block, int64_t 
  */
 int gsr_syrk(const double *D, int64_t k, int64_t cols, int64_t ldd, double *C, gsr_stream stream);
 
-/* Launch tuning of the row-streaming kernels: waves per CU (1..256), and,
- * when the attitude block does not fit in LDS, att_atomics = 1 to sum the
- * attitude part of aprod 2 with device-scope FP64 atomics instead of the
- * attitude-bucketed pass (for comparison; much slower).  Results are
+/* Launch tuning of the star-order row-streaming kernels: waves per CU
+ * (1..256), and, when the attitude block does not fit in LDS, att_atomics = 1
+ * to sum the attitude part of aprod 2 with device-scope FP64 atomics instead
+ * of the attitude-bucketed pass (for comparison; much slower).  Results are
  * unchanged up to the order of FP64 additions. */
 int gsr_set_tuning(gsr_system *sys, int32_t waves_per_cu, int32_t att_atomics);
 
