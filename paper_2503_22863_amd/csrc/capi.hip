@@ -78,7 +78,7 @@ struct gsr_system {
   int blk_failed = 0;    // the copy could not be built (memory or limits): not tried again
   int use_blk = 0;       // the current solve runs on it
   // refinement buffers
-  double *r = nullptr, *xr = nullptr, *dx = nullptr, *nrm2 = nullptr;
+  double *xr = nullptr, *xn = nullptr, *nrm2 = nullptr;
   // covariances
   int64_t nsel = 0;
   int32_t dblock = 64;
@@ -249,9 +249,8 @@ static void release(gsr_system* s) {
     if (e) (void)hipEventDestroy(e);
   dfree(s->x3);
   dfree(s->rix);
-  dfree(s->r);
   dfree(s->xr);
-  dfree(s->dx);
+  dfree(s->xn);
   dfree(s->nrm2);
   dfree(s->sel);
   dfree(s->D);
@@ -613,8 +612,11 @@ static int blk_applies(const gsr_system* s) {
          s->s.n_instr + 1 <= kLdsTailMax;
 }
 
+// fold_r0: on the regrouped copy, form r0 = b - A x0 inside the first pass
+// (u' = u + A vg with vg = -x0, FP64 products) instead of by a separate aprod 1;
+// the rounding of r0 then follows the pass's summation order.
 static int lsqr_begin(gsr_system* s, const double* b, const double* x0, const gsr_lsqr_opts* o, int32_t product,
-                      hipStream_t st) {
+                      hipStream_t st, int fold_r0 = 0) {
   CHK(check_opts(o));
   CHK(check_product(s, product));
   if (s->s.m > 0) NEED_DEV(b, "b");
@@ -674,24 +676,37 @@ static int lsqr_begin(gsr_system* s, const double* b, const double* x0, const gs
     s->cov_precond = o->precond;
   }
   // r0 = [b; c] - [A; C] x0
-  HIPCHK(launch_copy(b, s->u, s->s.m, st));
+  const int r0_in_pass = s->use_blk && fold_r0 && x0;
   double* uc = s->u + s->s.m;  // constraint rows of u
+  if (!r0_in_pass) {
+    HIPCHK(launch_copy(b, s->u, s->s.m, st));
+    if (x0 && s->s.m > 0)
+      HIPCHK(launch_aprod1(s->s, s->sh, x0, s->u, 1.0, -1.0, 0, nullptr, s->wk, 0, st));
+  }
   if (s->con.ncon > 0) HIPCHK(launch_copy(s->con_rhs, uc, s->con.ncon, st));
-  if (x0 && s->s.m > 0)
-    HIPCHK(launch_aprod1(s->s, s->sh, x0, s->u, 1.0, -1.0, 0, nullptr, s->wk, 0, st));
   if (x0) HIPCHK(launch_con_aprod1(s->con, x0, uc, 1.0, -1.0, nullptr, s->wk, st));
   if (s->use_blk) {
     // r0 in the regrouped order; then beta_1 and alpha_1 v_1 by the iteration's
-    // own pass with x = 0 (u' = u) and the init steps of the scalar recurrences
+    // own pass with x = 0 (u' = u), or x = -x0 on b when r0 is formed there,
+    // and the init steps of the scalar recurrences
     if (!s->zvec) {
       CHK(dalloc(&s->zvec, (size_t)s->s.n));
       HIPCHK(launch_fill(s->zvec, s->s.n, 0.0, st));
     }
-    HIPCHK(launch_blk_permute(s->blk, s->u, st));
-    HIPCHK(launch_att_interleave(s->s, s->zvec, s->x3, st));
+    const double* vg0 = s->zvec;
+    int32_t pm0 = product;
+    if (r0_in_pass) {
+      HIPCHK(launch_blk_permute(s->blk, b, st));
+      HIPCHK(launch_scaled_copy(x0, s->y, s->s.n, -1.0, st));  // y is free until init_vectors
+      vg0 = s->y;
+      pm0 = GSR_PROD_F64;
+    } else {
+      HIPCHK(launch_blk_permute(s->blk, s->u, st));
+    }
+    HIPCHK(launch_att_interleave(s->s, vg0, s->x3, st));
     // constraint rows of u stay after the m rows of s->u (uc)
     if (s->con.ncon > 0) HIPCHK(launch_con_aprod1(s->con, s->zvec, uc, 0.0, 1.0, s->sc, s->wk, st));
-    HIPCHK(launch_fblk(s->s, s->blk, product, s->zvec, s->x3, s->acc, s->sc, s->wk, st, 1));
+    HIPCHK(launch_fblk(s->s, s->blk, pm0, vg0, s->x3, s->acc, s->sc, s->wk, st, 1));
     HIPCHK(launch_seg_reduce(s->s, s->blk, s->gA, s->sc, st));
     if (s->con.ncon > 0) HIPCHK(launch_con_aprod2(s->con, s->s.n_astro, uc, s->gA, s->acc, s->sc, st));
     HIPCHK(launch_tail_blk(s->s, s->blk, s->v, s->acc, S, s->gA, s->sc, s->wk, st, 0));
@@ -1003,10 +1018,9 @@ extern "C" int gsr_lsqr_refine(gsr_system* s, const double* b, const double* x0,
   NEED_DEV(x, "x");
   if (s->s.m > 0) NEED_DEV(b, "b");
   hipStream_t st = (hipStream_t)stream;
-  const size_t m = (size_t)s->s.m, n = (size_t)s->s.n;
-  if (!s->r) CHK(dalloc(&s->r, m));
+  const size_t n = (size_t)s->s.n;
   if (!s->xr) CHK(dalloc(&s->xr, n));
-  if (!s->dx) CHK(dalloc(&s->dx, n));
+  if (!s->xn) CHK(dalloc(&s->xn, n));
   if (!s->nrm2) CHK(dalloc(&s->nrm2, 2));
   if (x0) {
     NEED_DEV(x0, "x0");
@@ -1024,18 +1038,15 @@ extern "C" int gsr_lsqr_refine(gsr_system* s, const double* b, const double* x0,
   gsr_lsqr_result last{};
   int rc = GSR_OK;
   for (int32_t it = 0; it < o->outer_max; ++it) {
-    // r = b - A x with FP64 products on the stored FP32 coefficients
-    if ((rc = (launch_copy(b, s->r, (int64_t)m, st) == hipSuccess ? GSR_OK : fail(GSR_EHIP, "copy failed")))) break;
-    if (m > 0 && launch_aprod1(s->s, s->sh, s->xr, s->r, 1.0, -1.0, 0, nullptr, s->wk, 0, st) != hipSuccess) {
-      rc = fail(GSR_EHIP, "aprod1 launch failed");
-      break;
-    }
-    if ((rc = lsqr_begin(s, s->r, nullptr, o, o->product, st))) break;
+    // LSQR from the current x on r = b - A x, formed with FP64 products on the
+    // stored FP32 coefficients (exact upcast); the solve returns x + dx
+    const double* xc = (it > 0 || x0) ? s->xr : nullptr;
+    if ((rc = lsqr_begin(s, b, xc, o, o->product, st, 1))) break;
     if ((rc = lsqr_run(s, st))) break;
-    if ((rc = lsqr_end(s, s->dx, nullptr, &last, st))) break;
+    if ((rc = lsqr_end(s, s->xn, nullptr, &last, st))) break;
     total += last.itn;
     steps = it + 1;
-    if (launch_axpy_norms((int64_t)n, s->dx, s->xr, s->nrm2, s->wk, st) != hipSuccess) {
+    if (launch_step_norms((int64_t)n, s->xn, s->xr, s->nrm2, s->wk, st) != hipSuccess) {
       rc = fail(GSR_EHIP, "update launch failed");
       break;
     }

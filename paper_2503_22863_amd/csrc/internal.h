@@ -258,7 +258,8 @@ hipError_t launch_pair_out(const double* Cp, int64_t P, const int32_t* pa, const
 hipError_t launch_cov_out(const double* C, int64_t k, const double* S, const int64_t* sel, double* out,
                           hipStream_t st);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
-hipError_t launch_axpy_norms(int64_t n, const double* dx, double* x, double* out2, Work w, hipStream_t st);
+hipError_t launch_step_norms(int64_t n, const double* xn, double* x, double* out2, Work w, hipStream_t st);
+hipError_t launch_scaled_copy(const double* src, double* dst, int64_t n, double s, hipStream_t st);
 
 // learned warm start (mlp.hip)
 hipError_t launch_features(const SysView& s, const double* b, const double* xo, double* F, hipStream_t st);

@@ -306,18 +306,18 @@ __global__ void k_cov_out(const double* __restrict__ C, int64_t k, const double*
   }
 }
 
-// dx accumulation of an outer refinement step: x += dx, partial ||dx||^2 and ||x||^2.
-__global__ void __launch_bounds__(kBlock) k_axpy_norms(int64_t n, const double* __restrict__ dx,
+// End of an outer refinement step: x <- x_new, partial ||x_new - x||^2 and ||x_new||^2.
+__global__ void __launch_bounds__(kBlock) k_step_norms(int64_t n, const double* __restrict__ xn,
                                                        double* __restrict__ x, double* out2, Work wk) {
   __shared__ double red[kWavesPerBlock];
   __shared__ int flag;
   double a = 0.0, b = 0.0;
   for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) {
-    const double d = dx[j];
-    const double xn = x[j] + d;
-    x[j] = xn;
+    const double v = xn[j];
+    const double d = v - x[j];
+    x[j] = v;
     a += d * d;
-    b += xn * xn;
+    b += v * v;
   }
   const double ba = block_sum(a, red);
   const double bb = block_sum(b, red);
@@ -334,6 +334,10 @@ __global__ void __launch_bounds__(kBlock) k_axpy_norms(int64_t n, const double* 
       ticket_reset(wk.tickets + T_VALID);
     }
   }
+}
+
+__global__ void k_scaled_copy(const double* __restrict__ a, double* __restrict__ b, int64_t n, double s) {
+  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) b[j] = s * a[j];
 }
 
 // ------------------------------------------------------------ launchers
@@ -413,8 +417,14 @@ hipError_t launch_cov_out(const double* C, int64_t k, const double* S, const int
   return hipGetLastError();
 }
 
-hipError_t launch_axpy_norms(int64_t n, const double* dx, double* x, double* out2, Work w, hipStream_t st) {
-  hipLaunchKernelGGL(k_axpy_norms, dim3(blocks_for(n)), dim3(kBlock), 0, st, n, dx, x, out2, w);
+hipError_t launch_step_norms(int64_t n, const double* xn, double* x, double* out2, Work w, hipStream_t st) {
+  hipLaunchKernelGGL(k_step_norms, dim3(blocks_for(n)), dim3(kBlock), 0, st, n, xn, x, out2, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_scaled_copy(const double* src, double* dst, int64_t n, double s, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scaled_copy, dim3(blocks_for(n)), dim3(kBlock), 0, st, src, dst, n, s);
   return hipGetLastError();
 }
 
