@@ -141,7 +141,7 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
     double xs;
     dd2u cw[6];
     auto gathers = [&]() {
-      const int64_t st0 = __shfl((int64_t)rec.x, 0, kWave);
+      const int64_t st0 = (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)rec.x, 0);
       xs = x[min(5 * st0 + lane, xa_last)];
       const int ao_l = (int)(rec.y & 0x1FFFu);
 #pragma unroll
@@ -177,7 +177,7 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
                          (int)((B >> 22) & 0x7FFu), (int)((B >> 33) & 0x7FFu), (int)((B >> 44) & 0x7FFu)};
       const bool end = (A >> 63) != 0;
       const double uo_c = (scale == 0.0) ? 0.0 : scale * uo;
-      const int64_t s0 = __shfl(star, 0, kWave);
+      const int64_t s0 = lane_read(star, 0);
       const int64_t ds = star - s0;
       const bool far = __ballot(ds >= 12) != 0;  // more than 12 stars in the tile: per-lane gathers
       u4 cur[CPR];
@@ -242,6 +242,9 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
         }
         ax = axh;
       }
+      // this tile's x is in LDS and registers: the next tile's gathers (its
+      // record arrived with the loads issued at the top) overlap the rest of it
+      gathers();
       // the previous tile's stores, issued once this tile's gathers are in (vector
       // memory counts stores and loads in one in-order counter): here they have
       // this tile's arithmetic to complete
@@ -272,30 +275,23 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
         for (int k = 0; k < 5; ++k) p[k] += carry[k];
       }
       // segment starts: lane 0 unless the previous tile's last segment goes on, else after an end
-      const bool prev_end = __shfl_up(end ? 1 : 0, 1, kWave) != 0;
+      const uint64_t ends = __ballot(end);
+      const bool prev_end = lane > 0 && ((ends >> (lane - 1)) & 1ull);
       const bool start = (lane == 0) ? !carry_valid : prev_end;
       const uint64_t starts = __ballot(start);
       const uint64_t le = (lane == kWave - 1) ? ~0ull : ((2ull << lane) - 1);
       const uint64_t mine = starts & le;
       const int seg0 = mine ? 63 - __clzll(mine) : 0;
-#pragma unroll
-      for (int off = 1; off < kWave; off <<= 1) {
-#pragma unroll
-        for (int k = 0; k < 5; ++k) {
-          const double o = __shfl_up(p[k], off, kWave);
-          if (lane - off >= seg0) p[k] += o;
-        }
-      }
+      seg_scan(p, lane, seg0);
       const int64_t sidx = nstart - 1 + __popcll(mine);
       p_dst = end ? bv.P + 5 * sidx : du + kWave;
 #pragma unroll
       for (int k = 0; k < 5; ++k) g_out[k] = p[k];
       nstart += __popcll(starts);
-      const int lend = __shfl(end ? 1 : 0, kWave - 1, kWave);
+      const int lend = (int)(ends >> 63);
 #pragma unroll
-      for (int k = 0; k < 5; ++k) carry[k] = __shfl(p[k], kWave - 1, kWave);
+      for (int k = 0; k < 5; ++k) carry[k] = lane_read(p[k], kWave - 1);
       carry_valid = !lend;
-      gathers();  // the next tile's (rec now holds its record)
     }
     *u_dst = u_out;
 #pragma unroll

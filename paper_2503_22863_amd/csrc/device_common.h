@@ -68,6 +68,64 @@ __device__ __forceinline__ void lds_rows(const u4* tmp, int nrow, u4* slab, int 
 // on the prefetch).
 __device__ __forceinline__ void order_point() { __builtin_amdgcn_sched_barrier(0); }
 
+// Cross-lane moves that bypass the LDS crossbar.  dpp0: a DPP move (GFX9
+// controls: row_shr:n = 0x110 + n shifts within rows of 16 lanes; row_bcast:15 =
+// 0x142 sends lane 15 of each row to the next row; row_bcast:31 = 0x143 sends
+// lane 31 to rows 2 and 3); lanes whose source lies outside their row, and the
+// rows left out of ROW_MASK, get 0.  lane_read: the value of lane l (uniform l).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp0(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double lane_read(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ int64_t lane_read(int64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Segmented inclusive sums over the wave: lane l ends with the sum of p over
+// lanes seg0(l)..l, where seg0(l) <= l is the first lane of l's segment.  Four
+// shifts within rows of 16 lanes, then the row totals: lane 15 into row 1 and
+// lane 47 into row 3, lane 31 into rows 2 and 3 (Hillis-Steele over the row
+// structure of DPP); a term is added only when its source lane lies in l's
+// segment, so every partial stays inside one segment.
+template <int OFF, int K>
+__device__ __forceinline__ void seg_shift_row(double (&p)[K], bool take) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const double o = dpp0<0x110 + OFF, 0xF>(p[k]);
+    if (take) p[k] += o;
+  }
+}
+
+template <int K>
+__device__ __forceinline__ void seg_scan(double (&p)[K], int lane, int seg0) {
+  seg_shift_row<1>(p, lane - 1 >= seg0);
+  seg_shift_row<2>(p, lane - 2 >= seg0);
+  seg_shift_row<4>(p, lane - 4 >= seg0);
+  seg_shift_row<8>(p, lane - 8 >= seg0);
+  const bool t15 = (lane & ~15) - 1 >= seg0, t31 = 31 >= seg0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const double o = dpp0<0x142, 0xA>(p[k]);
+    if (t15) p[k] += o;
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const double o = dpp0<0x143, 0xC>(p[k]);
+    if (t31) p[k] += o;
+  }
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);

@@ -154,6 +154,40 @@ def test_blocked_fp32_forms(dev, oracle_lib):
     S.close()
 
 
+@pytest.mark.parametrize("case", list(CASES))
+def test_blocked_fp32_storage_cases(dev, oracle_lib, case):
+    """FP32 coefficients (6 chunks per row: other tile offsets and window loads than
+    FP64) with FP64 products against the FP64 oracle on the same values, in every
+    layout case; FP32 products against the oracle's FP32-product LSQR."""
+    print(f"[blocked] FP32 storage, {case}", flush=True)
+    c = CASES[case]
+    g32 = _system(c).as_f32()
+    g64 = _system(c)
+    g64.vals = g32.vals.astype(np.float64)
+    o = oracle_lib.OSystem(g64)
+    bn = oracle_lib.known_terms(o, g64.x_true, g64.noise)
+    kw = dict(atol=0, btol=0, itmax=20, precond=True)
+    ref, sx, sv = _sensitivity(oracle_lib, g64, o, bn, **kw)
+    S = dev.System.from_generated(g32)
+    S.set_blocked(True, c["maxw"])
+    b = torch.from_numpy(bn).cuda()
+    x, var, r = S.lsqr_solve(b, product="f64", **kw)
+    info = S.blocked_info()
+    assert info["active"] == 1
+    ex, ev = _rel(x.cpu().numpy(), ref["x"]), _rel(var.cpu().numpy(), ref["var"])
+    print(f"  FP64 products: x {ex:.2e} var {ev:.2e} (sensitivity {sx:.1e}, {sv:.1e})", flush=True)
+    assert ex <= max(1e-12, 10 * sx) and ev <= max(1e-10, 10 * sv)
+    for k in ("rnorm", "anorm", "xnorm"):
+        assert abs(r[k] - ref[k]) <= max(1e-12, 10 * ref["sens"][k]) * abs(ref[k]), k
+    ref32 = oracle_lib.lsqr(oracle_lib.OSystem(g32), bn, mode=oracle_lib.P32, **kw)
+    dx = _rel(ref32["x"], ref["x"])
+    x, var, r = S.lsqr_solve(b, product="f32", **kw)
+    ex = _rel(x.cpu().numpy(), ref32["x"])
+    print(f"  FP32 products: x {ex:.2e} (FP32 effect {dx:.2e})", flush=True)
+    assert ex <= 5 * dx
+    S.close()
+
+
 def test_blocked_covariances(dev, oracle_lib):
     """Covariances of selected unknowns (astrometric, attitude, instrumental) from the
     direction vectors of a solve on the regrouped copy."""
