@@ -317,14 +317,7 @@ __global__ void __launch_bounds__(kBlock) k_aprod2(SysView s, int waves, const v
         for (int k = 0; k < 5; ++k) p[k] += carry[k];
       }
       // inclusive segmented scan over the star runs of this tile
-#pragma unroll
-      for (int off = 1; off < kWave; off <<= 1) {
-#pragma unroll
-        for (int k = 0; k < 5; ++k) {
-          const double o = __shfl_up(p[k], off, kWave);
-          if (lane - off >= seg0) p[k] += o;
-        }
-      }
+      seg_scan(p, lane, seg0);
       const bool ends_here = valid && (r == rend - 1);
       // new x of the lane's star from its old x and scale: from the shuffle window
       // (used on every path), or, with many short stars in the tile, from per-lane
@@ -359,9 +352,9 @@ __global__ void __launch_bounds__(kBlock) k_aprod2(SysView s, int waves, const v
       }
       // carry the last run of the tile if its star continues
       const int last = nrow - 1;
-      const int lend = __shfl(ends_here ? 1 : 0, last, kWave);
+      const int lend = (int)((__ballot(ends_here) >> last) & 1ull);
 #pragma unroll
-      for (int k = 0; k < 5; ++k) carry[k] = __shfl(p[k], last, kWave);
+      for (int k = 0; k < 5; ++k) carry[k] = lane_read(p[k], last);
       carry_valid = !lend;
     }
     if (c_out >= 0) {

@@ -221,22 +221,15 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
         for (int k = 0; k < 5; ++k) p[k] += carry[k];
       }
       const int seg0 = valid ? (int)(max(rbeg, t0) - t0) : lane;
-#pragma unroll
-      for (int off = 1; off < kWave; off <<= 1) {
-#pragma unroll
-        for (int k = 0; k < 5; ++k) {
-          const double o = __shfl_up(p[k], off, kWave);
-          if (lane - off >= seg0) p[k] += o;
-        }
-      }
+      seg_scan(p, lane, seg0);
       const bool ends_here = valid && (r == rend - 1);
       c_out = ends_here ? 5 * st : -1;
 #pragma unroll
       for (int k = 0; k < 5; ++k) g_out[k] = p[k];
       const int last = nrow - 1;
-      const int lend = __shfl(ends_here ? 1 : 0, last, kWave);
+      const int lend = (int)((__ballot(ends_here) >> last) & 1ull);
 #pragma unroll
-      for (int k = 0; k < 5; ++k) carry[k] = __shfl(p[k], last, kWave);
+      for (int k = 0; k < 5; ++k) carry[k] = lane_read(p[k], last);
       carry_valid = !lend;
     }
     if (r_out >= 0) u[r_out] = u_out;
