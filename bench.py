@@ -49,9 +49,16 @@ def pass_bytes(info, m, ns, f32=False):
     return "k_fused", (FUSED_B_ROW_F32 if f32 else FUSED_B_ROW) * m + FUSED_B_STAR * ns
 
 
-def kernel_source_hash() -> str:
+# the sources each row-pass kernel is compiled from
+KERNEL_SOURCES = {
+    "k_fblk": ("blocked.hip", "row_tiles.h", "device_common.h", "internal.h"),
+    "k_fused": ("fused.hip", "row_tiles.h", "device_common.h", "internal.h"),
+}
+
+
+def kernel_source_hash(kernel: str = "k_fblk") -> str:
     h = hashlib.sha256()
-    for f in ("fused.hip", "blocked.hip", "row_tiles.h", "device_common.h", "internal.h"):
+    for f in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_2503_22863_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -66,7 +73,7 @@ def load_traffic(kernel: str, workload: str):
     except (OSError, ValueError):
         return None
     e = rec.get(f"{kernel}:{workload}")
-    if not e or e.get("source_hash") != kernel_source_hash():
+    if not e or e.get("source_hash") != kernel_source_hash(kernel):
         return None
     return e.get("bytes_per_launch")
 
