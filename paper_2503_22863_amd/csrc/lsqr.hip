@@ -119,20 +119,21 @@ __global__ void k_finish(int64_t n, const double* __restrict__ y, const double* 
 // C += D D^T over the first `cols` columns of D ([k][ldd], row-major), on the
 // upper triangle of 32 x 32 tiles of C ([k][k], row-major).  A workgroup owns
 // a 64 x 64 tile of C (upper tiles only); its four waves each hold a 32 x 32
-// quadrant in 2 x 2 accumulators of v_mfma_f64_16x16x4f64.  D is staged 16
+// quadrant in 2 x 2 accumulators of v_mfma_f64_16x16x4f64.  D is staged 32
 // columns at a time: the 64 rows of the tile's row panel and of its column
-// panel go to LDS (row pitch 18 doubles: conflict-free 16-byte reads), the
-// next stage's panels are prefetched into registers meanwhile.  Inside a
-// stage the k index of MFMA step s for lane group g is 4g + s, so each lane
-// reads 4 consecutive doubles of a row; A and B use the same order, so the
-// contraction is unchanged.
+// panel go to LDS (row pitch 34 doubles: conflict-free 16-byte reads), the
+// next stage's panels are prefetched into registers meanwhile.  Inside each
+// 16-column half of a stage the k index of MFMA step s for lane group g is
+// 4g + s, so each lane reads 4 consecutive doubles of a row; A and B use the
+// same order, so the contraction is unchanged.  Four waves per SIMD (the
+// register budget is held to 128).
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef double dd2 __attribute__((ext_vector_type(2)));  // 16-byte aligned pair (LDS)
 constexpr int kSyT = 64;  // C tile per workgroup
-constexpr int kSyK = 16;  // D columns per stage
-constexpr int kSyP = 18;  // LDS row pitch (doubles)
+constexpr int kSyK = 32;  // D columns per stage
+constexpr int kSyP = 34;  // LDS row pitch (doubles)
 
-__global__ void __launch_bounds__(kBlock) k_syrk(const double* __restrict__ D, int64_t k, int64_t ldd,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) k_syrk(const double* __restrict__ D, int64_t k, int64_t ldd,
                                                  double* __restrict__ C, Scalars* sc, Work wk, int64_t fixed_cols,
                                                  int64_t T, int64_t ntiles) {
   __shared__ __align__(16) double pa[kSyT * kSyP];
@@ -151,13 +152,14 @@ __global__ void __launch_bounds__(kBlock) k_syrk(const double* __restrict__ D, i
     const int64_t r0 = ti * kSyT, c0 = tj * kSyT;
     const int qi = wid >> 1, qj = wid & 1;  // this wave's 32 x 32 quadrant
     const int i16 = lane & 15, g = lane >> 4;
-    // global -> register staging: thread t moves 16-byte pieces t and t+256 of
-    // each 64 x 16 panel (8 pieces per row)
-    dd2 ra[2], rb[2];
+    // global -> register staging: thread t moves 16-byte pieces t + 256 h of
+    // each 64 x kSyK panel (kSyK / 2 pieces per row)
+    constexpr int kPieces = kSyT * kSyK / 2 / kBlock, kRowPieces = kSyK / 2;
+    dd2 ra[kPieces], rb[kPieces];
     auto fetch = [&](int64_t kk) {
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int c = (int)threadIdx.x + h * kBlock, row = c >> 3, part = c & 7;
+      for (int h = 0; h < kPieces; ++h) {
+        const int c = (int)threadIdx.x + h * kBlock, row = c / kRowPieces, part = c % kRowPieces;
         const int64_t col = kk + 2 * part;
         const int64_t ga = r0 + row, gb = c0 + row;
         dd2 va = {0.0, 0.0}, vb = {0.0, 0.0};
@@ -182,18 +184,20 @@ __global__ void __launch_bounds__(kBlock) k_syrk(const double* __restrict__ D, i
     for (int64_t kk = 0; kk < cols; kk += kSyK) {
       __syncthreads();  // the previous stage's reads are done
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int c = (int)threadIdx.x + h * kBlock, row = c >> 3, part = c & 7;
+      for (int h = 0; h < kPieces; ++h) {
+        const int c = (int)threadIdx.x + h * kBlock, row = c / kRowPieces, part = c % kRowPieces;
         *reinterpret_cast<dd2*>(pa + row * kSyP + 2 * part) = ra[h];
         *reinterpret_cast<dd2*>(pb + row * kSyP + 2 * part) = rb[h];
       }
       __syncthreads();
       if (kk + kSyK < cols) fetch(kk + kSyK);
+#pragma unroll
+      for (int hh = 0; hh < kSyK / 16; ++hh) {
       double av[2][4], bv[2][4];
 #pragma unroll
       for (int bi = 0; bi < 2; ++bi) {
-        const double* a = pa + (32 * qi + 16 * bi + i16) * kSyP + 4 * g;
-        const double* b = pb + (32 * qj + 16 * bi + i16) * kSyP + 4 * g;
+        const double* a = pa + (32 * qi + 16 * bi + i16) * kSyP + 16 * hh + 4 * g;
+        const double* b = pb + (32 * qj + 16 * bi + i16) * kSyP + 16 * hh + 4 * g;
         const dd2 a01 = *reinterpret_cast<const dd2*>(a), a23 = *reinterpret_cast<const dd2*>(a + 2);
         const dd2 b01 = *reinterpret_cast<const dd2*>(b), b23 = *reinterpret_cast<const dd2*>(b + 2);
         av[bi][0] = a01.x;
@@ -212,6 +216,7 @@ __global__ void __launch_bounds__(kBlock) k_syrk(const double* __restrict__ D, i
 #pragma unroll
           for (int bj = 0; bj < 2; ++bj)
             acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bi][st], bv[bj][st], acc[bi][bj], 0, 0, 0);
+      }
     }
     // accumulator layout of the 16x16 f64 result: element e of lane l is row (l/16) + 4e, column l%16.
     // Only 32 x 32 tiles on or above the diagonal are written.
