@@ -90,8 +90,8 @@ __global__ void k_blk_permute(BlkView bv, const double* __restrict__ src) {
 // values are in, and ends by issuing the next tile's gathers.
 template <typename VT, int PM>
 __global__ void __launch_bounds__(kBlkThreads) __attribute__((amdgpu_waves_per_eu(2)))
-k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __restrict__ x3, double* __restrict__ acc,
-       Scalars* sc, Work wk, int init) {
+k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __restrict__ x3,
+       const float* __restrict__ x3f, double* __restrict__ acc, Scalars* sc, Work wk, int init) {
   constexpr int CPR = Geo<VT>::CPR;
   __shared__ dd2u rg[kBlkWaves][(kWave / 2) * 7];
   __shared__ double red[kBlkWaves];
@@ -112,6 +112,7 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
 
   const int64_t g = bv.wg_block[blockIdx.x];
   const double* xw = x3 + 3 * g * bv.Wb;  // interleaved x of the block's window
+  const float* xwf = x3f + 3 * g * bv.Wb;  // the same rounded to FP32 (FP32 products only)
   const int64_t w = (int64_t)blockIdx.x * kBlkWaves + wid;
   const int64_t T0 = bv.wave_tile[w], T1 = bv.wave_tile[w + 1];
   double sumsq = 0.0, gsum = 0.0;
@@ -137,18 +138,27 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
     // its 64 attitude windows of 96 bytes, loaded cooperatively (piece
     // j*64 + lane of the tile's windows in cw[j]; consecutive lanes take
     // consecutive 16-byte pieces of one window) and regrouped through LDS.
-    // Issued a tile ahead, right after that tile's record arrives.
+    // Issued a tile ahead, right after that tile's record arrives.  With FP32
+    // products the windows come from the FP32 copy: 48 bytes each, 3 pieces
+    // of 16 bytes (the products round x to FP32 anyway, so the arithmetic is
+    // the same).
+    constexpr int NP = PM == 1 ? 3 : 6;  // 16-byte pieces per window
     double xs;
-    dd2u cw[6];
+    dd2u cw[NP];
     auto gathers = [&]() {
       const int64_t st0 = (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)rec.x, 0);
       xs = x[min(5 * st0 + lane, xa_last)];
       const int ao_l = (int)(rec.y & 0x1FFFu);
 #pragma unroll
-      for (int j = 0; j < 6; ++j) {
-        const int c = j * kWave + lane, i = c / 6, q = c - 6 * i;
+      for (int j = 0; j < NP; ++j) {
+        const int c = j * kWave + lane, i = c / NP, q = c - NP * i;
         const int ao = __shfl(ao_l, i, kWave);
-        cw[j] = *reinterpret_cast<const dd2u*>(xw + 3 * ao + 2 * q);
+        if constexpr (PM == 1) {
+          const f4u v = *reinterpret_cast<const f4u*>(xwf + 3 * ao + 4 * q);
+          __builtin_memcpy(&cw[j], &v, sizeof v);
+        } else {
+          cw[j] = *reinterpret_cast<const dd2u*>(xw + 3 * ao + 2 * q);
+        }
       }
     };
     double carry[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -210,7 +220,31 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
         }
         ax += axa;
       }
-      {
+      if constexpr (PM == 1) {
+        // FP32 windows: all 64 rows in one round (piece c = 3 row + q, a row
+        // stride of 3 pieces: 8 consecutive rows fall on distinct banks);
+        // element e = 3j + axis is column start+j of that axis, taken in the
+        // same order as below
+        dd2u* wl = rg[wid];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) wl[j * kWave + lane] = cw[j];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+          const dd2u pq = wl[lane * NP + q];
+          float f[4];
+          __builtin_memcpy(f, &pq, sizeof f);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int e = 4 * q + k;
+            ax += prod<PM>(a[5 + 4 * (e % 3) + e / 3], (double)f[k]);
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+      } else {
         // regroup the attitude windows per row through LDS, 32 rows per round
         // (pieces 0..191 hold rows 0..31, pieces 192..383 rows 32..63; a padded
         // row stride of 7 pieces keeps the row reads free of bank conflicts);
@@ -320,16 +354,16 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
 }
 
 hipError_t launch_fblk(const SysView& s, const BlkView& bv, int pmode, const double* vg, const double* x3,
-                       double* acc, Scalars* sc, Work w, hipStream_t st, int init) {
+                       const float* x3f, double* acc, Scalars* sc, Work w, hipStream_t st, int init) {
   if (!bv.ready || bv.G < 1 || bv.G > kMaxPartials) return hipErrorInvalidValue;
-  if (pmode == 1 && s.value_type != GSR_F32) return hipErrorInvalidValue;
+  if (pmode == 1 && (s.value_type != GSR_F32 || x3f == nullptr)) return hipErrorInvalidValue;
   const dim3 g(bv.G), b(kBlkThreads);
   if (s.value_type == GSR_F32 && pmode == 1)
-    hipLaunchKernelGGL((k_fblk<float, 1>), g, b, bv.lds, st, s, bv, vg, x3, acc, sc, w, init);
+    hipLaunchKernelGGL((k_fblk<float, 1>), g, b, bv.lds, st, s, bv, vg, x3, x3f, acc, sc, w, init);
   else if (s.value_type == GSR_F32)
-    hipLaunchKernelGGL((k_fblk<float, 0>), g, b, bv.lds, st, s, bv, vg, x3, acc, sc, w, init);
+    hipLaunchKernelGGL((k_fblk<float, 0>), g, b, bv.lds, st, s, bv, vg, x3, x3f, acc, sc, w, init);
   else
-    hipLaunchKernelGGL((k_fblk<double, 0>), g, b, bv.lds, st, s, bv, vg, x3, acc, sc, w, init);
+    hipLaunchKernelGGL((k_fblk<double, 0>), g, b, bv.lds, st, s, bv, vg, x3, x3f, acc, sc, w, init);
   return hipGetLastError();
 }
 

@@ -69,6 +69,7 @@ struct gsr_system {
   double *u = nullptr, *v = nullptr, *vg = nullptr, *w = nullptr, *y = nullptr, *var = nullptr;
   double* gA = nullptr;  // raw astrometric sums of the fused iteration pass
   double* x3 = nullptr;  // attitude part of vg, axes interleaved, for the fused pass
+  float* x3f = nullptr;  // the same rounded to FP32, for the regrouped pass with FP32 products
   void* rix = nullptr;   // packed row indices for the fused pass (16 B per row); null: no fused pass
   int fused = 1;         // one pass over the rows per iteration (FP64 products, attitude mode 0 or 3)
   // rows regrouped by attitude window (one pass per iteration where the attitude block exceeds LDS)
@@ -248,6 +249,7 @@ static void release(gsr_system* s) {
   for (hipEvent_t e : {s->eev[0], s->eev[1], s->efill})
     if (e) (void)hipEventDestroy(e);
   dfree(s->x3);
+  dfree(s->x3f);
   dfree(s->rix);
   dfree(s->xr);
   dfree(s->xn);
@@ -612,6 +614,9 @@ static int blk_applies(const gsr_system* s) {
          s->s.n_instr + 1 <= kLdsTailMax;
 }
 
+// The FP32 copy of the interleaved attitude x that the regrouped pass reads with FP32 products.
+static float* x3f_for(const gsr_system* s) { return s->use_blk && s->pmode == GSR_PROD_F32 ? s->x3f : nullptr; }
+
 // fold_r0: on the regrouped copy, form r0 = b - A x0 inside the first pass
 // (u' = u + A vg with vg = -x0, FP64 products) instead of by a separate aprod 1;
 // the rounding of r0 then follows the pass's summation order.
@@ -639,6 +644,8 @@ static int lsqr_begin(gsr_system* s, const double* b, const double* x0, const gs
     s->use_blk = s->blk.ready;
   }
   if (!s->use_blk) CHK(ensure_att(s, st));
+  if (s->use_blk && product == GSR_PROD_F32 && !s->x3f)
+    CHK(dalloc(&s->x3f, (size_t)std::max<int64_t>(3 * s->s.n_att, 1)));
   if (s->con.ncon > 0 && !s->use_blk && !fused_for(s, product))
     return fail(GSR_EINVAL, "constraint equations need the fused iteration (no memory for the regrouped copy "
                             "and no bucketed attitude view)");
@@ -703,10 +710,10 @@ static int lsqr_begin(gsr_system* s, const double* b, const double* x0, const gs
     } else {
       HIPCHK(launch_blk_permute(s->blk, s->u, st));
     }
-    HIPCHK(launch_att_interleave(s->s, vg0, s->x3, st));
+    HIPCHK(launch_att_interleave(s->s, vg0, s->x3, st, pm0 == GSR_PROD_F32 ? s->x3f : nullptr));
     // constraint rows of u stay after the m rows of s->u (uc)
     if (s->con.ncon > 0) HIPCHK(launch_con_aprod1(s->con, s->zvec, uc, 0.0, 1.0, s->sc, s->wk, st));
-    HIPCHK(launch_fblk(s->s, s->blk, pm0, vg0, s->x3, s->acc, s->sc, s->wk, st, 1));
+    HIPCHK(launch_fblk(s->s, s->blk, pm0, vg0, s->x3, s->x3f, s->acc, s->sc, s->wk, st, 1));
     HIPCHK(launch_seg_reduce(s->s, s->blk, s->gA, s->sc, st));
     if (s->con.ncon > 0) HIPCHK(launch_con_aprod2(s->con, s->s.n_astro, uc, s->gA, s->acc, s->sc, st));
     HIPCHK(launch_tail_blk(s->s, s->blk, s->v, s->acc, S, s->gA, s->sc, s->wk, st, 0));
@@ -733,7 +740,8 @@ static int lsqr_begin(gsr_system* s, const double* b, const double* x0, const gs
     CHK(aprod2_launches(s, s->u, s->v, S, 0.0, product, 0, s->sc, 0, st));
   }
   HIPCHK(launch_init_vectors(s->s.n, s->v, s->vg, s->w, s->y, s->var, S, s->sc, st));
-  if (s->use_blk || iteration_fused(s)) HIPCHK(launch_att_interleave(s->s, o->precond ? s->vg : s->v, s->x3, st));
+  if (s->use_blk || iteration_fused(s))
+    HIPCHK(launch_att_interleave(s->s, o->precond ? s->vg : s->v, s->x3, st, x3f_for(s)));
   s->in_session = 1;
   return GSR_OK;
 }
@@ -786,7 +794,7 @@ static int enqueue_iteration(gsr_system* s, hipStream_t st) {
     }
     {
       TimeScope ts(s, 0, st);
-      HIPCHK(launch_fblk(s->s, s->blk, s->pmode, vg, s->x3, s->acc, s->sc, s->wk, st));
+      HIPCHK(launch_fblk(s->s, s->blk, s->pmode, vg, s->x3, s->x3f, s->acc, s->sc, s->wk, st));
     }
     {
       TimeScope ts(s, 1, st);
@@ -839,7 +847,7 @@ static int enqueue_iteration(gsr_system* s, hipStream_t st) {
     TimeScope ts(s, 3, st);
     HIPCHK(launch_update(s->s.n, s->v, vg, s->w, s->y, s->var, S, s->sc, s->wk, st, s->eblock ? s->ering : nullptr,
                          s->eblock ? s->eblock : 1));
-    if (s->use_blk || iteration_fused(s)) HIPCHK(launch_att_interleave(s->s, vg, s->x3, st));
+    if (s->use_blk || iteration_fused(s)) HIPCHK(launch_att_interleave(s->s, vg, s->x3, st, x3f_for(s)));
   }
   s->enq += 1;
   if (s->nsel > 0 && s->enq % s->dblock == 0) {

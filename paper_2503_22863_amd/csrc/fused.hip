@@ -37,11 +37,14 @@ __global__ void k_pack_rows(SysView s, u4* __restrict__ rix) {
 // x3[3c + a] = x[n_astro + a*n_att + c]: the attitude unknowns with the three
 // axes interleaved, so that the 12 attitude unknowns of a row (4 consecutive
 // columns on each axis) are 96 contiguous bytes.
-__global__ void k_att_interleave(SysView s, const double* __restrict__ x, double* __restrict__ x3) {
+__global__ void k_att_interleave(SysView s, const double* __restrict__ x, double* __restrict__ x3,
+                                 float* __restrict__ x3f) {
   const int64_t n3 = 3 * s.n_att;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n3; e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t c = e / 3, axs = e - 3 * c;
-    x3[e] = x[s.n_astro + axs * s.n_att + c];
+    const double v = x[s.n_astro + axs * s.n_att + c];
+    x3[e] = v;
+    if (x3f) x3f[e] = (float)v;
   }
 }
 
@@ -301,11 +304,11 @@ hipError_t launch_pack_rows(const SysView& s, void* rix, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_att_interleave(const SysView& s, const double* x, double* x3, hipStream_t st) {
+hipError_t launch_att_interleave(const SysView& s, const double* x, double* x3, hipStream_t st, float* x3f) {
   const int64_t n3 = 3 * s.n_att;
   if (n3 == 0) return hipSuccess;
   const int blocks = (int)std::min<int64_t>(1024, (n3 + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_att_interleave, dim3(blocks), dim3(kBlock), 0, st, s, x, x3);
+  hipLaunchKernelGGL(k_att_interleave, dim3(blocks), dim3(kBlock), 0, st, s, x, x3, x3f);
   return hipGetLastError();
 }
 

@@ -205,7 +205,8 @@ hipError_t launch_fused(const SysView& s, StreamShape sh, int att_mode, int pmod
 // rix[r] <- {att_start[r], instr_col[r][0..5] as 16-bit pairs} (16 bytes per row; needs n_instr <= 65536)
 hipError_t launch_pack_rows(const SysView& s, void* rix, hipStream_t st);
 // x3 <- attitude part of x with the three axes interleaved (the fused pass's copy of vg)
-hipError_t launch_att_interleave(const SysView& s, const double* x, double* x3, hipStream_t st);
+hipError_t launch_att_interleave(const SysView& s, const double* x, double* x3, hipStream_t st,
+                                 float* x3f = nullptr);
 // Tail of the fused iteration: every column x_j <- v_scale*x_j + S_j * raw_j / beta (raw_j from gA, acc
 // or the attitude windows), then alpha_{i+1} and the rotations, as launch_tail.
 hipError_t launch_tail_fused(const SysView& s, const AttView& av, int att_mode, double* x, double* acc,
@@ -226,8 +227,9 @@ void blk_free(BlkView* bv);
 // ub <- src (rows in the caller's order) permuted to the regrouped order, zero on padding
 hipError_t launch_blk_permute(const BlkView& bv, const double* src, hipStream_t st);
 // The iteration's pass as launch_fused, on the regrouped copy (u in bv.ub).
+// x3f: the interleaved attitude x rounded to FP32, required with pmode 1.
 hipError_t launch_fblk(const SysView& s, const BlkView& bv, int pmode, const double* vg, const double* x3,
-                       double* acc, Scalars* sc, Work w, hipStream_t st, int init = 0);
+                       const float* x3f, double* acc, Scalars* sc, Work w, hipStream_t st, int init = 0);
 // Covariance column of the iteration: D[p][dcount] = w[sel[p]] / rho_i for p < nsel (after the tail);
 // the last workgroup advances dcount.  Skipped once the solve has stopped or the block is full.
 hipError_t launch_cov_gather(int64_t nsel, const int64_t* sel, const double* w, double* D, Scalars* sc, Work wk,

@@ -8,6 +8,7 @@
 namespace gsr {
 
 typedef double dd2u __attribute__((ext_vector_type(2), aligned(8)));  // 16-byte load at 8-byte alignment
+typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));    // 16-byte load at 4-byte alignment
 
 template <typename VT>
 struct Geo;

@@ -151,6 +151,12 @@ def test_blocked_fp32_forms(dev, oracle_lib):
     e = _rel(xr.cpu().numpy(), ref_c["x"])
     print(f"  refined {e:.2e} after {rr['outer_steps']} outer / {rr['inner_total']} inner", flush=True)
     assert e <= 1e-10
+    # from a given x0 (its residual formed inside the first pass of each inner solve)
+    x0 = torch.from_numpy(ref_c["x"] + 1e-3 * np.random.default_rng(44).standard_normal(g64.dims.n)).cuda()
+    xr0, rr0 = S.lsqr_refine(b, x0=x0, atol=1e-6, btol=1e-6, itmax=1000, precond=True, outer_max=10, outer_tol=1e-11)
+    e0 = _rel(xr0.cpu().numpy(), ref_c["x"])
+    print(f"  refined from x0 {e0:.2e} after {rr0['outer_steps']} outer / {rr0['inner_total']} inner", flush=True)
+    assert e0 <= 1e-10 and rr0["inner_total"] <= rr["inner_total"]
     S.close()
 
 
