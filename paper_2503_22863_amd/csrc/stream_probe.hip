@@ -1,13 +1,15 @@
 // Memory-system calibration for the row pass (a standalone program, not part
 // of libgsr): streams exactly the regrouped pass's per-row bytes — 64-row tiles
-// of 12 chunk-major 16-byte chunks, a 16-byte record and an 8-byte u per row,
-// one tile prefetched, 8 waves per workgroup and one workgroup per CU (the
-// pass's LDS footprint) — with the per-row u store in several forms, to show
-// what a pass that must write u can reach on this chip.
+// of 12 chunk-major 16-byte chunks (FP64 coefficients; 6 for FP32), a 16-byte
+// record and an 8-byte u per row, one tile prefetched (or two), 8 waves per
+// workgroup and one workgroup per CU (the pass's LDS footprint) — with the
+// per-row u store in several forms, to show what a pass that must write u can
+// reach on this chip.
 //
 //   stream_probe [rows]      (default 70,004,736: the 10^6-star share)
 //
-// One JSON object per line: {"store": ..., "ms": ..., "read_GBps": ...}.
+// One JSON object per line: {"chunks": ..., "depth": ..., "store": ..., "ms": ...,
+// "read_GBps": ...}.
 #include <hip/hip_runtime.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -23,14 +25,73 @@ typedef unsigned u4 __attribute__((ext_vector_type(4)));
     }                                                                                 \
   } while (0)
 
-constexpr int kChunks = 12;    // 16-byte chunks per row (24 FP64 coefficients)
-constexpr int kWaves = 8;      // waves per workgroup
-constexpr int kStage = 16;     // tiles per burst in the LDS-staged form
+constexpr int kMaxChunks = 12;  // 16-byte chunks per row (24 FP64 coefficients; 6 for FP32)
+constexpr int kWaves = 8;       // waves per workgroup
+constexpr int kStage = 16;      // tiles per burst in the LDS-staged form
+
+// Two tiles ahead: tiles in pairs, each pair's loads issued while the other
+// pair member is consumed (no register copy of loads still in flight).
+template <int CH, bool STORE>
+__global__ void __launch_bounds__(kWaves * 64) k_stream2(const u4* __restrict__ T, const u4* __restrict__ R,
+                                                          double* __restrict__ u, long ntiles, double* sink) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const long W = (long)gridDim.x * kWaves, w = (long)blockIdx.x * kWaves + wid;
+  const long t0 = ntiles * w / W, t1 = ntiles * (w + 1) / W;
+  double acc = 0.0;
+  if (t0 < t1) {
+    struct Buf {
+      u4 c[CH];
+      u4 rec;
+      double uo;
+    };
+    auto fetch = [&](Buf& b, long t) {
+      const long tt = t < t1 ? t : t0;  // past the range: re-read its first tile (unused)
+      const u4* base = T + tt * CH * 64 + lane;
+#pragma unroll
+      for (int j = 0; j < CH; ++j) b.c[j] = __builtin_nontemporal_load(base + j * 64);
+      b.rec = __builtin_nontemporal_load(R + tt * 64 + lane);
+      b.uo = u[tt * 64 + lane];
+    };
+    long r_out = -1;
+    double u_out = 0.0;
+    auto consume = [&](const Buf& b, long t) {
+      if (STORE && r_out >= 0) u[r_out] = u_out;
+      double s = b.uo + (double)b.rec.x;
+#pragma unroll
+      for (int j = 0; j < CH; ++j) {
+        const double2 d = *reinterpret_cast<const double2*>(&b.c[j]);
+        s += d.x * 1.0000001 + d.y;
+      }
+      r_out = t * 64 + lane;
+      u_out = s;
+      acc += s;
+    };
+    Buf X, Y, cur;
+    fetch(X, t0);
+    fetch(Y, t0 + 1);
+    long t = t0;
+    for (; t + 1 < t1; t += 2) {
+      cur = X;
+      __builtin_amdgcn_sched_barrier(0);
+      fetch(X, t + 2);
+      __builtin_amdgcn_sched_barrier(0);
+      consume(cur, t);
+      cur = Y;
+      __builtin_amdgcn_sched_barrier(0);
+      fetch(Y, t + 3);
+      __builtin_amdgcn_sched_barrier(0);
+      consume(cur, t + 1);
+    }
+    if (t < t1) consume(X, t);
+    if (STORE && r_out >= 0) u[r_out] = u_out;
+  }
+  if (acc == 1.2345) sink[0] = acc;  // keeps the sums live
+}
 
 // Store forms: 0 none, 1 plain, 2 nontemporal, 3 into a 1 MB wrap-around buffer
 // (never reaches HBM), 4 from every fourth wave only, 5 staged in LDS and
 // written kStage tiles at a time.
-template <int STORE>
+template <int kChunks, int STORE>
 __global__ void __launch_bounds__(kWaves * 64) k_stream(const u4* __restrict__ T, const u4* __restrict__ R,
                                                          double* __restrict__ u, long ntiles, double* sink) {
   extern __shared__ double lds[];  // sized to leave one workgroup per CU
@@ -96,29 +157,29 @@ __global__ void __launch_bounds__(kWaves * 64) k_stream(const u4* __restrict__ T
   if (acc == 1.2345) sink[0] = acc;  // keeps the sums live
 }
 
-template <int STORE>
-static void run(const char* name, const u4* T, const u4* R, double* u, long ntiles, double* sink, int blocks,
-                size_t lds) {
-  (void)hipFuncSetAttribute((const void*)k_stream<STORE>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+template <typename K>
+static void run(K kernel, int chunks, int depth, const char* name, const u4* T, const u4* R, double* u, long ntiles,
+                double* sink, int blocks, size_t lds) {
+  (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   (void)hipGetLastError();
   hipEvent_t a, b;
   CHK(hipEventCreate(&a));
   CHK(hipEventCreate(&b));
   for (int i = 0; i < 2; ++i)
-    hipLaunchKernelGGL(k_stream<STORE>, dim3(blocks), dim3(kWaves * 64), lds, 0, T, R, u, ntiles, sink);
+    hipLaunchKernelGGL(kernel, dim3(blocks), dim3(kWaves * 64), lds, 0, T, R, u, ntiles, sink);
   CHK(hipGetLastError());
   const int reps = 10;
   CHK(hipEventRecord(a));
   for (int i = 0; i < reps; ++i)
-    hipLaunchKernelGGL(k_stream<STORE>, dim3(blocks), dim3(kWaves * 64), lds, 0, T, R, u, ntiles, sink);
+    hipLaunchKernelGGL(kernel, dim3(blocks), dim3(kWaves * 64), lds, 0, T, R, u, ntiles, sink);
   CHK(hipEventRecord(b));
   CHK(hipEventSynchronize(b));
   float ms = 0.0f;
   CHK(hipEventElapsedTime(&ms, a, b));
   ms /= reps;
-  const double read = (double)ntiles * 64 * (kChunks * 16 + 16 + 8);
-  printf("{\"store\": \"%s\", \"rows\": %ld, \"ms\": %.4f, \"read_GBps\": %.1f}\n", name, ntiles * 64, ms,
-         read / (ms * 1e-3) / 1e9);
+  const double read = (double)ntiles * 64 * (chunks * 16 + 16 + 8);
+  printf("{\"chunks\": %d, \"depth\": %d, \"store\": \"%s\", \"rows\": %ld, \"ms\": %.4f, \"read_GBps\": %.1f}\n",
+         chunks, depth, name, ntiles * 64, ms, read / (ms * 1e-3) / 1e9);
   fflush(stdout);
   CHK(hipEventDestroy(a));
   CHK(hipEventDestroy(b));
@@ -137,21 +198,28 @@ int main(int argc, char** argv) {
   if (lds < sizeof(double) * kWaves * kStage * 64) return 1;
   u4 *T, *R;
   double *u, *sink;
-  CHK(hipMalloc(&T, (size_t)ntiles * 64 * kChunks * 16));
+  CHK(hipMalloc(&T, (size_t)ntiles * 64 * kMaxChunks * 16));
   CHK(hipMalloc(&R, (size_t)ntiles * 64 * 16));
   CHK(hipMalloc(&u, (size_t)ntiles * 64 * 8));
   CHK(hipMalloc(&sink, 64));
-  CHK(hipMemset(T, 0, (size_t)ntiles * 64 * kChunks * 16));
+  CHK(hipMemset(T, 0, (size_t)ntiles * 64 * kMaxChunks * 16));
   CHK(hipMemset(R, 0, (size_t)ntiles * 64 * 16));
   CHK(hipMemset(u, 0, (size_t)ntiles * 64 * 8));
   CHK(hipDeviceSynchronize());
   const int blocks = 2 * cus;
-  run<0>("none", T, R, u, ntiles, sink, blocks, lds);
-  run<1>("plain", T, R, u, ntiles, sink, blocks, lds);
-  run<2>("nontemporal", T, R, u, ntiles, sink, blocks, lds);
-  run<3>("1 MB wrap-around buffer", T, R, u, ntiles, sink, blocks, lds);
-  run<4>("every fourth wave only", T, R, u, ntiles, sink, blocks, lds);
-  run<5>("LDS-staged, 16 tiles per burst", T, R, u, ntiles, sink, blocks, lds);
+  // FP64 rows, one tile ahead, every store form
+  run(k_stream<12, 0>, 12, 1, "none", T, R, u, ntiles, sink, blocks, lds);
+  run(k_stream<12, 1>, 12, 1, "plain", T, R, u, ntiles, sink, blocks, lds);
+  run(k_stream<12, 2>, 12, 1, "nontemporal", T, R, u, ntiles, sink, blocks, lds);
+  run(k_stream<12, 3>, 12, 1, "1 MB wrap-around buffer", T, R, u, ntiles, sink, blocks, lds);
+  run(k_stream<12, 4>, 12, 1, "every fourth wave only", T, R, u, ntiles, sink, blocks, lds);
+  run(k_stream<12, 5>, 12, 1, "LDS-staged, 16 tiles per burst", T, R, u, ntiles, sink, blocks, lds);
+  // two tiles ahead; FP32 rows one and two tiles ahead
+  run(k_stream2<12, true>, 12, 2, "plain", T, R, u, ntiles, sink, blocks, lds);
+  run(k_stream<6, 0>, 6, 1, "none", T, R, u, ntiles, sink, blocks, lds);
+  run(k_stream<6, 1>, 6, 1, "plain", T, R, u, ntiles, sink, blocks, lds);
+  run(k_stream2<6, false>, 6, 2, "none", T, R, u, ntiles, sink, blocks, lds);
+  run(k_stream2<6, true>, 6, 2, "plain", T, R, u, ntiles, sink, blocks, lds);
   CHK(hipFree(T));
   CHK(hipFree(R));
   CHK(hipFree(u));
