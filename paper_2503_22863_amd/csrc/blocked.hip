@@ -85,9 +85,9 @@ __global__ void k_blk_permute(BlkView bv, const double* __restrict__ src) {
 // The iteration's pass.  Workgroup b streams tiles of block wg_block[b]; its
 // waves take consecutive sub-ranges.  Per tile a wave waits for the tile's
 // record, chunks and u (loaded one tile ahead) and for its x gathers (issued
-// at the end of the previous tile), issues the next tile's loads, forms the
-// products, stores the previous tile's u and segment sums once the gathered
-// values are in, and ends by issuing the next tile's gathers.
+// during the previous tile), issues the next tile's loads, forms A x, issues
+// the next tile's gathers once this tile's windows sit in LDS, stores the
+// previous tile's u and segment sums, and forms the A^T u' parts.
 template <typename VT, int PM>
 __global__ void __launch_bounds__(kBlkThreads) __attribute__((amdgpu_waves_per_eu(2)))
 k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __restrict__ x3,
@@ -138,7 +138,7 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
     // its 64 attitude windows of 96 bytes, loaded cooperatively (piece
     // j*64 + lane of the tile's windows in cw[j]; consecutive lanes take
     // consecutive 16-byte pieces of one window) and regrouped through LDS.
-    // Issued a tile ahead, right after that tile's record arrives.  With FP32
+    // Issued a tile ahead, in the middle of the previous tile.  With FP32
     // products the windows come from the FP32 copy: 48 bytes each, 3 pieces
     // of 16 bytes (the products round x to FP32 anyway, so the arithmetic is
     // the same).
