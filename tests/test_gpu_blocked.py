@@ -100,6 +100,36 @@ def test_blocked_lsqr_matches_oracle(dev, oracle_lib, case, precond):
     S.close()
 
 
+@pytest.mark.parametrize("precond", [True, False])
+def test_blocked_empty_windows(dev, oracle_lib, precond):
+    """Attitude starts moved out of [200, 440): windows 5 to 10 of 40 starts hold no
+    rows (no workgroups, no window sums) and their columns are empty; the iterates
+    still meet the oracle's bar (its empty columns stay at zero)."""
+    print(f"[blocked] empty windows precond={precond}", flush=True)
+    c = dict(CASES["many_windows"], seed=35)
+    g = copy.copy(_system(c))
+    a = g.att_start.astype(np.int64)
+    g.att_start = np.where((a >= 200) & (a < 440), a + 400, a).astype(np.int32)
+    assert not np.any((g.att_start >= 200) & (g.att_start < 440))
+    o = oracle_lib.OSystem(g)
+    bn = oracle_lib.known_terms(o, g.x_true, g.noise)
+    itmax = 25 if precond else 6
+    ref, sx, sv = _sensitivity(oracle_lib, g, o, bn, atol=0, btol=0, itmax=itmax, precond=precond)
+    S = dev.System.from_generated(g)
+    S.set_blocked(True, c["maxw"])
+    x, var, r = S.lsqr_solve(torch.from_numpy(bn).cuda(), atol=0, btol=0, itmax=itmax, precond=precond)
+    info = S.blocked_info()
+    assert info["active"] == 1 and info["blocks"] == 25
+    ex, ev = _rel(x.cpu().numpy(), ref["x"]), _rel(var.cpu().numpy(), ref["var"])
+    print(f"  x {ex:.2e} var {ev:.2e} (sensitivity {sx:.1e}, {sv:.1e})", flush=True)
+    assert ex <= max(1e-12, 10 * sx) and ev <= max(1e-10, 10 * sv)
+    na, nat = g.dims.n_stars * 5, g.dims.n_att
+    empty = np.concatenate([na + axis * nat + np.arange(203, 440) for axis in range(3)])
+    xh = x.cpu().numpy()
+    assert np.all(xh[empty] == 0.0) and np.all(ref["x"][empty] == 0.0)
+    S.close()
+
+
 def test_blocked_converged_solution(dev, oracle_lib):
     """To tolerance: the solution within 1e-10 of the oracle's and the same stop."""
     print("[blocked] converged, many windows", flush=True)
