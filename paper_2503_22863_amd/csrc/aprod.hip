@@ -430,10 +430,18 @@ __global__ void __launch_bounds__(kBlock) k_tail(SysView s, AttView av, int att_
         for (int64_t b = max<int64_t>(bhi - 1, 0); b <= bhi; ++b) {
           const int64_t off = c - b * av.Wb;
           if (off < 0 || off >= win) continue;
-          // four windows at a time (independent loads), added in workgroup order
+          // sixteen windows at a time (independent loads in flight together: a
+          // block has tens of workgroups), added in workgroup order
           const double* qp = av.Q + axs * win + off;
           const int64_t qs = 3 * win;
           int32_t q = av.bsub[b];
+          for (; q + 16 <= av.bsub[b + 1]; q += 16) {
+            double v[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) v[i] = qp[(q + i) * qs];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) a += v[i];
+          }
           for (; q + 4 <= av.bsub[b + 1]; q += 4) {
             const double q0 = qp[q * qs], q1 = qp[(q + 1) * qs], q2 = qp[(q + 2) * qs], q3 = qp[(q + 3) * qs];
             a += q0;
