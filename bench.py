@@ -38,6 +38,12 @@ FUSED_B_ROW_F32 = 96 + 4 + 24 + 8 + 8
 FBLK_B_ROW = 192 + 16 + 8 + 8
 FBLK_B_ROW_F32 = 96 + 16 + 8 + 8
 FBLK_B_SEG = 40 + 40
+# The standalone products on the caller's rows: aprod 1 reads the coefficients, the
+# attitude start and the 6 instrumental columns and reads and writes y; aprod 2
+# reads the same and y, and per star reads and writes the 5 astrometric x.
+APROD1_B_ROW = 192 + 4 + 24 + 8 + 8
+APROD2_B_ROW = 192 + 4 + 24 + 8
+APROD2_B_STAR = 40 + 40
 
 
 def pass_bytes(info, m, ns, f32=False):
@@ -284,6 +290,31 @@ def time_to_tolerance_warm(gsr, tol=1e-10, train_steps=1500):
             "speedup_mlp_vs_zero": a[:, 3].mean() / a[:, 5].mean()}
 
 
+def aprods_bench(S, m, n, ns, workload, reps=10):
+    """The standalone products y = 0.5 y + A x and x = 0.5 x + A^T y on the caller's
+    rows (HIP events on the stream they run on), against their algorithmic bytes."""
+    import torch
+
+    x = torch.randn(n, dtype=torch.float64, device="cuda")
+    y = torch.randn(m, dtype=torch.float64, device="cuda")
+    out = {"metric": "standalone aprod HBM rate", "workload": workload, "unit": "GB/s", "peak": HBM_PEAK_GBS}
+    for name, f, by in (("aprod1", lambda: S.aprod1(x, y, scale=0.5), APROD1_B_ROW * m),
+                        ("aprod2", lambda: S.aprod2(y, x, scale=0.5), APROD2_B_ROW * m + APROD2_B_STAR * ns)):
+        f()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            f()
+        b.record()
+        b.synchronize()
+        ms = a.elapsed_time(b) / reps
+        gbs = by / (ms * 1e-3) / 1e9
+        out[name] = {"ms": ms, "bytes": by, "GBps": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS}
+    return out
+
+
 def syrk_bench(gsr, k=4000, reps=20):
     """The covariance update C += D D^T alone (upper 32x32 tiles, FP64 MFMA) for
     k selected unknowns and blocks of 64, 256 and 512 buffered iterations."""
@@ -340,6 +371,9 @@ def main():
                          "several forms) and print its results")
     ap.add_argument("--syrk-bench", action="store_true",
                     help="time the covariance SYRK alone (k = 4000) and print its MFMA rate instead")
+    ap.add_argument("--aprods", action="store_true",
+                    help="time the standalone aprod 1 and aprod 2 on the workload's rows and print their "
+                         "HBM rates instead")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU row split is not built.",
@@ -386,6 +420,10 @@ def main():
     print(f"# generated m={m} n={n} in {time.time() - t:.1f}s", file=sys.stderr, flush=True)
     S = gsr.System.from_generated(g)
     S.set_blocked(not args.star_order)
+    if args.aprods:
+        print(json.dumps(aprods_bench(S, m, n, ns, args.workload)), flush=True)
+        S.close()
+        return
     if args.cov > 0:
         nst = (args.cov * 3 // 5) // 5
         S.cov_request(gsr_synth.covariance_selection(g.dims, nst, args.cov * 3 // 10 // 3, args.cov - 5 * nst
