@@ -45,8 +45,8 @@ namespace gsr {
 // gathers.
 template <typename VT, int PM>
 __global__ void __launch_bounds__(kBlock) k_aprod1(SysView s, int waves, const double* __restrict__ x,
-                                                   double* __restrict__ y, double scale, double ax, Scalars* sc,
-                                                   Work wk, int lsqr_stage) {
+                                                   const double* __restrict__ x3, double* __restrict__ y,
+                                                   double scale, double ax, Scalars* sc, Work wk, int lsqr_stage) {
   constexpr int CPR = Geo<VT>::CPR;
   __shared__ u4 slabs[kWavesPerBlock][kWave * (CPR + 1)];
   __shared__ int64_t bnds[kWavesPerBlock][kWave];
@@ -109,17 +109,18 @@ __global__ void __launch_bounds__(kBlock) k_aprod1(SysView s, int waves, const d
       // stars of the tile (valid when the last row's star is among the 64 boundaries)
       const int64_t span = __popcll(__ballot(bv_c <= t0 + nrow - 1)) + 1;
       scur = tile_next(s, bv_c, t0, sf);
-      // gathers of x for this tile, issued before the next tile's loads
+      // gathers of x for this tile, issued before the next tile's loads: the
+      // astrometric x of the tile's first stars, and the tile's 64 attitude
+      // windows of the axis-interleaved x3 (96 bytes each), loaded
+      // cooperatively (piece j*64 + lane in cw[j]; consecutive lanes take
+      // consecutive 16-byte pieces of one window)
       const double xs = x[min(5 * sf + lane, xa_last)];
-      double gx[kSlots];
+      dd2u cw[6];
 #pragma unroll
-      for (int axs = 0; axs < 3; ++axs) {
-        const dd2u* xt = reinterpret_cast<const dd2u*>(x + s.n_astro + axs * s.n_att + at_c);
-        const dd2u p0 = xt[0], p1 = xt[1];
-        gx[5 + 4 * axs] = p0.x;
-        gx[6 + 4 * axs] = p0.y;
-        gx[7 + 4 * axs] = p1.x;
-        gx[8 + 4 * axs] = p1.y;
+      for (int j = 0; j < 6; ++j) {
+        const int c = j * kWave + lane, i = c / 6, q = c - 6 * i;
+        const int at_i = __shfl(at_c, i, kWave);
+        cw[j] = *reinterpret_cast<const dd2u*>(x3 + 3 * (int64_t)at_i + 2 * q);
       }
       bnds[wid][lane] = bv_c;
       lds_put<CPR>(tmp, nrow, slabs[wid], lane);
@@ -132,6 +133,29 @@ __global__ void __launch_bounds__(kBlock) k_aprod1(SysView s, int waves, const d
       if (r_out >= 0) y[r_out] = y_out;
       u4 mine[CPR];
       lds_get<CPR>(nrow, slabs[wid], lane, mine);
+      // the windows regrouped per row through the (now free) slab; window
+      // element e = 3j + axis is column at+j of that axis (slot 5 + 4 axis + j)
+      double gx[kSlots];
+      {
+        dd2u* wl = reinterpret_cast<dd2u*>(slabs[wid]);
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+          const int c = j * kWave + lane, i = c / 6, q = c - 6 * i;
+          wl[i * 7 + q] = cw[j];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+          const dd2u pq = wl[lane * 7 + q];
+          const int e0 = 2 * q, e1 = 2 * q + 1;
+          gx[5 + 4 * (e0 % 3) + e0 / 3] = pq.x;
+          gx[5 + 4 * (e1 % 3) + e1 / 3] = pq.y;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+      }
       const int64_t st = tile_star(s, t0, lane, bnds[wid], sf);
       VT a[kSlots];
       __builtin_memcpy(a, mine, sizeof(a));
@@ -517,16 +541,19 @@ StreamShape stream_shape(const SysView& s, int cus, int waves_per_cu) {
   return sh;
 }
 
-hipError_t launch_aprod1(const SysView& s, StreamShape sh, const double* x, double* y, double scale, double ax,
-                         int pmode, Scalars* sc, Work w, int lsqr_stage, hipStream_t st) {
+hipError_t launch_aprod1(const SysView& s, StreamShape sh, const double* x, double* x3w, double* y, double scale,
+                         double ax, int pmode, Scalars* sc, Work w, int lsqr_stage, hipStream_t st) {
+  if (x3w == nullptr) return hipErrorInvalidValue;
+  const hipError_t e = launch_att_interleave(s, x, x3w, st);
+  if (e != hipSuccess) return e;
   const dim3 g(sh.blocks), b(kBlock);
   const size_t lb = sizeof(double) * (size_t)std::max<int64_t>(s.n_instr, 1);
   if (s.value_type == GSR_F32 && pmode == 1)
-    hipLaunchKernelGGL((k_aprod1<float, 1>), g, b, lb, st, s, sh.waves, x, y, scale, ax, sc, w, lsqr_stage);
+    hipLaunchKernelGGL((k_aprod1<float, 1>), g, b, lb, st, s, sh.waves, x, x3w, y, scale, ax, sc, w, lsqr_stage);
   else if (s.value_type == GSR_F32)
-    hipLaunchKernelGGL((k_aprod1<float, 0>), g, b, lb, st, s, sh.waves, x, y, scale, ax, sc, w, lsqr_stage);
+    hipLaunchKernelGGL((k_aprod1<float, 0>), g, b, lb, st, s, sh.waves, x, x3w, y, scale, ax, sc, w, lsqr_stage);
   else
-    hipLaunchKernelGGL((k_aprod1<double, 0>), g, b, lb, st, s, sh.waves, x, y, scale, ax, sc, w, lsqr_stage);
+    hipLaunchKernelGGL((k_aprod1<double, 0>), g, b, lb, st, s, sh.waves, x, x3w, y, scale, ax, sc, w, lsqr_stage);
   return hipGetLastError();
 }
 

@@ -70,6 +70,7 @@ struct gsr_system {
   double* gA = nullptr;  // raw astrometric sums of the fused iteration pass
   double* x3 = nullptr;  // attitude part of vg, axes interleaved, for the fused pass
   float* x3f = nullptr;  // the same rounded to FP32, for the regrouped pass with FP32 products
+  double* x3a = nullptr;  // the attitude part of aprod 1's x, axes interleaved (aprod 1's workspace)
   void* rix = nullptr;   // packed row indices for the fused pass (16 B per row); null: no fused pass
   int fused = 1;         // one pass over the rows per iteration (FP64 products, attitude mode 0 or 3)
   // rows regrouped by attitude window (one pass per iteration where the attitude block exceeds LDS)
@@ -250,6 +251,7 @@ static void release(gsr_system* s) {
     if (e) (void)hipEventDestroy(e);
   dfree(s->x3);
   dfree(s->x3f);
+  dfree(s->x3a);
   dfree(s->rix);
   dfree(s->xr);
   dfree(s->xn);
@@ -508,6 +510,11 @@ static int check_product(gsr_system* s, int32_t product) {
   return GSR_OK;
 }
 
+static int ensure_x3a(gsr_system* s) {
+  if (!s->x3a) CHK(dalloc(&s->x3a, (size_t)std::max<int64_t>(3 * s->s.n_att, 1)));
+  return GSR_OK;
+}
+
 extern "C" int gsr_aprod1(gsr_system* s, const double* x, double* y, double scale_y, int32_t product,
                           gsr_stream stream) {
   CHK(check_handle(s));
@@ -516,7 +523,8 @@ extern "C" int gsr_aprod1(gsr_system* s, const double* x, double* y, double scal
   if (s->s.m > 0) NEED_DEV(y, "y");
   if (s->s.m == 0) return GSR_OK;
   TimeScope ts(s, 0, (hipStream_t)stream);
-  HIPCHK(launch_aprod1(s->s, s->sh, x, y, scale_y, 1.0, product, nullptr, s->wk, 0, (hipStream_t)stream));
+  CHK(ensure_x3a(s));
+  HIPCHK(launch_aprod1(s->s, s->sh, x, s->x3a, y, scale_y, 1.0, product, nullptr, s->wk, 0, (hipStream_t)stream));
   return GSR_OK;
 }
 
@@ -596,6 +604,7 @@ static int ensure_vectors(gsr_system* s) {
   if (!s->var) CHK(dalloc(&s->var, n));
   if (!s->gA) CHK(dalloc(&s->gA, (size_t)std::max<int64_t>(s->s.n_astro, 1)));
   if (!s->x3) CHK(dalloc(&s->x3, (size_t)std::max<int64_t>(3 * s->s.n_att, 1)));
+  CHK(ensure_x3a(s));
   return GSR_OK;
 }
 
@@ -688,7 +697,7 @@ static int lsqr_begin(gsr_system* s, const double* b, const double* x0, const gs
   if (!r0_in_pass) {
     HIPCHK(launch_copy(b, s->u, s->s.m, st));
     if (x0 && s->s.m > 0)
-      HIPCHK(launch_aprod1(s->s, s->sh, x0, s->u, 1.0, -1.0, 0, nullptr, s->wk, 0, st));
+      HIPCHK(launch_aprod1(s->s, s->sh, x0, s->x3a, s->u, 1.0, -1.0, 0, nullptr, s->wk, 0, st));
   }
   if (s->con.ncon > 0) HIPCHK(launch_copy(s->con_rhs, uc, s->con.ncon, st));
   if (x0) HIPCHK(launch_con_aprod1(s->con, x0, uc, 1.0, -1.0, nullptr, s->wk, st));
@@ -835,7 +844,7 @@ static int enqueue_iteration(gsr_system* s, hipStream_t st) {
   } else {
     {
       TimeScope ts(s, 0, st);
-      HIPCHK(launch_aprod1(s->s, s->sh, vg, s->u, 0.0, 1.0, s->pmode, s->sc, s->wk, 1, st));
+      HIPCHK(launch_aprod1(s->s, s->sh, vg, s->x3a, s->u, 0.0, 1.0, s->pmode, s->sc, s->wk, 1, st));
     }
     CHK(aprod2_launches(s, s->u, s->v, S, 0.0, s->pmode, 0, s->sc, 1, st));
   }

@@ -151,7 +151,9 @@ struct TailLsqr {
 // ---- launchers (all asynchronous on `st`) ---------------------------------
 // y <- scale*y + ax * A x (or with the LSQR scalars: scale = sc->u_scale, ax = 1,
 // and the last workgroup forms beta_{i+1}); mode: 0 FP64 products, 1 FP32 products.
-hipError_t launch_aprod1(const SysView& s, StreamShape sh, const double* x, double* y, double scale,
+// x3w: 3 n_att doubles of workspace, which first takes the attitude part of x with
+// the axes interleaved (the kernel loads each row's 12 values as one window).
+hipError_t launch_aprod1(const SysView& s, StreamShape sh, const double* x, double* x3w, double* y, double scale,
                          double ax, int pmode, Scalars* sc, Work w, int lsqr_stage, hipStream_t st);
 // astro part of x <- scale*x + S*(A^T (inv_beta*y)); tail part accumulated in acc
 // (attitude part by the bucketed pass when att_mode == 3).
