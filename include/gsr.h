@@ -102,7 +102,9 @@ int gsr_destroy(gsr_system *sys);
  *   x device [n], y device [m] (must not overlap).  scale_y = 1 gives the
  *   paper's "b += A x"; scale_y = 0 overwrites y without reading it.
  *   product GSR_PROD_F32 (FP32 systems only) forms each a*x in FP32 from
- *   fl32(x); sums are always FP64.
+ *   fl32(x); sums are always FP64.  The attitude part of x is first copied,
+ *   axes interleaved, into a handle workspace (3 n_att doubles), from which
+ *   each tile's 12-value windows are loaded together.
  */
 int gsr_aprod1(gsr_system *sys, const double *x, double *y, double scale_y, int32_t product,
                gsr_stream stream);
