@@ -74,11 +74,16 @@ __global__ void k_blk_rows(SysView s, BlkView bv, const uint32_t* __restrict__ s
   }
 }
 
+// ub <- src in the regrouped order: coalesced reads of src, and each wave's
+// writes fall in runs of consecutive positions (the rows of one block keep
+// their order); the padding positions are cleared.
 __global__ void k_blk_permute(BlkView bv, const double* __restrict__ src) {
-  for (int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pos < bv.mp;
-       pos += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t r = bv.perm[pos];
-    bv.ub[pos] = r >= 0 ? src[r] : 0.0;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < bv.m + bv.npad;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    if (r < bv.m)
+      bv.ub[bv.ipos[r]] = src[r];
+    else
+      bv.ub[bv.pad[r - bv.m]] = 0.0;
   }
 }
 
@@ -417,13 +422,15 @@ hipError_t launch_seg_reduce(const SysView& s, const BlkView& bv, double* gA, Sc
 }
 
 hipError_t launch_blk_permute(const BlkView& bv, const double* src, hipStream_t st) {
-  const int blocks = (int)std::min<int64_t>(8192, (bv.mp + kBlock - 1) / kBlock);
+  if (bv.ipos == nullptr) return hipErrorInvalidValue;
+  const int blocks = (int)std::min<int64_t>(8192, (bv.m + bv.npad + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_blk_permute, dim3(std::max(blocks, 1)), dim3(kBlock), 0, st, bv, src);
   return hipGetLastError();
 }
 
 void blk_free(BlkView* bv) {
-  for (void* p : {(void*)bv->T, (void*)bv->R, (void*)bv->perm, (void*)bv->wg_block, (void*)bv->wave_tile,
+  for (void* p : {(void*)bv->T, (void*)bv->R, (void*)bv->perm, (void*)bv->ipos, (void*)bv->pad,
+                  (void*)bv->wg_block, (void*)bv->wave_tile,
                   (void*)bv->seg_base, (void*)bv->bsub, (void*)bv->grp_base, (void*)bv->grp_cnt,
                   (void*)bv->grp_list, (void*)bv->P, (void*)bv->Q, (void*)bv->ub, (void*)bv->dummy})
     if (p) (void)hipFree(p);
@@ -590,6 +597,33 @@ int blk_build(const SysView& s, BlkView* bv, int cus, int max_window, int lds_ma
   }
   (void)hipFree(se_d);
   if (!ok) return failed(GSR_EHIP, "building the regrouped copy failed");
+  // from here on the permutation is applied row by row: perm's buffer takes the
+  // position of each original row, and the padding positions get a list of their own
+  {
+    std::vector<int32_t> ipos((size_t)m);
+    std::vector<int32_t> pads;
+    for (int64_t pos = 0; pos < mp; ++pos) {
+      const int32_t r = perm[(size_t)pos];
+      if (r >= 0)
+        ipos[(size_t)r] = (int32_t)pos;
+      else
+        pads.push_back((int32_t)pos);
+    }
+    bv->m = m;
+    bv->npad = (int64_t)pads.size();
+    bv->ipos = bv->perm;
+    bv->perm = nullptr;
+    if (!dalloc_((void**)&bv->pad, pads.size() * 4)) {
+      (void)hipGetLastError();
+      return failed(GSR_ENOMEM, "device memory for the regrouped copy");
+    }
+    if (hipMemcpy(bv->ipos, ipos.data(), (size_t)m * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        (!pads.empty() && hipMemcpy(bv->pad, pads.data(), pads.size() * 4, hipMemcpyHostToDevice) != hipSuccess) ||
+        hipMemset(bv->ub, 0, (size_t)mp * 8) != hipSuccess) {
+      (void)hipGetLastError();
+      return failed(GSR_EHIP, "building the regrouped copy failed");
+    }
+  }
   // allow the dynamic LDS size beyond 64 KB (where the runtime asks for it)
   (void)hipFuncSetAttribute((const void*)k_fblk<double, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bv->lds);
   (void)hipFuncSetAttribute((const void*)k_fblk<float, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bv->lds);

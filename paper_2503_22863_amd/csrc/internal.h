@@ -123,7 +123,11 @@ struct BlkView {
   size_t lds;           // dynamic LDS bytes of the pass
   void* T;              // [ntiles][CPR][64] 16-byte chunks of the coefficients
   uint32_t* R;          // [mp][4] row records: star | att_start - g*Wb (13 bits) << 32 | instr (11 bits each) | end bit
-  int32_t* perm;        // [mp] original row of each position (-1: padding)
+  int64_t m;            // rows of the system
+  int32_t* perm;        // [mp] original row of each position (-1: padding); only while the copy is built
+  int32_t* ipos;        // [m] position of each original row (perm's buffer, once built)
+  int32_t* pad;         // [npad] padding positions
+  int64_t npad;
   int32_t* wg_block;    // [G] block of each workgroup
   int32_t* wave_tile;   // [kBlkWaves*G + 1] first tile of each wave
   int32_t* seg_base;    // [kBlkWaves*G] segments before each wave's range
