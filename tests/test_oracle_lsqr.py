@@ -253,3 +253,86 @@ def test_refinement_stop_rule_predicts_the_next_correction(oracle_lib, inner_tol
     nxt = np.linalg.norm(dx) / np.linalg.norm(x)
     assert out["outer_steps"] < 10  # stopped by the rule, not by outer_max
     assert nxt <= 10 * tol, nxt
+
+
+def _scipy_out(A, b, **kw):
+    out = scipy_lsqr(sp.csr_matrix(A), b, **kw)
+    keys = ("x", "istop", "itn", "r1norm", "r2norm", "anorm", "acond", "arnorm", "xnorm", "var")
+    return dict(zip(keys, out))
+
+
+@pytest.mark.parametrize("damp", [0.0, 0.4])
+@pytest.mark.parametrize("k", [3, 9, 15])
+def test_estimates_match_scipy(oracle_lib, damp, k):
+    """The Paige-Saunders estimates after k iterations -- the Frobenius estimate anorm,
+    the condition estimate acond = anorm ||D_k||_F (D_k the search directions d_i =
+    w_i / rho_i), rnorm of the damped problem and ||A^T r|| -- against scipy's
+    independent LSQR, before loss of orthogonality makes the iterates (and with them
+    alpha_i, beta_i and every estimate) depend on rounding."""
+    g = _small(seed=71)
+    o = oracle_lib.OSystem(g)
+    A = dense_A(g)
+    b = oracle_lib.known_terms(o, g.x_true, g.noise)
+    s = _scipy_out(A, b, damp=damp, atol=0.0, btol=0.0, conlim=0.0, iter_lim=k)
+    r = oracle_lib.lsqr(o, b, damp=damp, atol=0.0, btol=0.0, itmax=k, precond=False)
+    assert r["itn"] == s["itn"] == k and r["istop"] == s["istop"] == 7
+    for ok, sk in (("anorm", "anorm"), ("acond", "acond"), ("rnorm", "r2norm"), ("arnorm", "arnorm")):
+        assert abs(r[ok] - s[sk]) <= 1e-12 * abs(s[sk]), (ok, r[ok], s[sk])
+
+
+def test_acond_is_frobenius_of_the_bidiagonal_inverse(oracle_lib):
+    """acond = anorm * ||D_k||_F where D_k = V_k R_k^{-1} and the Golub-Kahan closed form
+    gives ||D_k||_F^2 = trace(V_k (B_k^T B_k)^{-1} V_k^T) = trace((B_k^T B_k)^{-1}); anorm
+    is the Frobenius norm of B_k (sum of alpha_i^2 + beta_{i+1}^2).  Checked against
+    the dense bidiagonalisation with full reorthogonalisation."""
+    g = _small(seed=72, n_stars=20, obs=30)
+    o = oracle_lib.OSystem(g)
+    A = dense_A(g)
+    b = oracle_lib.known_terms(o, g.x_true, g.noise)
+    k = 10
+    r = oracle_lib.lsqr(o, b, atol=0, btol=0, itmax=k, precond=False)
+    M = _golub_kahan_cov(A, b, k)
+    assert abs(r["acond"] / r["anorm"] - np.sqrt(np.trace(M))) <= 1e-10 * np.sqrt(np.trace(M))
+
+
+def test_conlim_stop_matches_scipy(oracle_lib):
+    """conlim > 0 (ctol = 1/conlim): the solve stops with istop 3 at the first iteration
+    whose condition estimate reaches conlim; the stop iteration, x and the estimates
+    agree with scipy's LSQR (Paige-Saunders stop rules, lowest-numbered test first)."""
+    g = _small(seed=61)
+    o = oracle_lib.OSystem(g)
+    A = dense_A(g)
+    b = oracle_lib.known_terms(o, g.x_true, g.noise)
+    s = _scipy_out(A, b, atol=1e-14, btol=1e-14, conlim=30.0, iter_lim=3000)
+    r = oracle_lib.lsqr(o, b, atol=1e-14, btol=1e-14, conlim=30.0, itmax=3000, precond=False)
+    assert r["istop"] == s["istop"] == 3
+    assert r["itn"] == s["itn"]
+    assert r["acond"] >= 30.0 and s["acond"] >= 30.0
+    assert abs(r["acond"] - s["acond"]) <= 1e-12 * s["acond"]
+    assert _rel(r["x"], s["x"]) < 1e-11
+    # without the limit the same system runs on (and its estimate passes conlim)
+    r2 = oracle_lib.lsqr(o, b, atol=1e-14, btol=1e-14, conlim=0.0, itmax=3000, precond=False)
+    assert r2["istop"] != 3 and r2["itn"] > r["itn"]
+
+
+@pytest.mark.parametrize("case,expect", [("consistent", 4), ("inconsistent", 5)])
+def test_machine_precision_stops_match_scipy(oracle_lib, case, expect):
+    """atol = btol = 0: a consistent system stops on the machine-precision form of test 1
+    (istop 4), a clearly inconsistent one on that of test 2 (istop 5), as in scipy.  The
+    stop iterations lie far past the loss of orthogonality, so they agree to a few
+    iterations only."""
+    if case == "consistent":
+        g = _small(seed=62)
+        nf = 0.0
+    else:
+        g = _small(seed=63)
+        nf = 1e4
+    o = oracle_lib.OSystem(g)
+    A = dense_A(g)
+    b = oracle_lib.known_terms(o, g.x_true, g.noise * nf)
+    s = _scipy_out(A, b, atol=0.0, btol=0.0, conlim=0.0, iter_lim=3000)
+    r = oracle_lib.lsqr(o, b, atol=0.0, btol=0.0, conlim=0.0, itmax=3000, precond=False)
+    assert r["istop"] == s["istop"] == expect
+    assert abs(r["itn"] - s["itn"]) <= 0.05 * s["itn"]
+    x_ls = np.linalg.lstsq(A, b, rcond=None)[0]
+    assert _rel(r["x"], x_ls) < 1e-12
