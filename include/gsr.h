@@ -181,7 +181,9 @@ int gsr_lsqr_end(gsr_system *sys, double *x, double *var, gsr_lsqr_result *res, 
  * product = GSR_PROD_F32 and loose atol/btol), and updates x += dx, until
  * the correction, or the next one predicted from the contraction between the
  * last two, is at most outer_tol ||x||, or outer_max steps.  Arguments as
- * gsr_lsqr_solve.
+ * gsr_lsqr_solve, except that damp must be 0 (GSR_EINVAL otherwise): each
+ * inner solve would damp its correction towards zero rather than x towards
+ * x0, so the outer loop would not converge to the damped solution.
  */
 int gsr_lsqr_refine(gsr_system *sys, const double *b, const double *x0, double *x,
                     const gsr_lsqr_opts *inner, gsr_lsqr_result *res, gsr_stream stream);

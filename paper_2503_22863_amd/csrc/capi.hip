@@ -1032,6 +1032,9 @@ extern "C" int gsr_lsqr_refine(gsr_system* s, const double* b, const double* x0,
   if (s->s.value_type != GSR_F32) return fail(GSR_EINVAL, "gsr_lsqr_refine needs an FP32 system");
   if (s->con.ncon > 0) return fail(GSR_EINVAL, "gsr_lsqr_refine does not take constraint equations");
   if (o->outer_max < 1 || !(o->outer_tol >= 0)) return fail(GSR_EINVAL, "outer_max >= 1, outer_tol >= 0");
+  // each inner solve would damp its correction dx towards zero, not x towards x0:
+  // the outer loop would then converge to the undamped solution, not the damped one
+  if (o->damp != 0.0) return fail(GSR_EINVAL, "gsr_lsqr_refine solves the undamped problem (damp must be 0)");
   NEED_DEV(x, "x");
   if (s->s.m > 0) NEED_DEV(b, "b");
   hipStream_t st = (hipStream_t)stream;
