@@ -109,6 +109,19 @@ int gsr_destroy(gsr_system *sys);
 int gsr_aprod1(gsr_system *sys, const double *x, double *y, double scale_y, int32_t product,
                gsr_stream stream);
 /*
+ * gsr_aprod1 without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, kernels and results as gsr_aprod1, on
+ * handles made by gsr_create.  Its workspace, the interleaved attitude part
+ * of x, lives in a static device array of 4 MiB per GPU held until the
+ * process ends: 3 * n_att must not exceed 524,288 (GSR_EINVAL otherwise).
+ * The handle's device must be current.  Every call on one GPU shares that
+ * array, so calls that overlap on one GPU (other streams, other threads,
+ * other handles) race and must be ordered by the caller.
+ */
+int gsr_aprod1_noalloc(gsr_system *sys, const double *x, double *y, double scale_y, int32_t product,
+                       gsr_stream stream);
+/*
  * aprod 2 (Sec. 2, Eq. 3): x <- scale_x * x + A^T y.
  *   y device [m], x device [n] (must not overlap).  Same conventions as
  *   gsr_aprod1.  Attitude / instrumental / global sums use FP64 atomics, so

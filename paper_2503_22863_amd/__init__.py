@@ -75,6 +75,7 @@ _SIGS = {
     "gsr_destroy": (C.c_int, [C.c_void_p]),
     "gsr_aprod1": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int32, C.c_void_p]),
     "gsr_aprod2": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int32, C.c_void_p]),
+    "gsr_aprod1_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int32, C.c_void_p]),
     "gsr_column_scale": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "gsr_lsqr_solve": (C.c_int, [C.c_void_p] * 8),
     "gsr_lsqr_begin": (C.c_int, [C.c_void_p] * 5),
@@ -322,6 +323,12 @@ class System:
             y = self._new(self.m)
             scale = 0.0
         _check(lib().gsr_aprod1(self._h, _ptr(x), _ptr(y), float(scale), _prod(product), _stream(stream)))
+        return y
+
+    def aprod1_noalloc(self, x, y, scale=0.0, product="f64", stream=None):
+        """gsr_aprod1 with its workspace in the library's static device scratch (no allocation)."""
+        _check(lib().gsr_aprod1_noalloc(self._h, _ptr(x), _ptr(y), float(scale), _prod(product),
+                                        _stream(stream)))
         return y
 
     def aprod2(self, y, x=None, scale=0.0, product="f64", stream=None):

@@ -273,6 +273,8 @@ static void release(gsr_system* s) {
   delete s;
 }
 
+static void resolve_scratch(int dev);
+
 extern "C" int gsr_create(gsr_system** out, const gsr_dims* d, const void* vals, const int64_t* star_row_ptr,
                           const int32_t* att_start, const int32_t* instr_col, gsr_stream stream) {
   if (!out) return fail(GSR_EINVAL, "out is null");
@@ -313,6 +315,7 @@ extern "C" int gsr_create(gsr_system** out, const gsr_dims* d, const void* vals,
   v.has_empty_stars = 0;
   (void)hipGetDevice(&s->device);
   s->cus = device_cus();
+  resolve_scratch(s->device);  // set-up of gsr_aprod1_noalloc, once per device
 
   int rc = GSR_OK;
   auto bail = [&](int code) {
@@ -525,6 +528,59 @@ extern "C" int gsr_aprod1(gsr_system* s, const double* x, double* y, double scal
   TimeScope ts(s, 0, (hipStream_t)stream);
   CHK(ensure_x3a(s));
   HIPCHK(launch_aprod1(s->s, s->sh, x, s->x3a, y, scale_y, 1.0, product, nullptr, s->wk, 0, (hipStream_t)stream));
+  return GSR_OK;
+}
+
+// ------------------------------------------------- aprod 1 without allocation
+// The only workspace of the standalone aprod 1 is the interleaved attitude
+// part of x (3 n_att doubles).  gsr_aprod1_noalloc takes it from this
+// file-scope device array instead of a handle allocation; every GPU the
+// library runs on holds its own copy for the life of the process.  Host code
+// never passes the array's name to a kernel (on the host it is only a
+// stand-in symbol): its device address is looked up once per device, with that
+// device current, when the first handle on the device is created.
+constexpr int64_t kScratchDoubles = (int64_t)1 << 19;  // 4 MiB: attitude blocks up to 174,762 per axis
+static __device__ __align__(256) double scratch[kScratchDoubles];
+constexpr int kMaxDevices = 64;
+static double* g_scratch[kMaxDevices] = {};
+static int g_scratch_rc[kMaxDevices] = {};  // 0 not looked up, 1 resolved, -1 lookup failed
+
+static void resolve_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (g_scratch_rc[dev] != 0) return;
+  double* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || p == nullptr) {
+    (void)hipGetLastError();
+    g_scratch_rc[dev] = -1;
+    return;
+  }
+  g_scratch[dev] = p;
+  g_scratch_rc[dev] = 1;
+}
+
+extern "C" int gsr_aprod1_noalloc(gsr_system* s, const double* x, double* y, double scale_y, int32_t product,
+                                  gsr_stream stream) {
+  CHK(check_handle(s));
+  CHK(check_product(s, product));
+  NEED_DEV(x, "x");
+  if (s->s.m > 0) NEED_DEV(y, "y");
+  if (3 * s->s.n_att > kScratchDoubles)
+    return fail(GSR_EINVAL, "3 * n_att = %lld exceeds the no-allocation scratch of %lld doubles",
+                (long long)(3 * s->s.n_att), (long long)kScratchDoubles);
+  if (s->s.m == 0) return GSR_OK;
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev != s->device) return fail(GSR_EINVAL, "the handle's device must be current");
+  double* ptr = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (dev >= 0 && dev < kMaxDevices && g_scratch_rc[dev] == 1) ptr = g_scratch[dev];
+  }
+  if (!ptr) return fail(GSR_EHIP, "the device address of the no-allocation scratch is not available");
+  // no timing scope here: recording events may allocate them
+  HIPCHK(launch_aprod1(s->s, s->sh, x, ptr, y, scale_y, 1.0, product, nullptr, s->wk, 0, (hipStream_t)stream));
   return GSR_OK;
 }
 
