@@ -26,10 +26,15 @@
  *  - Pointers marked "device" must be device memory of the current HIP
  *    device (e.g. from hipMalloc or a PyTorch tensor); "host" pointers are
  *    ordinary host memory.  Arrays are dense and C-ordered.
- *  - The system arrays are BORROWED by the handle (never copied): the caller
- *    keeps them alive and unchanged until gsr_destroy.  The library allocates
- *    and frees its own workspaces (vectors of the solve, scalars, partial
- *    sums, covariance buffers).
+ *  - The system arrays are BORROWED by the handle: the caller keeps them
+ *    alive and unchanged until gsr_destroy.  A handle made by
+ *    gsr_create_packed holds no copy of the coefficients at all.  A handle
+ *    made by gsr_create over rows in star order makes, at the first solve
+ *    that needs it, a library-owned copy of the rows regrouped by attitude
+ *    window (about the bytes of A; see gsr_set_blocked) and, for star-order
+ *    passes, further row-level copies (see gsr_create).  The library
+ *    allocates and frees its own workspaces (vectors of the solve, scalars,
+ *    partial sums, covariance buffers, index records).
  *  - `stream` is a hipStream_t (NULL: the null stream).  Calls are
  *    asynchronous on it unless stated otherwise.  A handle is not
  *    thread-safe and its calls must be ordered on one stream; separate
@@ -45,6 +50,7 @@ extern "C" {
 #endif
 
 typedef struct gsr_system gsr_system;
+typedef struct gsr_layout gsr_layout;
 typedef struct gsr_mlp gsr_mlp;
 typedef void *gsr_stream; /* hipStream_t */
 
@@ -88,12 +94,15 @@ int gsr_create(gsr_system **out, const gsr_dims *d, const void *vals, const int6
 /* gsr_create also packs the instrumental columns and attitude start of each
  * row (16 bytes per row) for the one-pass iteration.  When 3*n_att + n_instr +
  * n_glob exceeds 2048 (the attitude block does not fit in LDS) the handle makes
- * further library-owned copies at their first use: the rows regrouped by
- * attitude window for LSQR solves (gsr_set_blocked), and, for gsr_aprod2 and
- * solves not on that copy, the 12 attitude coefficients of every row grouped
- * by attitude start plus the other 12 in row order (about 200 bytes per FP64
- * row), so that aprod 2 needs no global atomics.  If an allocation fails the
- * handle falls back to the star-order passes, or to atomics. */
+ * further library-owned COPIES OF THE COEFFICIENTS at their first use: the
+ * rows regrouped by attitude window for LSQR solves and gsr_aprod12 (192
+ * bytes per FP64 row plus 28 of indices; gsr_set_blocked), and, for
+ * gsr_aprod2 and solves not on that copy, the 12 attitude coefficients of
+ * every row grouped by attitude start plus the other 12 in row order (about
+ * 200 bytes per FP64 row), so that aprod 2 needs no global atomics.  If an
+ * allocation fails the handle falls back to the star-order passes, or to
+ * atomics.  To solve without any copy of A, place the rows yourself
+ * (gsr_layout_plan / gsr_layout_pack / gsr_create_packed). */
 /* Free the handle's workspaces (synchronises the device first).  NULL is a no-op. */
 int gsr_destroy(gsr_system *sys);
 
@@ -326,19 +335,87 @@ int gsr_set_fused(gsr_system *sys, int32_t on);
  * the bytes of A plus 28 bytes per row and is kept until gsr_destroy or a
  * change of max_window.  Without memory for it, solves use the bucketed
  * pass.  Results agree with the other forms up to summation order.  Fails
- * with GSR_ESTATE during a solve. */
+ * with GSR_ESTATE during a solve.  On a handle from gsr_create_packed the
+ * layout is fixed: only on = 1 with max_window = 0 is accepted. */
 int gsr_set_blocked(gsr_system *sys, int32_t on, int32_t max_window);
 
 typedef struct {
-    int32_t active;       /* 1 once the regrouped copy exists */
+    int32_t active;       /* 1 once the handle's regrouped rows exist */
     int32_t workgroups;   /* of its pass */
     int64_t window;       /* Wb: attitude starts per block */
     int64_t blocks;
     int64_t padded_rows;  /* rows including the padding to 64-row tiles */
     int64_t segments;     /* star segments (astrometric partial sums per pass) */
-    int64_t bytes;        /* device bytes held by the copy */
+    int64_t bytes;        /* device bytes the library holds for the layout besides the
+                             coefficients: row records (16 B per row), positions, segment
+                             lists and sums, workgroup windows, u in this order */
+    int64_t value_bytes;  /* coefficient bytes of the regrouped rows (padding included):
+                             padded_rows * 24 * sizeof(value) */
+    int32_t values_owned; /* 1: the coefficients are the library's copy (gsr_create);
+                             0: the caller's buffer (gsr_create_packed) */
+    int32_t reserved;
 } gsr_blocked_layout;
 int gsr_blocked_info(gsr_system *sys, gsr_blocked_layout *info);
+
+/*
+ * Rows placed by the caller in the regrouped order (no library copy of A).
+ * The one-pass iteration streams the rows grouped by attitude window (block
+ * g = att_start / Wb, star order inside a block, 64-row tiles stored
+ * chunk-major, blocks padded with zero rows to whole tiles): Sec. 2's
+ * products (Eq. 2 and Eq. 3) then read each coefficient once per iteration.
+ * Since GPU memory bounds the system one GPU can hold (Sec. 2.1), a caller
+ * with a large system computes the layout from its index data, places its
+ * coefficients there once while loading them, and hands the buffer over:
+ *
+ * gsr_layout_plan: the layout of a system from its index arrays (device
+ *   pointers, as for gsr_create; validated the same way); max_window > 0
+ *   caps Wb (>= 4), 0 takes the widest window that fits in LDS.  Needs
+ *   m > 0, n_att >= 8 and n_instr <= 2047.  The caller may free its index
+ *   arrays afterwards: the layout keeps 16-byte records per row (star,
+ *   attitude start, instrumental columns).  Synchronous.
+ * gsr_layout_info: sizes of the layout (active = 0, values_owned = 0); the
+ *   caller allocates value_bytes of device memory for the packed rows
+ *   (16-byte aligned).
+ * gsr_layout_pack: rows row0 .. row0+count-1 (caller's star order), given as
+ *   device [count][24] coefficients of the dims' value type, into their
+ *   places in packed.  Any chunking and order of calls; every row must be
+ *   placed once before gsr_create_packed.  Asynchronous on `stream`.
+ * gsr_create_packed: a handle over the packed rows.  The handle borrows
+ *   `packed` (kept alive and, apart from the padding rows, which this call
+ *   zeroes, unchanged until gsr_destroy) and takes the layout over: on
+ *   success the layout is consumed (not to be used or destroyed again); on
+ *   failure it stays with the caller.  Every product, solve, covariance and
+ *   constraint call works on such a handle, with vectors in the caller's
+ *   row order; LSQR always runs the one-pass iteration (gsr_set_fused(0) and
+ *   gsr_set_blocked(0) are refused), the standalone products run the same
+ *   pass (one pass reads every coefficient) and fail with GSR_ESTATE while a
+ *   solve is in progress; gsr_features and gsr_aprod1_noalloc, which read
+ *   rows in star order, are refused.  Synchronous.
+ * gsr_layout_destroy: frees a layout that was not consumed (NULL: no-op).
+ */
+int gsr_layout_plan(gsr_layout **out, const gsr_dims *d, const int64_t *star_row_ptr, const int32_t *att_start,
+                    const int32_t *instr_col, int32_t max_window, gsr_stream stream);
+int gsr_layout_info(gsr_layout *layout, gsr_blocked_layout *info);
+int gsr_layout_pack(gsr_layout *layout, const void *rows, int64_t row0, int64_t count, void *packed,
+                    gsr_stream stream);
+int gsr_create_packed(gsr_system **out, gsr_layout *layout, void *packed, gsr_stream stream);
+int gsr_layout_destroy(gsr_layout *layout);
+
+/*
+ * Both products of an LSQR iteration in one pass over the regrouped rows
+ * (Sec. 2, Eq. 2 then Eq. 3 on the updated vector):
+ *   u <- scale_u * u + A v,   then   x <- scale_x * x + A^T u  (the new u).
+ *   v device [n], u device [m] (caller's row order), x device [n]; v and x must
+ *   not overlap.  product as for gsr_aprod1.  This is the pass the LSQR
+ *   iteration runs every step, exposed with plain vectors.  On a handle from
+ *   gsr_create it builds the library's regrouped copy at first use
+ *   (GSR_ENOMEM without memory for it).  A^T u sums use FP64 LDS atomics and
+ *   per-segment partials, so their order (last bits) may vary between calls.
+ *   Fails with GSR_ESTATE while a solve is in progress and with GSR_EINVAL
+ *   when constraint equations are attached.
+ */
+int gsr_aprod12(gsr_system *sys, const double *v, double *u, double scale_u, double *x, double scale_x,
+                int32_t product, gsr_stream stream);
 
 /* Per-kernel timing with HIP events on the solve's stream (off by default).
  * gsr_timing_get synchronises, returns the totals since the last get and

@@ -49,7 +49,8 @@ class LsqrResult(C.Structure):
 
 class BlockedInfo(C.Structure):
     _fields_ = [("active", C.c_int32), ("workgroups", C.c_int32), ("window", C.c_int64), ("blocks", C.c_int64),
-                ("padded_rows", C.c_int64), ("segments", C.c_int64), ("bytes", C.c_int64)]
+                ("padded_rows", C.c_int64), ("segments", C.c_int64), ("bytes", C.c_int64),
+                ("value_bytes", C.c_int64), ("values_owned", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -76,6 +77,14 @@ _SIGS = {
     "gsr_aprod1": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int32, C.c_void_p]),
     "gsr_aprod2": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int32, C.c_void_p]),
     "gsr_aprod1_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int32, C.c_void_p]),
+    "gsr_aprod12": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_double, C.c_int32,
+                              C.c_void_p]),
+    "gsr_layout_plan": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                  C.c_void_p]),
+    "gsr_layout_info": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "gsr_layout_pack": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p]),
+    "gsr_create_packed": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gsr_layout_destroy": (C.c_int, [C.c_void_p]),
     "gsr_column_scale": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "gsr_lsqr_solve": (C.c_int, [C.c_void_p] * 8),
     "gsr_lsqr_begin": (C.c_int, [C.c_void_p] * 5),
@@ -268,6 +277,53 @@ def _opts(damp=0.0, atol=1e-12, btol=1e-12, conlim=0.0, itmax=200, precond=True,
                     _prod(product), int(outer_max), float(outer_tol))
 
 
+class Layout:
+    """The regrouped row order of a system, computed from its index arrays
+    (gsr_layout_plan).  The caller allocates ``info()["value_bytes"]`` of
+    device memory, places its rows there with ``pack`` and hands the buffer
+    to ``System.from_packed``, which consumes the layout."""
+
+    def __init__(self, star_row_ptr, att_start, instr_col, n_att, n_instr, n_glob=1, value_type=GSR_F64,
+                 max_window=0, stream=None):
+        if star_row_ptr.dtype != torch.int64 or att_start.dtype != torch.int32 or instr_col.dtype != torch.int32:
+            raise TypeError("star_row_ptr int64, att_start int32, instr_col int32")
+        n_stars = star_row_ptr.numel() - 1
+        m = att_start.numel()
+        self.dims = Dims(n_stars, m, n_att, n_instr, n_glob, value_type)
+        self.value_type = value_type
+        self.device = att_start.device
+        h = C.c_void_p()
+        _check(lib().gsr_layout_plan(C.byref(h), C.byref(self.dims), _ptr(star_row_ptr), _ptr(att_start),
+                                     _ptr(instr_col), int(max_window), _stream(stream)))
+        self._h = h
+
+    def info(self):
+        i = BlockedInfo()
+        _check(lib().gsr_layout_info(self._h, C.byref(i)))
+        return i.as_dict()
+
+    def new_buffer(self):
+        """Device tensor of the packed rows' size ([padded_rows, 24] of the value type)."""
+        dt = torch.float32 if self.value_type == GSR_F32 else torch.float64
+        return torch.empty((self.info()["padded_rows"], 24), dtype=dt, device=self.device)
+
+    def pack(self, rows, row0, packed, stream=None):
+        """Place rows row0 .. row0+len(rows)-1 (device [count, 24]) into packed."""
+        _check(lib().gsr_layout_pack(self._h, _ptr(rows), int(row0), int(rows.shape[0]), _ptr(packed),
+                                     _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(lib().gsr_layout_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class System:
     """A handle over a system held in device tensors (borrowed; kept alive here)."""
 
@@ -293,6 +349,44 @@ class System:
                                 _ptr(instr_col), _stream(stream)))
         self._h = h
         self.ncov = 0
+
+    @classmethod
+    def from_packed(cls, layout, packed, stream=None):
+        """A handle over rows placed by ``layout.pack`` into ``packed`` (borrowed; the
+        library holds no copy of the coefficients).  Consumes the layout."""
+        self = cls.__new__(cls)
+        self.vals, self.star_row_ptr, self.att_start, self.instr_col = None, None, None, None
+        self.packed = packed
+        d = layout.dims
+        self.dims = Dims(d.n_stars, d.m, d.n_att, d.n_instr, d.n_glob, d.value_type)
+        self.n_stars, self.m, self.n_att, self.n_instr, self.n_glob = d.n_stars, d.m, d.n_att, d.n_instr, d.n_glob
+        self.n = int(lib().gsr_num_unknowns(C.byref(self.dims)))
+        self.value_type = d.value_type
+        self.device = packed.device
+        h = C.c_void_p()
+        _check(lib().gsr_create_packed(C.byref(h), layout._h, _ptr(packed), _stream(stream)))
+        layout._h = None  # consumed
+        self._h = h
+        self.ncov = 0
+        return self
+
+    @classmethod
+    def packed_from_generated(cls, g, device="cuda", value_dtype=None, max_window=0, chunk_rows=1 << 22):
+        """Load a gsr_synth system the way a caller without room for two copies of A
+        would: upload the index arrays, plan the layout, move the coefficients in
+        chunks of ``chunk_rows`` rows through a staging buffer into their places,
+        and free the index arrays.  The device then holds one copy of A."""
+        vals = g.vals if value_dtype is None else g.vals.astype(value_dtype)
+        vt = GSR_F32 if vals.dtype == np.float32 else GSR_F64
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)
+        L = Layout(t(g.star_row_ptr), t(g.att_start), t(g.instr_col), g.dims.n_att, g.dims.n_instr, g.dims.n_glob,
+                   value_type=vt, max_window=max_window)
+        packed = L.new_buffer()
+        m = vals.shape[0]
+        for r0 in range(0, m, chunk_rows):
+            L.pack(t(vals[r0:r0 + chunk_rows]), r0, packed)
+            torch.cuda.synchronize(packed.device)  # the staging tensor may be freed
+        return cls.from_packed(L, packed)
 
     @classmethod
     def from_generated(cls, g, device="cuda", value_dtype=None):
@@ -330,6 +424,15 @@ class System:
         _check(lib().gsr_aprod1_noalloc(self._h, _ptr(x), _ptr(y), float(scale), _prod(product),
                                         _stream(stream)))
         return y
+
+    def aprod12(self, v, u, x=None, scale_u=1.0, scale_x=0.0, product="f64", stream=None):
+        """Both products in one pass: u <- scale_u*u + A v, then x <- scale_x*x + A^T u (new u)."""
+        if x is None:
+            x = self._new(self.n)
+            scale_x = 0.0
+        _check(lib().gsr_aprod12(self._h, _ptr(v), _ptr(u), float(scale_u), _ptr(x), float(scale_x),
+                                 _prod(product), _stream(stream)))
+        return u, x
 
     def aprod2(self, y, x=None, scale=0.0, product="f64", stream=None):
         """Eq. (3): x <- scale*x + A^T y."""

@@ -45,32 +45,55 @@ __device__ __forceinline__ void rec_pack(uint32_t* R, int64_t pos, uint32_t star
   reinterpret_cast<u4*>(R)[pos] = v;
 }
 
-// Builds the chunk-major coefficient tiles and the row records.  se[pos]:
+// Row records of every position: for original row r at ipos[r] its star, the
+// attitude start within the block's window and the instrumental columns; for
+// a padding position the star it repeats and zero columns.  se[pos]:
 // star | end << 31.
-template <typename VT>
-__global__ void k_blk_rows(SysView s, BlkView bv, const uint32_t* __restrict__ se) {
-  constexpr int CPR = Geo<VT>::CPR;
-  const u4* src = reinterpret_cast<const u4*>(s.vals);
-  u4* T = reinterpret_cast<u4*>(bv.T);
-  for (int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pos < bv.mp;
-       pos += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = bv.perm[pos];
-    const int64_t tile = pos / kWave, lane = pos - tile * kWave;
-    u4* dst = T + tile * CPR * kWave + lane;
+__global__ void k_blk_records(SysView s, BlkView bv, const uint32_t* __restrict__ se) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < bv.m + bv.npad;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t pos = i < bv.m ? bv.ipos[i] : bv.pad[i - bv.m];
     int ic[6] = {0, 0, 0, 0, 0, 0};
     uint32_t off = 0;
-    if (r >= 0) {
+    if (i < bv.m) {
+      off = (uint32_t)(s.att_start[i] % bv.Wb);
 #pragma unroll
-      for (int j = 0; j < CPR; ++j) dst[j * kWave] = src[r * CPR + j];
-      off = (uint32_t)(s.att_start[r] % bv.Wb);
-#pragma unroll
-      for (int q = 0; q < 6; ++q) ic[q] = s.instr_col[6 * r + q];
-    } else {
-#pragma unroll
-      for (int j = 0; j < CPR; ++j) dst[j * kWave] = u4{0u, 0u, 0u, 0u};
+      for (int q = 0; q < 6; ++q) ic[q] = s.instr_col[6 * i + q];
     }
     const uint32_t e = se[pos];
     rec_pack(bv.R, pos, e & 0x7FFFFFFFu, off, ic, e >> 31);
+  }
+}
+
+// Rows row0 .. row0+count-1 of the caller's order (src: their [count][24]
+// coefficients) into the chunk-major tiles of T, one row per thread: the rows
+// of one block keep their order, so a wave's 16-byte stores of chunk j fall
+// in runs of consecutive lanes of a tile.
+template <typename VT>
+__global__ void k_blk_pack(BlkView bv, const u4* __restrict__ src, int64_t row0, int64_t count, u4* __restrict__ T) {
+  constexpr int CPR = Geo<VT>::CPR;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t pos = bv.ipos[row0 + i];
+    const int64_t tile = pos / kWave, lane = pos - tile * kWave;
+    u4 v[CPR];
+#pragma unroll
+    for (int j = 0; j < CPR; ++j) v[j] = src[i * CPR + j];
+    u4* dst = T + tile * CPR * kWave + lane;
+#pragma unroll
+    for (int j = 0; j < CPR; ++j) dst[j * kWave] = v[j];
+  }
+}
+
+// Zero coefficients on every padding position of T.
+template <typename VT>
+__global__ void k_blk_zero_pad(BlkView bv, u4* __restrict__ T) {
+  constexpr int CPR = Geo<VT>::CPR;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < bv.npad; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t pos = bv.pad[i];
+    const int64_t tile = pos / kWave, lane = pos - tile * kWave;
+    u4* dst = T + tile * CPR * kWave + lane;
+#pragma unroll
+    for (int j = 0; j < CPR; ++j) dst[j * kWave] = u4{0u, 0u, 0u, 0u};
   }
 }
 
@@ -87,13 +110,21 @@ __global__ void k_blk_permute(BlkView bv, const double* __restrict__ src) {
   }
 }
 
+// dst (rows in the caller's order) <- ub, the inverse of k_blk_permute.
+__global__ void k_blk_unpermute(BlkView bv, double* __restrict__ dst) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < bv.m; r += (int64_t)gridDim.x * blockDim.x)
+    dst[r] = bv.ub[bv.ipos[r]];
+}
+
 // The iteration's pass.  Workgroup b streams tiles of block wg_block[b]; its
 // waves take consecutive sub-ranges.  Per tile a wave waits for the tile's
 // record, chunks and u (loaded one tile ahead) and for its x gathers (issued
 // during the previous tile), issues the next tile's loads, forms A x, issues
 // the next tile's gathers once this tile's windows sit in LDS, stores the
 // previous tile's u and segment sums, and forms the A^T u' parts.
-template <typename VT, int PM>
+// SQ = 1: the column sums of squares instead (every row value taken as 1 and
+// each term a^2 in FP64), for the column norms of the preconditioner.
+template <typename VT, int PM, int SQ>
 __global__ void __launch_bounds__(kBlkThreads) __attribute__((amdgpu_waves_per_eu(2)))
 k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __restrict__ x3,
        const float* __restrict__ x3f, double* __restrict__ acc, Scalars* sc, Work wk, int init) {
@@ -294,7 +325,7 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
 #pragma unroll
       for (int q = 0; q < 6; ++q) ax += prod<PM>(a[17 + q], xil[ic[q]]);
       if (s.n_glob) ax += prod<PM>(a[23], xg);
-      const double un = uo_c + ax;
+      const double un = SQ ? 1.0 : uo_c + ax;
       u_dst = bv.ub + t * kWave + lane;
       u_out = un;
       sumsq += un * un;
@@ -302,13 +333,13 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
 #pragma unroll
       for (int axs = 0; axs < 3; ++axs)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) atomicAdd(win + axs * W3 + aoff + j, prod<PM>(a[5 + 4 * axs + j], un));
+        for (int j = 0; j < 4; ++j) atomicAdd(win + axs * W3 + aoff + j, tprod<PM, SQ>(a[5 + 4 * axs + j], un));
 #pragma unroll
-      for (int q = 0; q < 6; ++q) atomicAdd(tl + ic[q], prod<PM>(a[17 + q], un));
-      if (s.n_glob) gsum += prod<PM>(a[23], un);
+      for (int q = 0; q < 6; ++q) atomicAdd(tl + ic[q], tprod<PM, SQ>(a[17 + q], un));
+      if (s.n_glob) gsum += tprod<PM, SQ>(a[23], un);
       double p[5];
 #pragma unroll
-      for (int k = 0; k < 5; ++k) p[k] = prod<PM>(a[k], un);
+      for (int k = 0; k < 5; ++k) p[k] = tprod<PM, SQ>(a[k], un);
       if (carry_valid && lane == 0) {
 #pragma unroll
         for (int k = 0; k < 5; ++k) p[k] += carry[k];
@@ -359,16 +390,23 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
 }
 
 hipError_t launch_fblk(const SysView& s, const BlkView& bv, int pmode, const double* vg, const double* x3,
-                       const float* x3f, double* acc, Scalars* sc, Work w, hipStream_t st, int init) {
+                       const float* x3f, double* acc, Scalars* sc, Work w, hipStream_t st, int init, int square) {
   if (!bv.ready || bv.G < 1 || bv.G > kMaxPartials) return hipErrorInvalidValue;
   if (pmode == 1 && (s.value_type != GSR_F32 || x3f == nullptr)) return hipErrorInvalidValue;
   const dim3 g(bv.G), b(kBlkThreads);
-  if (s.value_type == GSR_F32 && pmode == 1)
-    hipLaunchKernelGGL((k_fblk<float, 1>), g, b, bv.lds, st, s, bv, vg, x3, x3f, acc, sc, w, init);
-  else if (s.value_type == GSR_F32)
-    hipLaunchKernelGGL((k_fblk<float, 0>), g, b, bv.lds, st, s, bv, vg, x3, x3f, acc, sc, w, init);
-  else
-    hipLaunchKernelGGL((k_fblk<double, 0>), g, b, bv.lds, st, s, bv, vg, x3, x3f, acc, sc, w, init);
+  if (square) {
+    if (pmode != 0) return hipErrorInvalidValue;
+    if (s.value_type == GSR_F32)
+      hipLaunchKernelGGL((k_fblk<float, 0, 1>), g, b, bv.lds, st, s, bv, vg, x3, x3f, acc, sc, w, init);
+    else
+      hipLaunchKernelGGL((k_fblk<double, 0, 1>), g, b, bv.lds, st, s, bv, vg, x3, x3f, acc, sc, w, init);
+  } else if (s.value_type == GSR_F32 && pmode == 1) {
+    hipLaunchKernelGGL((k_fblk<float, 1, 0>), g, b, bv.lds, st, s, bv, vg, x3, x3f, acc, sc, w, init);
+  } else if (s.value_type == GSR_F32) {
+    hipLaunchKernelGGL((k_fblk<float, 0, 0>), g, b, bv.lds, st, s, bv, vg, x3, x3f, acc, sc, w, init);
+  } else {
+    hipLaunchKernelGGL((k_fblk<double, 0, 0>), g, b, bv.lds, st, s, bv, vg, x3, x3f, acc, sc, w, init);
+  }
   return hipGetLastError();
 }
 
@@ -421,6 +459,14 @@ hipError_t launch_seg_reduce(const SysView& s, const BlkView& bv, double* gA, Sc
   return hipGetLastError();
 }
 
+hipError_t launch_blk_unpermute(const BlkView& bv, double* dst, hipStream_t st) {
+  if (bv.ipos == nullptr) return hipErrorInvalidValue;
+  if (bv.m == 0) return hipSuccess;
+  const int blocks = (int)std::min<int64_t>(8192, (bv.m + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_blk_unpermute, dim3(blocks), dim3(kBlock), 0, st, bv, dst);
+  return hipGetLastError();
+}
+
 hipError_t launch_blk_permute(const BlkView& bv, const double* src, hipStream_t st) {
   if (bv.ipos == nullptr) return hipErrorInvalidValue;
   const int blocks = (int)std::min<int64_t>(8192, (bv.m + bv.npad + kBlock - 1) / kBlock);
@@ -429,8 +475,8 @@ hipError_t launch_blk_permute(const BlkView& bv, const double* src, hipStream_t 
 }
 
 void blk_free(BlkView* bv) {
-  for (void* p : {(void*)bv->T, (void*)bv->R, (void*)bv->perm, (void*)bv->ipos, (void*)bv->pad,
-                  (void*)bv->wg_block, (void*)bv->wave_tile,
+  if (bv->t_owned && bv->T) (void)hipFree(bv->T);
+  for (void* p : {(void*)bv->R, (void*)bv->ipos, (void*)bv->pad, (void*)bv->wg_block, (void*)bv->wave_tile,
                   (void*)bv->seg_base, (void*)bv->bsub, (void*)bv->grp_base, (void*)bv->grp_cnt,
                   (void*)bv->grp_list, (void*)bv->P, (void*)bv->Q, (void*)bv->ub, (void*)bv->dummy})
     if (p) (void)hipFree(p);
@@ -439,10 +485,12 @@ void blk_free(BlkView* bv) {
 
 // ------------------------------------------------------------------ build
 // The regrouping (positions, workgroup and wave ranges, segments) is laid out
-// on the host from att_start and star_row_ptr; the copy itself is made on the
-// device.
-int blk_build(const SysView& s, BlkView* bv, int cus, int max_window, int lds_max, char* err, size_t errlen,
-              hipStream_t st) {
+// on the host from att_start and star_row_ptr; the records are made on the
+// device.  The coefficients are placed separately: blk_copy_values from the
+// caller's rows in star order, or launch_blk_pack chunk by chunk into a
+// buffer the caller owns.
+int blk_plan(const SysView& s, BlkView* bv, int cus, int max_window, int lds_max, char* err, size_t errlen,
+             hipStream_t st) {
   *bv = BlkView{};
   auto failed = [&](int code, const char* what) {
     snprintf(err, errlen, "%s", what);
@@ -463,6 +511,7 @@ int blk_build(const SysView& s, BlkView* bv, int cus, int max_window, int lds_ma
   bv->Wb = Wb;
   bv->nb = nb;
   bv->lds = sizeof(double) * (size_t)(3 * (Wb + 3) + 2 * s.n_instr + s.n_glob);
+  bv->value_type = s.value_type;
 
   std::vector<int32_t> att((size_t)m);
   std::vector<int64_t> rp((size_t)S + 1);
@@ -476,9 +525,11 @@ int blk_build(const SysView& s, BlkView* bv, int cus, int max_window, int lds_ma
   if (mp >= ((int64_t)1 << 31)) return failed(GSR_EINVAL, "too many rows for the regrouped pass");
   bv->ntiles = ntiles;
   bv->mp = mp;
+  bv->m = m;
 
   // positions: block-major, star order inside a block; padding repeats the block's last star
-  std::vector<int32_t> perm((size_t)mp, -1);
+  std::vector<int32_t> ipos((size_t)m);
+  std::vector<int32_t> pads;
   std::vector<uint32_t> se((size_t)mp, 0);
   {
     std::vector<int64_t> fill((size_t)nb);
@@ -486,12 +537,16 @@ int blk_build(const SysView& s, BlkView* bv, int cus, int max_window, int lds_ma
     for (int64_t st_ = 0; st_ < S; ++st_)
       for (int64_t r = rp[(size_t)st_]; r < rp[(size_t)st_ + 1]; ++r) {
         const int64_t pos = fill[(size_t)(att[(size_t)r] / Wb)]++;
-        perm[(size_t)pos] = (int32_t)r;
+        ipos[(size_t)r] = (int32_t)pos;
         se[(size_t)pos] = (uint32_t)st_;
       }
     for (int64_t g = 0; g < nb; ++g)
-      for (int64_t pos = fill[(size_t)g]; pos < tb[(size_t)g + 1] * kWave; ++pos) se[(size_t)pos] = se[(size_t)pos - 1];
+      for (int64_t pos = fill[(size_t)g]; pos < tb[(size_t)g + 1] * kWave; ++pos) {
+        se[(size_t)pos] = se[(size_t)pos - 1];
+        pads.push_back((int32_t)pos);
+      }
   }
+  bv->npad = (int64_t)pads.size();
 
   // workgroups per block in proportion to its tiles (at least one per non-empty block)
   const int64_t gt = std::max<int64_t>(1, 2 * (int64_t)cus);
@@ -556,11 +611,10 @@ int blk_build(const SysView& s, BlkView* bv, int cus, int max_window, int lds_ma
     }
   }
 
-  const int cpr = s.value_type == GSR_F32 ? Geo<float>::CPR : Geo<double>::CPR;
   uint32_t* se_d = nullptr;
   auto dalloc_ = [](void** p, size_t bytes) { return hipMalloc(p, std::max<size_t>(bytes, 16)) == hipSuccess; };
-  if (!dalloc_(&bv->T, (size_t)mp * cpr * 16) || !dalloc_((void**)&bv->R, (size_t)mp * 16) ||
-      !dalloc_((void**)&bv->perm, (size_t)mp * 4) || !dalloc_((void**)&bv->wg_block, (size_t)G * 4) ||
+  if (!dalloc_((void**)&bv->R, (size_t)mp * 16) || !dalloc_((void**)&bv->ipos, (size_t)m * 4) ||
+      !dalloc_((void**)&bv->pad, pads.size() * 4) || !dalloc_((void**)&bv->wg_block, (size_t)G * 4) ||
       !dalloc_((void**)&bv->wave_tile, (size_t)(W + 1) * 4) || !dalloc_((void**)&bv->seg_base, (size_t)W * 4) ||
       !dalloc_((void**)&bv->bsub, (size_t)(nb + 1) * 4) ||
       !dalloc_((void**)&bv->grp_base, (size_t)(ngroups + 1) * 8) ||
@@ -571,9 +625,11 @@ int blk_build(const SysView& s, BlkView* bv, int cus, int max_window, int lds_ma
       !dalloc_((void**)&se_d, (size_t)mp * 4)) {
     (void)hipGetLastError();
     if (se_d) (void)hipFree(se_d);
-    return failed(GSR_ENOMEM, "device memory for the regrouped copy");
+    return failed(GSR_ENOMEM, "device memory for the regrouped layout");
   }
-  bool ok = hipMemcpyAsync(bv->perm, perm.data(), (size_t)mp * 4, hipMemcpyHostToDevice, st) == hipSuccess &&
+  bool ok = hipMemcpyAsync(bv->ipos, ipos.data(), (size_t)m * 4, hipMemcpyHostToDevice, st) == hipSuccess &&
+            (pads.empty() ||
+             hipMemcpyAsync(bv->pad, pads.data(), pads.size() * 4, hipMemcpyHostToDevice, st) == hipSuccess) &&
             hipMemcpyAsync(se_d, se.data(), (size_t)mp * 4, hipMemcpyHostToDevice, st) == hipSuccess &&
             hipMemcpyAsync(bv->wg_block, wg_block.data(), (size_t)G * 4, hipMemcpyHostToDevice, st) == hipSuccess &&
             hipMemcpyAsync(bv->wave_tile, wave_tile.data(), (size_t)(W + 1) * 4, hipMemcpyHostToDevice, st) ==
@@ -586,49 +642,87 @@ int blk_build(const SysView& s, BlkView* bv, int cus, int max_window, int lds_ma
                 hipSuccess &&
             hipMemcpyAsync(bv->grp_list, grp_list.data(), grp_list.size() * 4, hipMemcpyHostToDevice, st) ==
                 hipSuccess &&
-            hipMemsetAsync(bv->P + 5 * nseg, 0, 40, st) == hipSuccess;
+            hipMemsetAsync(bv->P + 5 * nseg, 0, 40, st) == hipSuccess &&
+            hipMemsetAsync(bv->ub, 0, (size_t)mp * 8, st) == hipSuccess;
   if (ok) {
-    const int blocks = (int)std::min<int64_t>(8192, (mp + kBlock - 1) / kBlock);
-    if (s.value_type == GSR_F32)
-      hipLaunchKernelGGL(k_blk_rows<float>, dim3(blocks), dim3(kBlock), 0, st, s, *bv, se_d);
-    else
-      hipLaunchKernelGGL(k_blk_rows<double>, dim3(blocks), dim3(kBlock), 0, st, s, *bv, se_d);
+    const int blocks = (int)std::min<int64_t>(8192, (m + bv->npad + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_blk_records, dim3(blocks), dim3(kBlock), 0, st, s, *bv, se_d);
     ok = hipGetLastError() == hipSuccess && hipStreamSynchronize(st) == hipSuccess;
   }
   (void)hipFree(se_d);
-  if (!ok) return failed(GSR_EHIP, "building the regrouped copy failed");
-  // from here on the permutation is applied row by row: perm's buffer takes the
-  // position of each original row, and the padding positions get a list of their own
-  {
-    std::vector<int32_t> ipos((size_t)m);
-    std::vector<int32_t> pads;
-    for (int64_t pos = 0; pos < mp; ++pos) {
-      const int32_t r = perm[(size_t)pos];
-      if (r >= 0)
-        ipos[(size_t)r] = (int32_t)pos;
-      else
-        pads.push_back((int32_t)pos);
-    }
-    bv->m = m;
-    bv->npad = (int64_t)pads.size();
-    bv->ipos = bv->perm;
-    bv->perm = nullptr;
-    if (!dalloc_((void**)&bv->pad, pads.size() * 4)) {
-      (void)hipGetLastError();
-      return failed(GSR_ENOMEM, "device memory for the regrouped copy");
-    }
-    if (hipMemcpy(bv->ipos, ipos.data(), (size_t)m * 4, hipMemcpyHostToDevice) != hipSuccess ||
-        (!pads.empty() && hipMemcpy(bv->pad, pads.data(), pads.size() * 4, hipMemcpyHostToDevice) != hipSuccess) ||
-        hipMemset(bv->ub, 0, (size_t)mp * 8) != hipSuccess) {
-      (void)hipGetLastError();
-      return failed(GSR_EHIP, "building the regrouped copy failed");
-    }
-  }
+  if (!ok) return failed(GSR_EHIP, "building the regrouped layout failed");
   // allow the dynamic LDS size beyond 64 KB (where the runtime asks for it)
-  (void)hipFuncSetAttribute((const void*)k_fblk<double, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bv->lds);
-  (void)hipFuncSetAttribute((const void*)k_fblk<float, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bv->lds);
-  (void)hipFuncSetAttribute((const void*)k_fblk<float, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bv->lds);
+  (void)hipFuncSetAttribute((const void*)k_fblk<double, 0, 0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)bv->lds);
+  (void)hipFuncSetAttribute((const void*)k_fblk<double, 0, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)bv->lds);
+  (void)hipFuncSetAttribute((const void*)k_fblk<float, 0, 0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)bv->lds);
+  (void)hipFuncSetAttribute((const void*)k_fblk<float, 0, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)bv->lds);
+  (void)hipFuncSetAttribute((const void*)k_fblk<float, 1, 0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)bv->lds);
   (void)hipGetLastError();
+  return GSR_OK;
+}
+
+size_t blk_value_bytes(const BlkView& bv) {
+  return (size_t)bv.mp * (bv.value_type == GSR_F32 ? Geo<float>::CPR : Geo<double>::CPR) * 16;
+}
+
+size_t blk_index_bytes(const BlkView& bv) {
+  const int64_t W = (int64_t)bv.G * kBlkWaves;
+  return (size_t)bv.mp * 16 + (size_t)bv.m * 4 + (size_t)bv.npad * 4 + (size_t)bv.G * 4 + (size_t)(W + 1) * 4 +
+         (size_t)W * 4 + (size_t)(bv.nb + 1) * 4 + (size_t)(bv.ngroups + 1) * 8 + (size_t)bv.ngroups * 4 +
+         (size_t)std::max<int64_t>(bv.nlist, 1) * 4 + (size_t)(bv.nseg + 1) * 40 +
+         (size_t)bv.G * 3 * (bv.Wb + 3) * 8 + (size_t)bv.mp * 8 + (size_t)W * kBlkDummy * 8;
+}
+
+hipError_t launch_blk_pack(const BlkView& bv, const void* rows, int64_t row0, int64_t count, void* T,
+                           hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  if (row0 < 0 || row0 + count > bv.m || bv.ipos == nullptr) return hipErrorInvalidValue;
+  const int blocks = (int)std::min<int64_t>(8192, (count + kBlock - 1) / kBlock);
+  if (bv.value_type == GSR_F32)
+    hipLaunchKernelGGL(k_blk_pack<float>, dim3(blocks), dim3(kBlock), 0, st, bv, (const u4*)rows, row0, count,
+                       (u4*)T);
+  else
+    hipLaunchKernelGGL(k_blk_pack<double>, dim3(blocks), dim3(kBlock), 0, st, bv, (const u4*)rows, row0, count,
+                       (u4*)T);
+  return hipGetLastError();
+}
+
+hipError_t launch_blk_zero_pad(const BlkView& bv, void* T, hipStream_t st) {
+  if (bv.npad == 0) return hipSuccess;
+  const int blocks = (int)std::min<int64_t>(8192, (bv.npad + kBlock - 1) / kBlock);
+  if (bv.value_type == GSR_F32)
+    hipLaunchKernelGGL(k_blk_zero_pad<float>, dim3(blocks), dim3(kBlock), 0, st, bv, (u4*)T);
+  else
+    hipLaunchKernelGGL(k_blk_zero_pad<double>, dim3(blocks), dim3(kBlock), 0, st, bv, (u4*)T);
+  return hipGetLastError();
+}
+
+// The library-owned copy for a handle over rows in star order: the layout, then
+// every row placed from the caller's array.
+int blk_build(const SysView& s, BlkView* bv, int cus, int max_window, int lds_max, char* err, size_t errlen,
+              hipStream_t st) {
+  int rc = blk_plan(s, bv, cus, max_window, lds_max, err, errlen, st);
+  if (rc != GSR_OK) return rc;
+  if (hipMalloc(&bv->T, std::max<size_t>(blk_value_bytes(*bv), 16)) != hipSuccess) {
+    (void)hipGetLastError();
+    bv->T = nullptr;
+    snprintf(err, errlen, "device memory for the regrouped copy");
+    blk_free(bv);
+    return GSR_ENOMEM;
+  }
+  bv->t_owned = 1;
+  if (launch_blk_pack(*bv, s.vals, 0, s.m, bv->T, st) != hipSuccess ||
+      launch_blk_zero_pad(*bv, bv->T, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+    (void)hipGetLastError();
+    snprintf(err, errlen, "building the regrouped copy failed");
+    blk_free(bv);
+    return GSR_EHIP;
+  }
   bv->ready = 1;
   return GSR_OK;
 }

@@ -79,6 +79,8 @@ struct gsr_system {
   int blk_maxw = 0;      // cap on its window width (0: as large as LDS allows)
   int blk_failed = 0;    // the copy could not be built (memory or limits): not tried again
   int use_blk = 0;       // the current solve runs on it
+  int packed = 0;        // the rows exist only in the regrouped order, in the caller's buffer (gsr_create_packed)
+  Scalars* psc = nullptr;  // scalars of the standalone passes over the regrouped rows
   // refinement buffers
   double *xr = nullptr, *xn = nullptr, *nrm2 = nullptr;
   // covariances
@@ -226,6 +228,7 @@ static void con_free(gsr_system* s) {
 static void release(gsr_system* s) {
   (void)hipDeviceSynchronize();
   dfree(s->sc);
+  dfree(s->psc);
   if (s->sc_host) (void)hipHostFree(s->sc_host);
   dfree(s->wk.part_a);
   dfree(s->wk.part_b);
@@ -275,30 +278,53 @@ static void release(gsr_system* s) {
 
 static void resolve_scratch(int dev);
 
-extern "C" int gsr_create(gsr_system** out, const gsr_dims* d, const void* vals, const int64_t* star_row_ptr,
-                          const int32_t* att_start, const int32_t* instr_col, gsr_stream stream) {
-  if (!out) return fail(GSR_EINVAL, "out is null");
-  *out = nullptr;
+// The handle's scalars, reduction partials, tickets and tail accumulators.
+static int init_workspaces(gsr_system* s, hipStream_t st) {
+  const SysView& v = s->s;
+  CHK(dalloc(&s->sc, 1));
+  CHK(dalloc(&s->wk.part_a, kMaxPartials));
+  CHK(dalloc(&s->wk.part_b, kMaxPartials));
+  CHK(dalloc(&s->wk.part_c, kMaxPartials));
+  CHK(dalloc(&s->wk.tickets, kTickets));
+  CHK(dalloc(&s->acc, (size_t)v.tail_len));
+  if (hipHostMalloc((void**)&s->sc_host, sizeof(Scalars), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    s->sc_host = nullptr;
+    return fail(GSR_ENOMEM, "pinned host allocation failed");
+  }
+  if (hipMemsetAsync(s->wk.tickets, 0, kTickets * sizeof(unsigned), st) != hipSuccess ||
+      hipMemsetAsync(s->acc, 0, (size_t)v.tail_len * sizeof(double), st) != hipSuccess)
+    return fail(GSR_EHIP, "workspace clear failed");
+  return GSR_OK;
+}
+
+// Argument checks shared by gsr_create and gsr_layout_plan (vals may be absent).
+static int check_system_args(const gsr_dims* d, const void* vals, const int64_t* star_row_ptr,
+                             const int32_t* att_start, const int32_t* instr_col, int need_vals) {
   if (gsr_num_unknowns(d) < 0)
     return fail(GSR_EINVAL, "bad dims: need n_stars >= 0, m >= 0, n_att >= 4, n_instr >= 6, n_glob in {0,1}");
   if (d->value_type != GSR_F64 && d->value_type != GSR_F32) return fail(GSR_EINVAL, "bad value_type");
   if (d->n_att > INT32_MAX || d->n_instr > INT32_MAX) return fail(GSR_EINVAL, "n_att / n_instr too large");
   NEED_DEV(star_row_ptr, "star_row_ptr");
   if (d->m > 0) {
-    NEED_DEV(vals, "vals");
+    if (need_vals) {
+      NEED_DEV(vals, "vals");
+      if ((uintptr_t)vals % 16) return fail(GSR_EINVAL, "vals must be 16-byte aligned");
+    }
     NEED_DEV(att_start, "att_start");
     NEED_DEV(instr_col, "instr_col");
-    if ((uintptr_t)vals % 16) return fail(GSR_EINVAL, "vals must be 16-byte aligned");
     if ((uintptr_t)instr_col % 8) return fail(GSR_EINVAL, "instr_col must be 8-byte aligned");
     if ((uintptr_t)att_start % 4) return fail(GSR_EINVAL, "att_start must be 4-byte aligned");
   }
   if ((uintptr_t)star_row_ptr % 8) return fail(GSR_EINVAL, "star_row_ptr must be 8-byte aligned");
   if (d->n_stars == 0 && d->m > 0) return fail(GSR_EINVAL, "rows without stars");
   if (d->n_instr + 1 > kLdsTailMax) return fail(GSR_EINVAL, "n_instr above %d is not supported", kLdsTailMax - 1);
+  return GSR_OK;
+}
 
-  gsr_system* s = new gsr_system();
-  hipStream_t st = (hipStream_t)stream;
-  SysView& v = s->s;
+static SysView make_view(const gsr_dims* d, const void* vals, const int64_t* star_row_ptr, const int32_t* att_start,
+                         const int32_t* instr_col) {
+  SysView v{};
   v.n_stars = d->n_stars;
   v.m = d->m;
   v.n_att = d->n_att;
@@ -313,6 +339,43 @@ extern "C" int gsr_create(gsr_system** out, const gsr_dims* d, const void* vals,
   v.att_start = att_start;
   v.instr_col = instr_col;
   v.has_empty_stars = 0;
+  return v;
+}
+
+// Index validation on the device: the first bad row or star is reported.
+static int validate_indices(SysView& v, hipStream_t st) {
+  unsigned long long* bad = nullptr;
+  CHK(dalloc(&bad, 3));
+  unsigned long long hb[3] = {~0ull, ~0ull, 0ull};
+  hipError_t e = hipMemcpyAsync(bad, hb, sizeof hb, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = launch_validate(v, bad, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(hb, bad, sizeof hb, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  dfree(bad);
+  if (e != hipSuccess) return fail(GSR_EHIP, "validation failed: %s", hipGetErrorString(e));
+  if (hb[1] != ~0ull) return fail(GSR_EINVAL, "star_row_ptr invalid at star %llu", hb[1]);
+  if (v.n_stars > 0) {
+    int64_t ends[2];
+    if (hipMemcpy(ends, v.row_ptr, sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(ends + 1, v.row_ptr + v.n_stars, sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(GSR_EHIP, "reading star_row_ptr failed");
+    if (ends[0] != 0 || ends[1] != v.m) return fail(GSR_EINVAL, "star_row_ptr must run from 0 to m");
+  }
+  if (hb[0] != ~0ull) return fail(GSR_EINVAL, "att_start / instr_col out of range at row %llu", hb[0]);
+  v.has_empty_stars = hb[2] != 0;
+  return GSR_OK;
+}
+
+extern "C" int gsr_create(gsr_system** out, const gsr_dims* d, const void* vals, const int64_t* star_row_ptr,
+                          const int32_t* att_start, const int32_t* instr_col, gsr_stream stream) {
+  if (!out) return fail(GSR_EINVAL, "out is null");
+  *out = nullptr;
+  CHK(check_system_args(d, vals, star_row_ptr, att_start, instr_col, 1));
+
+  gsr_system* s = new gsr_system();
+  hipStream_t st = (hipStream_t)stream;
+  s->s = make_view(d, vals, star_row_ptr, att_start, instr_col);
+  SysView& v = s->s;
   (void)hipGetDevice(&s->device);
   s->cus = device_cus();
   resolve_scratch(s->device);  // set-up of gsr_aprod1_noalloc, once per device
@@ -322,38 +385,8 @@ extern "C" int gsr_create(gsr_system** out, const gsr_dims* d, const void* vals,
     release(s);
     return code;
   };
-  if ((rc = dalloc(&s->sc, 1)) || (rc = dalloc(&s->wk.part_a, kMaxPartials)) ||
-      (rc = dalloc(&s->wk.part_b, kMaxPartials)) || (rc = dalloc(&s->wk.part_c, kMaxPartials)) ||
-      (rc = dalloc(&s->wk.tickets, kTickets)) || (rc = dalloc(&s->acc, (size_t)v.tail_len)))
-    return bail(rc);
-  if (hipHostMalloc((void**)&s->sc_host, sizeof(Scalars), hipHostMallocDefault) != hipSuccess) {
-    (void)hipGetLastError();
-    return bail(fail(GSR_ENOMEM, "pinned host allocation failed"));
-  }
-  if (hipMemsetAsync(s->wk.tickets, 0, kTickets * sizeof(unsigned), st) != hipSuccess ||
-      hipMemsetAsync(s->acc, 0, (size_t)v.tail_len * sizeof(double), st) != hipSuccess)
-    return bail(fail(GSR_EHIP, "workspace clear failed"));
-
-  // index validation on the device
-  unsigned long long* bad = nullptr;
-  if ((rc = dalloc(&bad, 3))) return bail(rc);
-  unsigned long long hb[3] = {~0ull, ~0ull, 0ull};
-  hipError_t e = hipMemcpyAsync(bad, hb, sizeof hb, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = launch_validate(v, bad, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(hb, bad, sizeof hb, hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  dfree(bad);
-  if (e != hipSuccess) return bail(fail(GSR_EHIP, "validation failed: %s", hipGetErrorString(e)));
-  if (hb[1] != ~0ull) return bail(fail(GSR_EINVAL, "star_row_ptr invalid at star %llu", hb[1]));
-  if (d->n_stars > 0) {
-    int64_t ends[2];
-    if (hipMemcpy(ends, star_row_ptr, sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess ||
-        hipMemcpy(ends + 1, star_row_ptr + d->n_stars, sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess)
-      return bail(fail(GSR_EHIP, "reading star_row_ptr failed"));
-    if (ends[0] != 0 || ends[1] != d->m) return bail(fail(GSR_EINVAL, "star_row_ptr must run from 0 to m"));
-  }
-  if (hb[0] != ~0ull) return bail(fail(GSR_EINVAL, "att_start / instr_col out of range at row %llu", hb[0]));
-  v.has_empty_stars = hb[2] != 0;
+  if ((rc = init_workspaces(s, st))) return bail(rc);
+  if ((rc = validate_indices(v, st))) return bail(rc);
   reshape(s);
   if (v.m > 0 && v.n_instr <= 65536) {
     // packed row indices for the fused iteration pass; without memory for them
@@ -366,6 +399,155 @@ extern "C" int gsr_create(gsr_system** out, const gsr_dims* d, const void* vals,
       s->rix = nullptr;
     }
   }
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_live.insert(s);
+  }
+  *out = s;
+  return GSR_OK;
+}
+
+// ------------------------------------------------------ rows placed by the caller
+// A layout plan: the regrouped row order (records, positions, segments and the
+// pass's workspaces) computed from the index data, without coefficients.  The
+// caller places its rows with gsr_layout_pack into a buffer of its own, which
+// gsr_create_packed then borrows: the library never holds a copy of A.
+struct gsr_layout {
+  gsr_dims d{};
+  SysView v{};  // sizes; the caller's index arrays only during planning
+  BlkView bv{};
+  int device = 0;
+};
+static std::set<gsr_layout*> g_layouts;
+
+static int check_layout(gsr_layout* L) {
+  if (!L) return fail(GSR_EINVAL, "null layout");
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!g_layouts.count(L)) return fail(GSR_EINVAL, "unknown, destroyed or consumed layout");
+  return GSR_OK;
+}
+
+static void drop_layout(gsr_layout* L) {
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_layouts.erase(L);
+  }
+  delete L;
+}
+
+extern "C" int gsr_layout_plan(gsr_layout** out, const gsr_dims* d, const int64_t* star_row_ptr,
+                               const int32_t* att_start, const int32_t* instr_col, int32_t max_window,
+                               gsr_stream stream) {
+  if (!out) return fail(GSR_EINVAL, "out is null");
+  *out = nullptr;
+  CHK(check_system_args(d, nullptr, star_row_ptr, att_start, instr_col, 0));
+  if (d->m <= 0) return fail(GSR_EINVAL, "a layout needs rows (m > 0)");
+  if (max_window != 0 && max_window < 4) return fail(GSR_EINVAL, "max_window must be 0 or >= 4");
+  hipStream_t st = (hipStream_t)stream;
+  gsr_layout* L = new gsr_layout();
+  L->d = *d;
+  L->v = make_view(d, nullptr, star_row_ptr, att_start, instr_col);
+  (void)hipGetDevice(&L->device);
+  int rc = validate_indices(L->v, st);
+  if (rc != GSR_OK) {
+    delete L;
+    return rc;
+  }
+  char msg[256] = "";
+  rc = blk_plan(L->v, &L->bv, device_cus(), max_window, device_lds(), msg, sizeof msg, st);
+  if (rc != GSR_OK) {
+    delete L;
+    return fail(rc, "layout: %s", msg);
+  }
+  L->v.vals = nullptr;
+  L->v.row_ptr = nullptr;
+  L->v.att_start = nullptr;
+  L->v.instr_col = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_layouts.insert(L);
+  }
+  *out = L;
+  return GSR_OK;
+}
+
+static void layout_info(const BlkView& b, int active, int owned, gsr_blocked_layout* info) {
+  memset(info, 0, sizeof *info);
+  info->active = active;
+  info->workgroups = b.G;
+  info->window = b.Wb;
+  info->blocks = b.nb;
+  info->padded_rows = b.mp;
+  info->segments = b.nseg;
+  info->bytes = (int64_t)blk_index_bytes(b);
+  info->value_bytes = (int64_t)blk_value_bytes(b);
+  info->values_owned = owned;
+}
+
+extern "C" int gsr_layout_info(gsr_layout* L, gsr_blocked_layout* info) {
+  CHK(check_layout(L));
+  if (!info) return fail(GSR_EINVAL, "info is null");
+  layout_info(L->bv, 0, 0, info);
+  return GSR_OK;
+}
+
+extern "C" int gsr_layout_pack(gsr_layout* L, const void* rows, int64_t row0, int64_t count, void* packed,
+                               gsr_stream stream) {
+  CHK(check_layout(L));
+  if (row0 < 0 || count < 0 || row0 + count > L->d.m)
+    return fail(GSR_EINVAL, "rows %lld .. %lld outside [0, m = %lld)", (long long)row0, (long long)(row0 + count),
+                (long long)L->d.m);
+  if (count == 0) return GSR_OK;
+  NEED_DEV(rows, "rows");
+  NEED_DEV(packed, "packed");
+  if ((uintptr_t)rows % 16 || (uintptr_t)packed % 16) return fail(GSR_EINVAL, "rows and packed must be 16-byte aligned");
+  HIPCHK(launch_blk_pack(L->bv, rows, row0, count, packed, (hipStream_t)stream));
+  return GSR_OK;
+}
+
+extern "C" int gsr_layout_destroy(gsr_layout* L) {
+  if (!L) return GSR_OK;
+  CHK(check_layout(L));
+  (void)hipDeviceSynchronize();
+  blk_free(&L->bv);
+  drop_layout(L);
+  return GSR_OK;
+}
+
+extern "C" int gsr_create_packed(gsr_system** out, gsr_layout* L, void* packed, gsr_stream stream) {
+  if (!out) return fail(GSR_EINVAL, "out is null");
+  *out = nullptr;
+  CHK(check_layout(L));
+  NEED_DEV(packed, "packed");
+  if ((uintptr_t)packed % 16) return fail(GSR_EINVAL, "packed must be 16-byte aligned");
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev != L->device) return fail(GSR_EINVAL, "the layout's device must be current");
+  hipStream_t st = (hipStream_t)stream;
+  gsr_system* s = new gsr_system();
+  s->s = L->v;
+  s->device = dev;
+  s->cus = device_cus();
+  s->packed = 1;
+  resolve_scratch(s->device);
+  int rc = init_workspaces(s, st);
+  if (rc == GSR_OK) rc = dalloc(&s->psc, 1);
+  if (rc == GSR_OK && (launch_blk_zero_pad(L->bv, packed, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)) {
+    (void)hipGetLastError();
+    rc = fail(GSR_EHIP, "clearing the padding rows failed");
+  }
+  if (rc != GSR_OK) {
+    release(s);  // the layout stays with the caller
+    return rc;
+  }
+  reshape(s);
+  // the handle takes the layout over; the coefficients stay in the caller's buffer
+  s->blk = L->bv;
+  s->blk.T = packed;
+  s->blk.t_owned = 0;
+  s->blk.ready = 1;
+  L->bv = BlkView{};
+  drop_layout(L);
   {
     std::lock_guard<std::mutex> lk(g_mu);
     g_live.insert(s);
@@ -404,6 +586,7 @@ extern "C" int gsr_set_graphs(gsr_system* s, int32_t on) {
 extern "C" int gsr_set_fused(gsr_system* s, int32_t on) {
   CHK(check_handle(s));
   if (s->in_session) return fail(GSR_ESTATE, "gsr_set_fused: a solve is in progress");
+  if (s->packed && !on) return fail(GSR_EINVAL, "gsr_set_fused: a handle over packed rows runs the one-pass iteration");
   s->fused = on != 0;
   return GSR_OK;
 }
@@ -414,6 +597,11 @@ extern "C" int gsr_set_blocked(gsr_system* s, int32_t on, int32_t max_window) {
   CHK(check_handle(s));
   if (s->in_session) return fail(GSR_ESTATE, "gsr_set_blocked: a solve is in progress");
   if (max_window != 0 && max_window < 4) return fail(GSR_EINVAL, "max_window must be 0 or >= 4");
+  if (s->packed) {
+    if (!on || max_window != 0)
+      return fail(GSR_EINVAL, "gsr_set_blocked: a packed handle keeps its layout (set max_window in gsr_layout_plan)");
+    return GSR_OK;
+  }
   if (max_window != s->blk_maxw) {
     (void)hipDeviceSynchronize();
     blk_free(&s->blk);  // rebuilt with the new width when next used
@@ -429,17 +617,8 @@ extern "C" int gsr_blocked_info(gsr_system* s, gsr_blocked_layout* info) {
   CHK(check_handle(s));
   if (!info) return fail(GSR_EINVAL, "info is null");
   memset(info, 0, sizeof *info);
-  const BlkView& b = s->blk;
-  if (!b.ready) return GSR_OK;
-  const int64_t cpr = s->s.value_type == GSR_F32 ? 6 : 12;
-  info->active = 1;
-  info->workgroups = b.G;
-  info->window = b.Wb;
-  info->blocks = b.nb;
-  info->padded_rows = b.mp;
-  info->segments = b.nseg;
-  info->bytes = b.mp * (16 * cpr + 16 + 4 + 8) + (b.nseg + 1) * 40 + b.nlist * 4 + b.ngroups * 12 +
-                (int64_t)b.G * (3 * (b.Wb + 3) * 8 + 4 + 8 * kBlkWaves + 8 * kBlkWaves * kBlkDummy);
+  if (!s->blk.ready) return GSR_OK;
+  layout_info(s->blk, 1, s->blk.t_owned, info);
   return GSR_OK;
 }
 
@@ -518,6 +697,90 @@ static int ensure_x3a(gsr_system* s) {
   return GSR_OK;
 }
 
+// The regrouped rows for a standalone pass: the caller's packed buffer, or the
+// library's copy (built at first use) on a handle over rows in star order.
+static int ensure_blk(gsr_system* s, hipStream_t st) {
+  if (!s->blk.ready) {
+    if (s->blk_failed) return fail(GSR_ENOMEM, "the regrouped copy could not be built");
+    char msg[256] = "";
+    HIPCHK(hipStreamSynchronize(st));
+    const int rc = blk_build(s->s, &s->blk, s->cus, s->blk_maxw, device_lds(), msg, sizeof msg, st);
+    if (rc != GSR_OK) {
+      if (rc != GSR_EHIP) s->blk_failed = 1;
+      return fail(rc, "regrouped copy: %s", msg);
+    }
+  }
+  if (!s->psc) CHK(dalloc(&s->psc, 1));
+  return GSR_OK;
+}
+
+// Work vectors of the standalone passes over the regrouped rows.
+static int ensure_blk_vectors(gsr_system* s, int32_t product, hipStream_t st) {
+  const size_t n3 = (size_t)std::max<int64_t>(3 * s->s.n_att, 1);
+  if (!s->x3) CHK(dalloc(&s->x3, n3));
+  if (product == GSR_PROD_F32 && !s->x3f) CHK(dalloc(&s->x3f, n3));
+  if (!s->gA) CHK(dalloc(&s->gA, (size_t)std::max<int64_t>(s->s.n_astro, 1)));
+  if (!s->zvec) {
+    CHK(dalloc(&s->zvec, (size_t)s->s.n));
+    HIPCHK(launch_fill(s->zvec, s->s.n, 0.0, st));
+  }
+  return GSR_OK;
+}
+
+// Standalone products as one pass over the regrouped rows (the LSQR
+// iteration's pass with its own scalars, whose epilogues only record norms):
+//   u' = su * u_in + A v (rows in the caller's order; u_in null: u' = A v), written
+//   to u_out unless it is null; with want_t also x <- sx * x + A^T u' (every column).
+// square = 1: x <- column sums of squares instead (v, u_in ignored).
+static int no_session(gsr_system* s) {
+  if (s->in_session) return fail(GSR_ESTATE, "a solve is in progress (its u occupies the regrouped rows' vector)");
+  return GSR_OK;
+}
+
+static int blk_products(gsr_system* s, const double* v, const double* u_in, double* u_out, double su, double* x,
+                        double sx, int32_t product, int want_t, int square, int kind, hipStream_t st) {
+  CHK(ensure_blk(s, st));
+  CHK(ensure_blk_vectors(s, product, st));
+  if (s->s.m == 0) return GSR_OK;
+  TimeScope ts(s, kind, st);
+  const BlkView& bv = s->blk;
+  if (!v || square) v = s->zvec;
+  if (u_in && !square)
+    HIPCHK(launch_blk_permute(bv, u_in, st));
+  else
+    su = 0.0;
+  HIPCHK(launch_att_interleave(s->s, v, s->x3, st, product == GSR_PROD_F32 ? s->x3f : nullptr));
+  HIPCHK(launch_raw_scalars(s->psc, su, sx, st));
+  HIPCHK(launch_fblk(s->s, bv, square ? GSR_PROD_F64 : product, v, s->x3, s->x3f, s->acc, s->psc, s->wk, st, 0,
+                     square));
+  if (want_t || square) {
+    HIPCHK(launch_seg_reduce(s->s, bv, s->gA, s->psc, st));
+    HIPCHK(launch_tail_blk(s->s, bv, x, s->acc, nullptr, s->gA, s->psc, s->wk, st, 1));
+  } else {
+    // the pass added its instrumental and global sums into the tail accumulators
+    HIPCHK(launch_fill(s->acc + 3 * s->s.n_att, s->s.n_instr + s->s.n_glob, 0.0, st));
+  }
+  if (u_out) HIPCHK(launch_blk_unpermute(bv, u_out, st));
+  return GSR_OK;
+}
+
+extern "C" int gsr_aprod12(gsr_system* s, const double* v, double* u, double scale_u, double* x, double scale_x,
+                           int32_t product, gsr_stream stream) {
+  CHK(check_handle(s));
+  CHK(check_product(s, product));
+  NEED_DEV(v, "v");
+  NEED_DEV(x, "x");
+  if (s->s.m > 0) NEED_DEV(u, "u");
+  if (s->con.ncon > 0) return fail(GSR_EINVAL, "gsr_aprod12 computes with A alone: detach the constraints first");
+  CHK(no_session(s));
+  if (s->s.m == 0) {
+    // no rows: A^T u' = 0
+    HIPCHK(launch_scaled_copy(x, x, s->s.n, scale_x, (hipStream_t)stream));
+    return GSR_OK;
+  }
+  return blk_products(s, v, u, u, scale_u, x, scale_x, product, 1, 0, 0, (hipStream_t)stream);
+}
+
 extern "C" int gsr_aprod1(gsr_system* s, const double* x, double* y, double scale_y, int32_t product,
                           gsr_stream stream) {
   CHK(check_handle(s));
@@ -525,6 +788,10 @@ extern "C" int gsr_aprod1(gsr_system* s, const double* x, double* y, double scal
   NEED_DEV(x, "x");
   if (s->s.m > 0) NEED_DEV(y, "y");
   if (s->s.m == 0) return GSR_OK;
+  if (s->packed) {
+    CHK(no_session(s));
+    return blk_products(s, x, y, y, scale_y, nullptr, 0.0, product, 0, 0, 0, (hipStream_t)stream);
+  }
   TimeScope ts(s, 0, (hipStream_t)stream);
   CHK(ensure_x3a(s));
   HIPCHK(launch_aprod1(s->s, s->sh, x, s->x3a, y, scale_y, 1.0, product, nullptr, s->wk, 0, (hipStream_t)stream));
@@ -566,6 +833,7 @@ extern "C" int gsr_aprod1_noalloc(gsr_system* s, const double* x, double* y, dou
   CHK(check_product(s, product));
   NEED_DEV(x, "x");
   if (s->s.m > 0) NEED_DEV(y, "y");
+  if (s->packed) return fail(GSR_EINVAL, "gsr_aprod1_noalloc runs on handles made by gsr_create");
   if (3 * s->s.n_att > kScratchDoubles)
     return fail(GSR_EINVAL, "3 * n_att = %lld exceeds the no-allocation scratch of %lld doubles",
                 (long long)(3 * s->s.n_att), (long long)kScratchDoubles);
@@ -616,14 +884,22 @@ extern "C" int gsr_aprod2(gsr_system* s, const double* y, double* x, double scal
   CHK(check_product(s, product));
   NEED_DEV(x, "x");
   if (s->s.m > 0) NEED_DEV(y, "y");
+  if (s->packed) {
+    CHK(no_session(s));
+    return blk_products(s, nullptr, y, nullptr, 1.0, x, scale_x, product, 1, 0, 1, (hipStream_t)stream);
+  }
   return aprod2_raw(s, y, x, scale_x, product, 0, (hipStream_t)stream);
 }
 
 static int ensure_scale(gsr_system* s, hipStream_t st) {
   if (s->S_valid) return GSR_OK;
   if (!s->S) CHK(dalloc(&s->S, (size_t)s->s.n));
-  // column sums of squares with the aprod 2 machinery, then 1/sqrt
-  CHK(aprod2_raw(s, nullptr, s->S, 0.0, 0, 1, st));
+  // column sums of squares with the aprod 2 machinery (on packed rows the
+  // regrouped pass in its square mode), then 1/sqrt
+  if (s->packed && s->s.m > 0)
+    CHK(blk_products(s, nullptr, nullptr, nullptr, 0.0, s->S, 0.0, GSR_PROD_F64, 1, 1, 1, st));
+  else
+    CHK(aprod2_raw(s, nullptr, s->S, 0.0, 0, 1, st));
   HIPCHK(launch_con_sq(s->con, s->S, st));  // columns of [A; C]
   HIPCHK(launch_scale_from_sq(s->s.n, s->S, st));
   s->S_valid = 1;
@@ -650,9 +926,14 @@ static int check_opts(const gsr_lsqr_opts* o) {
   return GSR_OK;
 }
 
+// The constraint rows of the LSQR u vector (after its m rows, or alone when the
+// rows are packed and u lives in the regrouped order).
+static double* u_con(gsr_system* s) { return s->u + (s->packed ? 0 : s->s.m); }
+
 static int ensure_vectors(gsr_system* s) {
   const size_t m = (size_t)s->s.m, n = (size_t)s->s.n;
-  if (!s->u) CHK(dalloc(&s->u, m + (size_t)s->con.ncon));
+  // packed rows: u lives in the regrouped order only; this holds the constraint rows
+  if (!s->u) CHK(dalloc(&s->u, (s->packed ? 0 : m) + (size_t)s->con.ncon));
   if (!s->v) CHK(dalloc(&s->v, n));
   if (!s->vg) CHK(dalloc(&s->vg, n));
   if (!s->w) CHK(dalloc(&s->w, n));
@@ -675,6 +956,7 @@ static int iteration_fused(const gsr_system* s) { return fused_for(s, s->pmode);
 
 // Whether a solve runs on the copy regrouped by attitude window.
 static int blk_applies(const gsr_system* s) {
+  if (s->packed) return 1;
   return s->blocked && s->fused && !s->blk_failed && s->s.m > 0 && s->s.tail_len > kLdsTailMax &&
          s->s.n_instr + 1 <= kLdsTailMax;
 }
@@ -747,10 +1029,10 @@ static int lsqr_begin(gsr_system* s, const double* b, const double* x0, const gs
       HIPCHK(launch_fill(s->Cacc, s->nsel * s->nsel, 0.0, st));
     s->cov_precond = o->precond;
   }
-  // r0 = [b; c] - [A; C] x0
-  const int r0_in_pass = s->use_blk && fold_r0 && x0;
-  double* uc = s->u + s->s.m;  // constraint rows of u
-  if (!r0_in_pass) {
+  // r0 = [b; c] - [A; C] x0 (on packed rows always inside the first pass)
+  const int r0_in_pass = s->use_blk && (fold_r0 || s->packed) && x0;
+  double* uc = u_con(s);  // constraint rows of u
+  if (!r0_in_pass && !(s->use_blk && !x0)) {
     HIPCHK(launch_copy(b, s->u, s->s.m, st));
     if (x0 && s->s.m > 0)
       HIPCHK(launch_aprod1(s->s, s->sh, x0, s->x3a, s->u, 1.0, -1.0, 0, nullptr, s->wk, 0, st));
@@ -773,7 +1055,7 @@ static int lsqr_begin(gsr_system* s, const double* b, const double* x0, const gs
       vg0 = s->y;
       pm0 = GSR_PROD_F64;
     } else {
-      HIPCHK(launch_blk_permute(s->blk, s->u, st));
+      HIPCHK(launch_blk_permute(s->blk, x0 ? s->u : b, st));
     }
     HIPCHK(launch_att_interleave(s->s, vg0, s->x3, st, pm0 == GSR_PROD_F32 ? s->x3f : nullptr));
     // constraint rows of u stay after the m rows of s->u (uc)
@@ -852,7 +1134,7 @@ static int enqueue_iteration(gsr_system* s, hipStream_t st) {
     if (s->eissued[h]) HIPCHK(hipStreamWaitEvent(st, s->eev[h], 0));
   }
   if (s->use_blk) {
-    double* uc = s->u + s->s.m;  // constraint rows of u
+    double* uc = u_con(s);  // constraint rows of u
     if (s->con.ncon > 0) {
       TimeScope ts(s, 2, st);
       HIPCHK(launch_con_aprod1(s->con, vg, uc, 0.0, 1.0, s->sc, s->wk, st));
@@ -875,7 +1157,7 @@ static int enqueue_iteration(gsr_system* s, hipStream_t st) {
     }
   } else if (iteration_fused(s)) {
     const int mode = att_mode(s);
-    double* uc = s->u + s->s.m;
+    double* uc = u_con(s);
     if (s->con.ncon > 0) {
       TimeScope ts(s, 2, st);
       HIPCHK(launch_con_aprod1(s->con, vg, uc, 0.0, 1.0, s->sc, s->wk, st));
@@ -1496,6 +1778,7 @@ extern "C" int gsr_syrk(const double* D, int64_t k, int64_t cols, int64_t ldd, d
 
 extern "C" int gsr_features(gsr_system* s, const double* b, const double* x_other, double* F, gsr_stream stream) {
   CHK(check_handle(s));
+  if (s->packed) return fail(GSR_EINVAL, "gsr_features reads the rows in star order: use a handle from gsr_create");
   if (s->s.m > 0) NEED_DEV(b, "b");
   NEED_DEV(x_other, "x_other");
   if (s->s.n_stars > 0) NEED_DEV(F, "F");

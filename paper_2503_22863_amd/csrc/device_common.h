@@ -188,6 +188,7 @@ __device__ __forceinline__ double sum_partials(const double* p, int n, double* r
 __device__ inline void epi_beta(Scalars* sc, double sumsq, int init) {
   const double beta = sqrt(sumsq);
   sc->beta = beta;
+  if (sc->raw) return;  // standalone product: u_scale, inv_beta and v_scale stay as set
   if (init) {
     sc->bnorm = beta;
     sc->rnorm = beta;
@@ -215,6 +216,10 @@ __device__ inline void epi_beta(Scalars* sc, double sumsq, int init) {
 
 // alpha_{i+1} and the two plane rotations of iteration i.
 __device__ inline void epi_alpha(Scalars* sc, double sumsq, int init) {
+  if (sc->raw) {  // standalone product: ||x'|| only
+    sc->alpha = sqrt(sumsq);
+    return;
+  }
   if (init) {
     const double alpha = sqrt(sumsq);
     sc->alpha = alpha;

@@ -40,6 +40,7 @@ struct Scalars {
   int32_t done;              // 1 once the solve has stopped (any reason)
   int32_t do_v;              // 1 if aprod2 runs this iteration (beta_{i+1} > 0)
   int32_t dcount;            // covariance columns buffered since the last SYRK flush
+  int32_t raw;               // 1: a standalone product pass; the epilogues only record beta / alpha
   int64_t dblock;            // columns per covariance block
   int64_t nsel;              // selected unknowns (0: no covariances)
 };
@@ -105,8 +106,9 @@ struct AttView {
   void* sv;             // [m][12] astrometric, instrumental, global coefficients in row order (value type)
 };
 
-// Rows regrouped by attitude window, a library-owned copy for the one-pass
-// iteration when the attitude block does not fit in LDS.  Rows are grouped
+// Rows regrouped by attitude window for the one-pass iteration when the
+// attitude block does not fit in LDS: a library-owned copy of the caller's
+// rows, or a buffer the caller filled in this order itself (gsr_layout_pack).  Rows are grouped
 // by block g = att_start / Wb and keep star order inside a block; each block
 // is padded with zero rows to whole 64-row tiles.  A tile's coefficients are
 // stored chunk-major (chunk j of its 64 rows is 1 KB), so a wave loads its
@@ -122,10 +124,11 @@ struct BlkView {
   int64_t nseg;         // star segments
   size_t lds;           // dynamic LDS bytes of the pass
   void* T;              // [ntiles][CPR][64] 16-byte chunks of the coefficients
+  int t_owned;          // 1: T is the library's copy (freed with the view); 0: the caller's buffer
+  int32_t value_type;   // GSR_F64 or GSR_F32
   uint32_t* R;          // [mp][4] row records: star | att_start - g*Wb (13 bits) << 32 | instr (11 bits each) | end bit
   int64_t m;            // rows of the system
-  int32_t* perm;        // [mp] original row of each position (-1: padding); only while the copy is built
-  int32_t* ipos;        // [m] position of each original row (perm's buffer, once built)
+  int32_t* ipos;        // [m] position of each original row
   int32_t* pad;         // [npad] padding positions
   int64_t npad;
   int32_t* wg_block;    // [G] block of each workgroup
@@ -229,13 +232,27 @@ hipError_t launch_seg_reduce(const SysView& s, const BlkView& bv, double* gA, Sc
 // GSR_EINVAL if the system does not qualify, GSR_ENOMEM without memory for it.
 int blk_build(const SysView& s, BlkView* bv, int cus, int max_window, int lds_max, char* err, size_t errlen,
               hipStream_t st);
+// The layout alone (records, positions, segments, workspaces; T left null):
+// what a caller needs to place its rows in the regrouped order itself.
+int blk_plan(const SysView& s, BlkView* bv, int cus, int max_window, int lds_max, char* err, size_t errlen,
+             hipStream_t st);
 void blk_free(BlkView* bv);
+size_t blk_value_bytes(const BlkView& bv);  // coefficient bytes of the layout (padding included)
+size_t blk_index_bytes(const BlkView& bv);  // device bytes of everything else the view holds
+// rows (the caller's [count][24] coefficients of rows row0 .. row0+count-1) into T
+hipError_t launch_blk_pack(const BlkView& bv, const void* rows, int64_t row0, int64_t count, void* T, hipStream_t st);
+// zero coefficients on T's padding positions
+hipError_t launch_blk_zero_pad(const BlkView& bv, void* T, hipStream_t st);
 // ub <- src (rows in the caller's order) permuted to the regrouped order, zero on padding
 hipError_t launch_blk_permute(const BlkView& bv, const double* src, hipStream_t st);
+// dst (rows in the caller's order) <- ub
+hipError_t launch_blk_unpermute(const BlkView& bv, double* dst, hipStream_t st);
 // The iteration's pass as launch_fused, on the regrouped copy (u in bv.ub).
 // x3f: the interleaved attitude x rounded to FP32, required with pmode 1.
+// square = 1: column sums of squares (pmode 0; u taken as 1, the sums as for A^T u).
 hipError_t launch_fblk(const SysView& s, const BlkView& bv, int pmode, const double* vg, const double* x3,
-                       const float* x3f, double* acc, Scalars* sc, Work w, hipStream_t st, int init = 0);
+                       const float* x3f, double* acc, Scalars* sc, Work w, hipStream_t st, int init = 0,
+                       int square = 0);
 // Covariance column of the iteration: D[p][dcount] = w[sel[p]] / rho_i for p < nsel (after the tail);
 // the last workgroup advances dcount.  Skipped once the solve has stopped or the block is full.
 hipError_t launch_cov_gather(int64_t nsel, const int64_t* sel, const double* w, double* D, Scalars* sc, Work wk,
@@ -266,6 +283,8 @@ hipError_t launch_pair_out(const double* Cp, int64_t P, const int32_t* pa, const
 hipError_t launch_cov_out(const double* C, int64_t k, const double* S, const int64_t* sel, double* out,
                           hipStream_t st);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
+// sc <- the scalars of a standalone product pass (raw = 1): u_scale, v_scale, inv_beta = 1, do_v = 1
+hipError_t launch_raw_scalars(Scalars* sc, double u_scale, double v_scale, hipStream_t st);
 hipError_t launch_step_norms(int64_t n, const double* xn, double* x, double* out2, Work w, hipStream_t st);
 hipError_t launch_scaled_copy(const double* src, double* dst, int64_t n, double s, hipStream_t st);
 

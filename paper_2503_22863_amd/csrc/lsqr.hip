@@ -16,6 +16,19 @@ __global__ void k_fill(double* __restrict__ p, int64_t n, double v) {
   for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) p[j] = v;
 }
 
+// The scalars of a standalone product pass: u' = u_scale u + A v, then
+// x = v_scale x + A^T u' (inv_beta = 1); the epilogues record ||u'|| and ||x|| only.
+__global__ void k_raw_scalars(Scalars* sc, double u_scale, double v_scale) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  Scalars h = {};
+  h.raw = 1;
+  h.u_scale = u_scale;
+  h.v_scale = v_scale;
+  h.inv_beta = 1.0;
+  h.do_v = 1;
+  *sc = h;
+}
+
 __global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
   for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) b[j] = a[j];
 }
@@ -349,6 +362,11 @@ __global__ void k_scaled_copy(const double* __restrict__ a, double* __restrict__
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill, dim3(blocks_for(n)), dim3(kBlock), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_raw_scalars(Scalars* sc, double u_scale, double v_scale, hipStream_t st) {
+  hipLaunchKernelGGL(k_raw_scalars, dim3(1), dim3(64), 0, st, sc, u_scale, v_scale);
   return hipGetLastError();
 }
 

@@ -48,6 +48,14 @@ __device__ __forceinline__ double prod(VT a, double x) {
   return (double)a * x;
 }
 
+// A term of A^T u: a * u as prod forms it, or a^2 in FP64 when summing the
+// squares of the columns (SQ = 1).
+template <int PM, int SQ, typename VT>
+__device__ __forceinline__ double tprod(VT a, double u) {
+  if (SQ) return (double)a * (double)a;
+  return prod<PM>(a, u);
+}
+
 // Star boundaries for a tile whose first row is in star scur: lane i holds
 // row_ptr[scur + 1 + i] (the end row of star scur + i), clamped at n_stars.
 __device__ __forceinline__ int64_t bnd_load(const SysView& s, int64_t scur, int lane) {
