@@ -29,7 +29,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-ffp-contract=off",
-                               "-fno-fast-math", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+                               "-fno-fast-math", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -79,10 +79,23 @@ def _L():
         lib.orc_covariances.argtypes = [vp, i64, i64, vp, vp]
         lib.orc_lsqr_refine.restype = C.c_int
         lib.orc_lsqr_refine.argtypes = [vp, vp, vp, vp, vp, i32, d, vp, vp, vp]
+        lib.orc_set_threads.restype = None
+        lib.orc_set_threads.argtypes = [C.c_int]
+        lib.orc_get_threads.restype = C.c_int
+        lib.orc_get_threads.argtypes = []
         lib.orc_features.restype = None
         lib.orc_features.argtypes = [vp, vp, vp, vp]
         _lib = lib
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's products (0: all processors).  Results do not depend on it."""
+    _L().orc_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(_L().orc_get_threads())
 
 
 def _p(a):

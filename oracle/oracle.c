@@ -22,12 +22,18 @@
  *     k = 23      N_A + 3*n_att + n_instr            (only when n_glob = 1)
  * with N_A = 5*n_stars.  Rows are sorted by star.
  *
+ * Threads (OpenMP) only split work whose result does not depend on the split:
+ * aprod 1 by stars (each row's sum is unchanged), and the column sums of
+ * aprod 2 / the column norms by fixed chunks of stars (see below): the
+ * results are the same for any thread count.
+ *
  * Constraint equations (Sec. 2: a set of them makes the solution unique): ncon
  * extra sparse rows after the m observation rows, row i holding the entries
  * con_col[e], con_val[e] for e in [con_ptr[i], con_ptr[i+1]).  The system is
  * then [A; C] x = [b; c], and every m-sized vector has m + ncon entries.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -104,11 +110,20 @@ static void comp_add(double *sum, double *c, double v)
     *sum = t;
 }
 
+/* Threads used by the products (0 or less: the OpenMP default). */
+void orc_set_threads(int n)
+{
+    omp_set_num_threads(n > 0 ? n : omp_get_num_procs());
+}
+
+int orc_get_threads(void) { return omp_get_max_threads(); }
+
 /* Eq. (2): y <- scale_y * y + A x.  Each row is summed in slot order.
  * scale_y == 0 overwrites y without reading it. */
 void orc_aprod1(const orc_sys *A, const double *x, double *y, double scale_y, int mode)
 {
     int ns = n_slots(A);
+#pragma omp parallel for schedule(dynamic, 4096)
     for (int64_t s = 0; s < A->n_stars; ++s) {
         for (int64_t r = A->star_row_ptr[s]; r < A->star_row_ptr[s + 1]; ++r) {
             double acc = 0.0;
@@ -125,28 +140,96 @@ void orc_aprod1(const orc_sys *A, const double *x, double *y, double scale_y, in
     }
 }
 
-/* Eq. (3): x <- scale_x * x + A^T y.  Every column is accumulated over the
- * rows in row order with a compensated sum.  scale_x == 0 overwrites x. */
+/*
+ * Column sums of A^T y (sq == 0) or of the squared coefficients (sq == 1) over
+ * the observation rows, each column a compensated sum in row order.  A star's
+ * five astrometric columns take only that star's rows, so stars are shared out
+ * between threads freely.  The other columns take rows of every star: the
+ * stars are cut into NCH fixed chunks of consecutive stars, each chunk sums its
+ * rows in row order into its own compensated pair (sum, cmp) per column, and
+ * the chunks' pairs are added in chunk order with compensation.  The chunks do
+ * not depend on the thread count.
+ */
+#define NCH 16
+
+static int column_sums(const orc_sys *A, const double *y, int mode, int sq, double *sum, double *cmp)
+{
+    int64_t NA = 5 * A->n_stars, nt = orc_n_unknowns(A) - NA;
+    int ns = n_slots(A);
+    int64_t nch = A->n_stars < NCH ? A->n_stars : NCH;
+    double *cs = NULL, *cc = NULL;
+    if (nch > 0) {
+        cs = calloc((size_t)(nch * nt), sizeof(double));
+        cc = calloc((size_t)(nch * nt), sizeof(double));
+        if (!cs || !cc) {
+            free(cs);
+            free(cc);
+            return -1;
+        }
+    }
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t ch = 0; ch < nch; ++ch) {
+        /* chunk ch: stars [s0, s1) holding about a (1/nch) share of the rows */
+        int64_t s0 = 0, s1 = 0, lo = 0, hi = A->n_stars;
+        int64_t r0 = A->m * ch / nch, r1 = A->m * (ch + 1) / nch;
+        while (lo < hi) { /* first star whose rows start at or after r0 */
+            int64_t mid = (lo + hi) / 2;
+            if (A->star_row_ptr[mid] < r0) lo = mid + 1; else hi = mid;
+        }
+        s0 = ch == 0 ? 0 : lo;
+        lo = 0;
+        hi = A->n_stars;
+        while (lo < hi) {
+            int64_t mid = (lo + hi) / 2;
+            if (A->star_row_ptr[mid] < r1) lo = mid + 1; else hi = mid;
+        }
+        s1 = ch == nch - 1 ? A->n_stars : lo;
+        double *ps = cs + ch * nt, *pc = cc + ch * nt;
+        for (int64_t s = s0; s < s1; ++s)
+            for (int64_t r = A->star_row_ptr[s]; r < A->star_row_ptr[s + 1]; ++r)
+                for (int k = 0; k < ns; ++k) {
+                    int64_t c = orc_col(A, s, r, k);
+                    double term;
+                    if (sq) {
+                        double a = coef(A, r, k);
+                        term = a * a;
+                    } else {
+                        term = product(A, r, k, y[r], mode);
+                    }
+                    if (c < NA)
+                        comp_add(&sum[c], &cmp[c], term);
+                    else
+                        comp_add(&ps[c - NA], &pc[c - NA], term);
+                }
+    }
+    for (int64_t ch = 0; ch < nch; ++ch)
+        for (int64_t j = 0; j < nt; ++j) {
+            comp_add(&sum[NA + j], &cmp[NA + j], cs[ch * nt + j]);
+            comp_add(&sum[NA + j], &cmp[NA + j], cc[ch * nt + j]);
+        }
+    free(cs);
+    free(cc);
+    /* constraint rows, after the observation rows */
+    for (int64_t i = 0; i < A->ncon; ++i)
+        for (int64_t e = A->con_ptr[i]; e < A->con_ptr[i + 1]; ++e) {
+            double a = A->con_val[e];
+            comp_add(&sum[A->con_col[e]], &cmp[A->con_col[e]], sq ? a * a : a * y[A->m + i]);
+        }
+    return 0;
+}
+
+/* Eq. (3): x <- scale_x * x + A^T y, every column a compensated sum (see
+ * column_sums).  scale_x == 0 overwrites x. */
 int orc_aprod2(const orc_sys *A, const double *y, double *x, double scale_x, int mode)
 {
     int64_t n = orc_n_unknowns(A);
-    int ns = n_slots(A);
     double *sum = calloc((size_t)n, sizeof(double));
     double *cmp = calloc((size_t)n, sizeof(double));
-    if (!sum || !cmp) {
+    if (!sum || !cmp || column_sums(A, y, mode, 0, sum, cmp)) {
         free(sum);
         free(cmp);
         return -1;
     }
-    for (int64_t s = 0; s < A->n_stars; ++s)
-        for (int64_t r = A->star_row_ptr[s]; r < A->star_row_ptr[s + 1]; ++r)
-            for (int k = 0; k < ns; ++k) {
-                int64_t c = orc_col(A, s, r, k);
-                comp_add(&sum[c], &cmp[c], product(A, r, k, y[r], mode));
-            }
-    for (int64_t i = 0; i < A->ncon; ++i)
-        for (int64_t e = A->con_ptr[i]; e < A->con_ptr[i + 1]; ++e)
-            comp_add(&sum[A->con_col[e]], &cmp[A->con_col[e]], A->con_val[e] * y[A->m + i]);
     for (int64_t c = 0; c < n; ++c)
         x[c] = (scale_x == 0.0 ? 0.0 : scale_x * x[c]) + (sum[c] + cmp[c]);
     free(sum);
@@ -154,28 +237,17 @@ int orc_aprod2(const orc_sys *A, const double *y, double *x, double scale_x, int
     return 0;
 }
 
-/* Euclidean norm of every column of [A; C] (compensated sum of squares). */
+/* Euclidean norm of every column of [A; C] (compensated sums of squares). */
 int orc_colnorms(const orc_sys *A, double *norms)
 {
     int64_t n = orc_n_unknowns(A);
-    int ns = n_slots(A);
     double *sum = calloc((size_t)n, sizeof(double));
     double *cmp = calloc((size_t)n, sizeof(double));
-    if (!sum || !cmp) {
+    if (!sum || !cmp || column_sums(A, NULL, ORC_P64, 1, sum, cmp)) {
         free(sum);
         free(cmp);
         return -1;
     }
-    for (int64_t s = 0; s < A->n_stars; ++s)
-        for (int64_t r = A->star_row_ptr[s]; r < A->star_row_ptr[s + 1]; ++r)
-            for (int k = 0; k < ns; ++k) {
-                double a = coef(A, r, k);
-                int64_t c = orc_col(A, s, r, k);
-                comp_add(&sum[c], &cmp[c], a * a);
-            }
-    for (int64_t i = 0; i < A->ncon; ++i)
-        for (int64_t e = A->con_ptr[i]; e < A->con_ptr[i + 1]; ++e)
-            comp_add(&sum[A->con_col[e]], &cmp[A->con_col[e]], A->con_val[e] * A->con_val[e]);
     for (int64_t c = 0; c < n; ++c)
         norms[c] = sqrt(sum[c] + cmp[c]);
     free(sum);

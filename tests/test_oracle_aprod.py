@@ -134,3 +134,29 @@ def test_fp32_products(small_sys, oracle_lib):
     np.testing.assert_allclose(oracle_lib.aprod2(o, y, mode=oracle_lib.P32), ref2, rtol=0, atol=1e-12)
     # FP64 products on FP32 storage are the exact upcast
     np.testing.assert_allclose(oracle_lib.aprod1(o, x), A32.astype(np.float64) @ x, rtol=1e-13, atol=1e-12)
+
+
+def test_threads_do_not_change_results(oracle_lib):
+    """The threaded oracle splits aprod 1 by stars and the column sums by fixed
+    chunks of stars, so its results are bit for bit the same for any thread count;
+    with more stars than chunks every column sum still lands within two units in
+    the last place of the exactly rounded sum (math.fsum of the exact products)."""
+    g = gsr_synth.make_system(500, (5, 30), 40, 12, 1, seed=12)
+    o = oracle_lib.OSystem(g)
+    rng = np.random.default_rng(13)
+    x = rng.standard_normal(g.dims.n)
+    y = rng.standard_normal(g.dims.m) * np.exp(rng.uniform(-8, 8, g.dims.m))
+    out = {}
+    try:
+        for t in (1, 3, 8):
+            oracle_lib.set_threads(t)
+            out[t] = (oracle_lib.aprod1(o, x), oracle_lib.aprod2(o, y), oracle_lib.colnorms(o))
+    finally:
+        oracle_lib.set_threads(0)
+    for t in (3, 8):
+        for a, b in zip(out[t], out[1]):
+            assert np.array_equal(a, b), t
+    A = dense_A(g)
+    exact = np.array([math.fsum(c) for c in (A * y[:, None]).T])
+    got = out[8][1]
+    assert np.all(np.abs(got - exact) <= 2 * np.spacing(np.abs(exact)) + 1e-300)
