@@ -1,15 +1,20 @@
 """Throughput of the AVU-GSR LSQR hot path on one MI355X.
 
-A step is one LSQR iteration (both products A v and A^T u -- one fused pass
-over the rows plus the bucketed attitude pass -- the tail pass, the x / w /
-variance update and the scalar recurrences) on the one-GPU share:
-1,000,000 stars with U[50,90] observations each (m ~ 7.0e7 rows,
+A step is one LSQR iteration (both products A v and A^T u in one pass over
+the rows regrouped by attitude window, the star-segment reduction, the tail
+pass with the scalar recurrences, the x / w / variance update) on the one-GPU
+share: 1,000,000 stars with U[50,90] observations each (m ~ 7.0e7 rows,
 ~1.7e9 nonzeros), 3 x 40,000 attitude, 200 instrumental and 1 global
 unknown, FP64 coefficients N(0,1), plain (unscaled) FP64 LSQR with damp 0.
+The caller places its rows in the regrouped order at load time, so the
+library holds no copy of A.
 
-Prints one JSON line: iterations/s, the roofline of the dominant kernel (the
-fused row pass; HIP-event timing inside the timed region), and the CPU oracle
-timed on a bounded sample of the same workload.
+Prints one JSON line: iterations/s (graph replay on, as shipped), the
+roofline of the dominant kernel (HIP events around every kernel over a
+separate run of iterations right after the timed region), the same for the
+3e6-star share with the covariances of 4,000 unknowns, the time to 1e-10 of
+the FP32 forms and of the warm start, and the CPU oracle timed on a bounded
+sample of the same workload.
 """
 from __future__ import annotations
 
@@ -128,60 +133,41 @@ def _usable_cores() -> int:
 
 def cpu_baseline(full_m: int, budget_s: float = 12.0):
     """The oracle, as it stands, on a bounded sample: a 20,000-star system of the same
-    construction (same attitude / instrumental sizes, same distributions).  One thread,
-    then all usable cores: one oracle LSQR per thread on the same sample, concurrently
-    (the oracle's C code runs outside the interpreter lock), the aggregate rows per
-    second scaled to the full share.  The second figure is the throughput of
-    independent row streams: it leaves out the reductions a row-split oracle would add,
-    so it is an upper bound for the oracle on these cores."""
-    import threading
-
+    construction (same attitude / instrumental sizes, same distributions), timed on
+    one thread and on every usable core (its products are threaded by stars and by
+    fixed chunks of stars), the per-iteration time scaled by rows to the full share."""
     import gsr_synth
     import oracle
 
     g = gsr_synth.share_1m(seed=2505, n_stars=20_000)
     o = oracle.OSystem(g)
     b = oracle.known_terms(o, g.x_true, g.noise)
-    t = time.perf_counter()
-    oracle.lsqr(o, b, atol=0, btol=0, itmax=1, precond=False)
-    t1 = time.perf_counter() - t
-    k = max(2, min(50, int(budget_s / max(t1, 1e-3))))
-    t = time.perf_counter()
-    r = oracle.lsqr(o, b, atol=0, btol=0, itmax=k, precond=False)
-    tk = time.perf_counter() - t
-    per_it = (tk - t1) / max(1, k - 1)  # remove the one-time setup
-    per_it_full = per_it * full_m / g.dims.m
-    # all cores: P concurrent single-thread solves of k iterations (each also pays one setup)
-    P = _usable_cores()
-    kp = max(2, min(k, int(budget_s / max(per_it, 1e-3))))
-    errs = []
 
-    def worker():
-        try:
-            oracle.lsqr(o, b, atol=0, btol=0, itmax=kp, precond=False, want_var=True)
-        except Exception as e:  # noqa: BLE001 -- reported below
-            errs.append(e)
+    def per_iteration(threads, budget):
+        oracle.set_threads(threads)
+        t = time.perf_counter()
+        oracle.lsqr(o, b, atol=0, btol=0, itmax=1, precond=False)
+        t1 = time.perf_counter() - t
+        k = max(2, min(200, int(budget / max(t1, 1e-3))))
+        t = time.perf_counter()
+        r = oracle.lsqr(o, b, atol=0, btol=0, itmax=k, precond=False)
+        tk = time.perf_counter() - t
+        return (tk - t1) / max(1, k - 1), r["itn"], tk  # the one-time setup removed
 
-    th = [threading.Thread(target=worker) for _ in range(P)]
-    t = time.perf_counter()
-    for x in th:
-        x.start()
-    for x in th:
-        x.join()
-    tp = time.perf_counter() - t
-    if errs:
-        raise errs[0]
-    setup = t1 - per_it  # one-time part of one solve
-    rate_all = P * kp / max(tp - setup, 1e-9) * g.dims.m / full_m
-    return {"value": 1.0 / per_it_full, "unit": "iterations/s", "cores": 1, "kind": "oracle",
-            "sample": f"{g.dims.n_stars} stars ({g.dims.m} rows) of the same construction, "
-                      f"{r['itn']} unscaled LSQR iterations in {tk:.1f} s on one thread, scaled by rows to "
-                      f"m={full_m}",
+    try:
+        per1, it1, t1 = per_iteration(1, budget_s)
+        P = _usable_cores()
+        perP, itP, tP = per_iteration(P, budget_s / 2)
+    finally:
+        oracle.set_threads(0)
+    scale = full_m / g.dims.m
+    return {"value": 1.0 / (per1 * scale), "unit": "iterations/s", "cores": 1, "kind": "oracle",
+            "sample": f"{g.dims.n_stars} stars ({g.dims.m} rows) of the same construction, {it1} unscaled LSQR "
+                      f"iterations in {t1:.1f} s on one thread, scaled by rows to m={full_m}",
             "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
-            "all_cores": {"value": rate_all, "unit": "iterations/s", "cores": P,
-                          "sample": f"{P} concurrent oracle solves of {kp} iterations on the same sample in "
-                                    f"{tp:.1f} s; aggregate rows per second scaled to m={full_m} (independent "
-                                    f"row streams, no reduction cost: an upper bound)"}}
+            "all_cores": {"value": 1.0 / (perP * scale), "unit": "iterations/s", "cores": P, "kind": "oracle",
+                          "sample": f"the same sample, {itP} iterations in {tP:.1f} s on {P} threads, scaled "
+                                    f"by rows to m={full_m}"}}
 
 
 def _rel(a, b):
@@ -240,7 +226,7 @@ def _pass_rates(S, b, product, m, ns, f32, iters=10):
             "row_pass_bytes": by, "row_pass_GBps": by / (f_ms * 1e-3) / 1e9}
 
 
-def time_to_tolerance_fp32(gsr, g, tol=1e-10, label="", inner_tol=1e-5):
+def time_to_tolerance_fp32(gsr, g, tol=1e-10, label="", inner_tol=1e-5, packed=False):
     """FP64 LSQR vs the FP32 forms on the same FP32-representable matrix: FP32 products
     with FP64 iterative refinement (inner atol = btol = inner_tol, outer_tol 1e-11), and
     FP32 storage with FP64 products.  Reference: the FP64 solve converged to
@@ -249,12 +235,22 @@ def time_to_tolerance_fp32(gsr, g, tol=1e-10, label="", inner_tol=1e-5):
     import numpy as np
     import torch
 
+    import copy
+
     g32 = g.as_f32()
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
-    rp, at, ic = t(g.star_row_ptr), t(g.att_start), t(g.instr_col)
-    v32 = t(g32.vals)
-    S64 = gsr.System(v32.double(), rp, at, ic, g.dims.n_att, g.dims.n_instr, g.dims.n_glob)
-    S32 = gsr.System(v32, rp, at, ic, g.dims.n_att, g.dims.n_instr, g.dims.n_glob)
+    if packed:
+        # rows placed by the caller in the regrouped order, as the headline runs them
+        g64 = copy.copy(g32)
+        g64.vals = g32.vals.astype(np.float64)
+        S64 = gsr.System.packed_from_generated(g64)
+        del g64
+        S32 = gsr.System.packed_from_generated(g32)
+    else:
+        rp, at, ic = t(g.star_row_ptr), t(g.att_start), t(g.instr_col)
+        v32 = t(g32.vals)
+        S64 = gsr.System(v32.double(), rp, at, ic, g.dims.n_att, g.dims.n_instr, g.dims.n_glob)
+        S32 = gsr.System(v32, rp, at, ic, g.dims.n_att, g.dims.n_instr, g.dims.n_glob)
     b = t(g.noise)
     S64.aprod1(t(g.x_true), b, scale=1.0)
     x_ref, _, rref = S64.lsqr_solve(b, atol=1e-14, btol=1e-14, itmax=5000, precond=True, want_var=False)
@@ -414,6 +410,11 @@ def main():
     ap.add_argument("--constraints", action="store_true",
                     help="add 6 constraint equations: the sums over all stars of astrometric unknowns 0-2 and "
                          "the sums over each attitude axis")
+    ap.add_argument("--library-copy", action="store_true",
+                    help="hand the rows over in star order and let the library make its regrouped copy (instead of "
+                         "placing them in the regrouped order first)")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 3e6-star leg with the covariances of 4,000 unknowns")
     ap.add_argument("--star-order", action="store_true",
                     help="iterate on the rows in star order (bucketed attitude pass) instead of the copy "
                          "regrouped by attitude window")
@@ -462,27 +463,107 @@ def main():
         c.copy_(a)  # reads and writes 2 GiB
         torch.cuda.synchronize()
         del a, c
-    t = time.time()
-    if args.workload == "share_3m":
-        g = gsr_synth.share_3m() if args.stars == 1_000_000 else gsr_synth.share_3m(n_stars=args.stars)
-    else:
-        g = gsr_synth.share_1m(n_stars=args.stars)
-    m, n, ns = g.dims.m, g.dims.n, g.dims.n_stars
-    print(f"# generated m={m} n={n} in {time.time() - t:.1f}s", file=sys.stderr, flush=True)
-    S = gsr.System.from_generated(g)
-    S.set_blocked(not args.star_order)
+    workload = args.workload
     if args.aprods:
-        print(json.dumps(aprods_bench(S, m, n, ns, args.workload)), flush=True)
+        g = _generate(gsr_synth, workload, args.stars)
+        S = gsr.System.from_generated(g)  # the standalone products on the caller's rows in star order
+        print(json.dumps(aprods_bench(S, g.dims.m, g.dims.n, g.dims.n_stars, workload)), flush=True)
         S.close()
         return
-    if args.cov > 0:
-        nst = (args.cov * 3 // 5) // 5
-        S.cov_request(gsr_synth.covariance_selection(g.dims, nst, args.cov * 3 // 10 // 3, args.cov - 5 * nst
-                                                     - 3 * (args.cov * 3 // 10 // 3), seed=19), block=64)
-    if args.pairs > 0:
+    layout = "star_order" if args.star_order else ("library_copy" if args.library_copy else "packed")
+    g = _generate(gsr_synth, workload, args.stars)
+    g_share = None if args.no_ttt else g  # the FP32 forms are timed on the same system
+    out, extra = share_leg(gsr, g, args.steps, args.warmup, layout=layout, cov=args.cov, export=args.export,
+                           pairs=args.pairs, constraints=args.constraints, timed_kernels=min(args.steps, 20))
+    del g
+    m, n, ns = out["_m"], out["_n"], out["_ns"]
+    res = {
+        "metric": "LSQR iterations/s (FP64, one-GPU share)",
+        "value": out["value"],
+        "unit": "iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": out["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": out["workload"], "global_batch": m, "seq_len": None, "parallelism": "single-gpu"},
+        "roofline": out["roofline"],
+        "iteration_ms": out["iteration_ms"],
+        "row_layout": out["row_layout"],
+    }
+    res.update(extra)
+    if "covariances" in out:
+        res["covariances"] = out["covariances"]
+    if not args.no_large and workload == "share_1m" and args.stars == 1_000_000 and layout == "packed":
+        # the largest single-GPU configuration: 3e6 stars with the covariances of 4,000
+        # unknowns in blocks of 64 iterations (one graph block warm-up, one timed block,
+        # one block with per-kernel events)
+        g3 = _generate(gsr_synth, "share_3m", 3_000_000)
+        o3, _ = share_leg(gsr, g3, 64, 64, layout="packed", cov=4000, timed_kernels=64)
+        del g3
+        res["share_3m_cov4000"] = {k: v for k, v in o3.items() if not k.startswith("_")}
+    if not args.no_ttt:
+        import gsr_synth as _gs
+
+        res["time_to_1e-10"] = {
+            "fp32_forms_tiny": time_to_tolerance_fp32(gsr, _gs.tiny(), label="tiny: 1,000 stars x 20 rows"),
+            "fp32_forms_share": time_to_tolerance_fp32(gsr, g_share, label=f"{workload}: {ns} stars x U[50,90] rows",
+                                                       packed=True),
+            "warm_start": time_to_tolerance_warm(gsr),
+        }
+    del g_share
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(m)
+    print(json.dumps(res), flush=True)
+
+
+def _generate(gsr_synth, workload, stars):
+    t = time.time()
+    if workload == "share_3m":
+        g = gsr_synth.share_3m() if stars in (1_000_000, 3_000_000) else gsr_synth.share_3m(n_stars=stars)
+    else:
+        g = gsr_synth.share_1m(n_stars=stars)
+    print(f"# generated {workload}: m={g.dims.m} n={g.dims.n} in {time.time() - t:.1f}s", file=sys.stderr,
+          flush=True)
+    return g
+
+
+def share_leg(gsr, g, K, W, layout="packed", cov=0, export=0, pairs=0, constraints=False, timed_kernels=20):
+    """One timed LSQR run on a share.  The handle is made over rows the caller placed
+    in the regrouped order (layout "packed": the library holds no copy of A), over the
+    rows in star order with the library's regrouped copy ("library_copy"), or in star
+    order with the bucketed attitude pass ("star_order").  A throwaway solve first
+    captures the iteration graph; then W untimed warm-up iterations and exactly K timed
+    ones with graph replay on (the shipped configuration) give the iteration rate;
+    then `timed_kernels` more iterations with HIP events around every kernel (graph
+    replay off) give the per-kernel times the roofline uses."""
+    import numpy as np
+    import torch
+
+    import gsr_synth
+
+    m, n, ns = g.dims.m, g.dims.n, g.dims.n_stars
+    t = time.time()
+    if layout == "packed":
+        S = gsr.System.packed_from_generated(g)
+    else:
+        S = gsr.System.from_generated(g)
+        S.set_blocked(layout == "library_copy")
+    print(f"# handle ({layout}) in {time.time() - t:.1f}s", file=sys.stderr, flush=True)
+    sel = None
+    if cov > 0:
+        nst = (cov * 3 // 5) // 5
+        sel = gsr_synth.covariance_selection(g.dims, nst, cov * 3 // 10 // 3, cov - 5 * nst - 3 * (cov * 3 // 10 // 3),
+                                             seed=19)
+        S.cov_request(sel, block=64)
+    if pairs > 0:
         rngp = np.random.default_rng(29)
-        S.cov_request_pairs(rngp.integers(0, g.dims.n, size=(args.pairs, 2)), block=64)
-    if args.constraints:
+        S.cov_request_pairs(rngp.integers(0, n, size=(pairs, 2)), block=64)
+    if constraints:
         d = g.dims
         rows = [np.arange(k, d.n_astro, 5) for k in range(3)]
         rows += [d.n_astro + a * d.n_att + np.arange(d.n_att) for a in range(3)]
@@ -491,121 +572,109 @@ def main():
         val = np.concatenate([np.full(r.size, np.sqrt(24.0 / r.size)) for r in rows])
         rhs = np.array([val[ptr[i]:ptr[i + 1]] @ g.x_true[col[ptr[i]:ptr[i + 1]]] for i in range(6)])
         S.set_constraints(ptr, col, val, rhs)
-    dims = g.dims
-    sel = None
-    if args.cov > 0:
-        sel = gsr_synth.covariance_selection(g.dims, nst, args.cov * 3 // 10 // 3,
-                                             args.cov - 5 * nst - 3 * (args.cov * 3 // 10 // 3), seed=19)
     ehost = None
-    if args.export > 0:
-        nblk = (args.warmup + args.steps + args.export - 1) // args.export + 1
-        ehost = torch.empty((nblk, args.export, g.dims.n), dtype=torch.float64).pin_memory()
-        S.cov_export(ehost, args.export)
+    if export > 0:
+        nblk = (W + K + timed_kernels + export - 1) // export + 1
+        ehost = torch.empty((nblk, export, n), dtype=torch.float64).pin_memory()
+        S.cov_export(ehost, export)
     xt = torch.from_numpy(g.x_true).cuda()
     b = torch.from_numpy(g.noise).cuda()
-    g_share = None if args.no_ttt else g  # the FP32 forms are timed on the same system
-    del g
     S.aprod1(xt, b, scale=1.0)  # b = A x_true + noise
+    del xt
     torch.cuda.synchronize()
-
-    K, W = args.steps, args.warmup
-    S.lsqr_begin(b, atol=0.0, btol=0.0, itmax=W + K + 1, precond=False)
+    G = 64 if (cov > 0 or pairs > 0) else 16
+    if export == 0:
+        # capture the iteration graph once (it is replayed by later solves of the same configuration)
+        S.lsqr_begin(b, atol=0.0, btol=0.0, itmax=G + 1, precond=False)
+        S.lsqr_iterate(G)
+        S.lsqr_end(want_var=False)
+    S.lsqr_begin(b, atol=0.0, btol=0.0, itmax=W + K + timed_kernels + 1, precond=False)
     S.lsqr_iterate(W)
     st = S.lsqr_status()
     assert st["itn"] == W, st
-    S.timing_enable(True)
-    S.timing_get()  # reset
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     S.lsqr_iterate(K)
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
-    tm = S.timing_get()
-    S.timing_enable(False)
     st = S.lsqr_status()
     if st["itn"] != W + K:
         raise RuntimeError(f"solve stopped early (itn={st['itn']}, istop={st['istop']}): timed steps not all real")
+    # per-kernel HIP events on the solve's stream, over a separate run of iterations
+    S.timing_enable(True)
+    S.timing_get()  # reset
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    S.lsqr_iterate(timed_kernels)
+    torch.cuda.synchronize()
+    Tk = time.perf_counter() - t1
+    tm = S.timing_get()
+    S.timing_enable(False)
+    if S.lsqr_status()["itn"] != W + K + timed_kernels:
+        raise RuntimeError("solve stopped early in the per-kernel timing run")
     cov_ms = None
-    if args.cov > 0:
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        S.lsqr_end(want_var=False)  # flushes the last partial covariance block
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    S.lsqr_end(want_var=False)  # flushes the last partial covariance block
+    if cov > 0:
         C = S.cov_get()
         torch.cuda.synchronize()
-        cov_ms = 1e3 * (time.perf_counter() - t1)
+        cov_ms = 1e3 * (time.perf_counter() - t2)
         del C
-    else:
-        S.lsqr_end(want_var=False)
-
-    # timing scopes of an iteration: the row pass, the second pass (segment
-    # reduction of the regrouped pass, or partition of u and the bucketed
-    # attitude sums), the tail, the x / w / var update
     f_ms = tm["aprod1_ms"] / max(1, tm["aprod1_n"])
-    att_ms = tm["aprod2_ms"] / max(1, tm["aprod2_n"])
-    kname, by = pass_bytes(S.blocked_info(), m, ns)
+    info = S.blocked_info()
+    kname, by = pass_bytes(info, m, ns)
     achieved = by / (f_ms * 1e-3) / 1e9
     copy_gbps = stream_copy_gbps()
-    workload = args.workload
-    traffic = load_traffic(kname, workload)
+    wl = "share_3m" if g.dims.n_att == 120_000 else "share_1m"
+    d = g.dims
     out = {
-        "metric": "LSQR iterations/s (FP64, one-GPU share)",
-        "value": K / T,
-        "unit": "iterations/s",
-        "n_gpus": 1,
-        "steps": K,
-        "warmup": W,
-        "ms_per_step": 1e3 * T / K,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": f"{workload}: {ns} stars x U[50,90] obs (m={m}), 3x{dims.n_att} attitude, "
-                               f"{dims.n_instr} instr, {dims.n_glob} global (n={n}); unscaled FP64 LSQR, damp 0, "
-                               f"variances on" + (f", covariances of {args.cov} unknowns" if args.cov else "")
-                               + (", 6 constraint equations" if args.constraints else ""),
-                   "global_batch": m, "seq_len": None, "parallelism": "single-gpu"},
+        "_m": m, "_n": n, "_ns": ns,
+        "workload": f"{wl}: {ns} stars x U[50,90] obs (m={m}), 3x{d.n_att} attitude, {d.n_instr} instr, "
+                    f"{d.n_glob} global (n={n}); unscaled FP64 LSQR, damp 0, variances on"
+                    + (f", covariances of {cov} unknowns in blocks of 64 iterations" if cov else "")
+                    + (", 6 constraint equations" if constraints else "")
+                    + {"packed": "; rows placed by the caller in the regrouped order (no library copy of A)",
+                       "library_copy": "; rows in star order, library's regrouped copy",
+                       "star_order": "; rows in star order, bucketed attitude pass"}[layout],
+        "value": K / T, "ms_per_step": 1e3 * T / K, "steps": K, "warmup": W,
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(kname, wl),
                      "bytes_per_launch": by, "avg_ms": f_ms,
+                     "timed_over": f"{timed_kernels} iterations with HIP events around every kernel on the solve's "
+                                   f"stream, right after the timed region ({1e3 * Tk / timed_kernels:.3f} ms per "
+                                   f"iteration there, graph replay off)",
                      "stream_copy_GBps": copy_gbps, "frac_of_stream_copy": achieved / copy_gbps},
-        "iteration_ms": {"row_pass": f_ms, "second_pass": att_ms,
+        "iteration_ms": {"row_pass": f_ms, "second_pass": tm["aprod2_ms"] / max(1, tm["aprod2_n"]),
                          "tail": tm["tail_ms"] / max(1, tm["tail_n"]),
                          "update": tm["update_ms"] / max(1, tm["update_n"])},
-        "row_layout": S.blocked_info() if kname == "k_fblk" else "star order",
+        "row_layout": info if kname == "k_fblk" else "star order",
     }
-    if args.export > 0:
+    extra = {}
+    if export > 0:
         nb, lc = S.cov_export_status()
-        out["export"] = {"block": args.export, "blocks": nb, "last_cols": lc,
-                         "bytes_per_block": 8 * args.export * n,
-                         "iteration_ms_with_export": 1e3 * T / K}
+        extra["export"] = {"block": export, "blocks": nb, "last_cols": lc, "bytes_per_block": 8 * export * n,
+                           "iteration_ms_with_export": 1e3 * T / K}
         if sel is not None:
             torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            Cx = gsr.cov_from_export(ehost, n, args.export, nb, lc, sel)
+            t3 = time.perf_counter()
+            Cx = gsr.cov_from_export(ehost, n, export, nb, lc, sel)
             torch.cuda.synchronize()
-            out["export"]["read_cov_ms_per_block"] = 1e3 * (time.perf_counter() - t1) / max(1, nb)
-            out["export"]["k"] = int(sel.size)
+            extra["export"]["read_cov_ms_per_block"] = 1e3 * (time.perf_counter() - t3) / max(1, nb)
+            extra["export"]["k"] = int(sel.size)
             del Cx
-    if args.pairs > 0:
-        out["pair_covariances"] = {"pairs": args.pairs, "block": 64,
-                                   "pair_dots_ms_per_block": tm["syrk_ms"] / max(1, tm["syrk_n"]),
-                                   "blocks_timed": tm["syrk_n"]}
-    if args.cov > 0:
-        out["covariances"] = {"k": args.cov, "block": 64, "syrk_ms_per_block": tm["syrk_ms"] / max(1, tm["syrk_n"]),
+    if pairs > 0:
+        extra["pair_covariances"] = {"pairs": pairs, "block": 64,
+                                     "pair_dots_ms_per_block": tm["syrk_ms"] / max(1, tm["syrk_n"]),
+                                     "blocks_timed": tm["syrk_n"]}
+    if cov > 0:
+        out["covariances"] = {"k": cov, "block": 64, "syrk_ms_per_block": tm["syrk_ms"] / max(1, tm["syrk_n"]),
                               "syrk_blocks_timed": tm["syrk_n"], "final_flush_and_get_ms": cov_ms}
     S.close()
-    if not args.no_ttt:
-        import gsr_synth as _gs
-
-        out["time_to_1e-10"] = {
-            "fp32_forms_tiny": time_to_tolerance_fp32(gsr, _gs.tiny(), label="tiny: 1,000 stars x 20 rows"),
-            "fp32_forms_share": time_to_tolerance_fp32(gsr, g_share, label=f"{workload}: {ns} stars x U[50,90] rows"),
-            "warm_start": time_to_tolerance_warm(gsr),
-        }
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(m)
-    print(json.dumps(out), flush=True)
+    del b
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out, extra
 
 
 if __name__ == "__main__":

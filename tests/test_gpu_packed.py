@@ -18,31 +18,15 @@ import pytest
 import torch
 
 import gsr_synth
+from _checks import abs_system, blocks, check_aprod1 as _check_aprod1, check_aprod2, rel
 
 pytestmark = pytest.mark.gpu
 
-EPS = np.finfo(np.float64).eps
+_rel, _blocks, _abs_system = rel, blocks, abs_system
 
 
-def _rel(a, b):
-    nb = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
-
-
-def _blocks(d):
-    na = d.n_astro
-    nt = na + 3 * d.n_att
-    ni = nt + d.n_instr
-    out = {"astro": slice(0, na), "att": slice(na, nt), "instr": slice(nt, ni), "all": slice(0, d.n)}
-    if d.n_glob:
-        out["glob"] = slice(ni, ni + 1)
-    return out
-
-
-def _abs_system(oracle_lib, g):
-    ga = copy.copy(g)
-    ga.vals = np.abs(g.vals)
-    return oracle_lib.OSystem(ga)
+def check_aprod1(oracle_lib, g, o, oa, x, y0, scale, y_gpu, tag):
+    return _check_aprod1(oracle_lib, o, oa, x, y0, scale, y_gpu, tag)
 
 
 @pytest.fixture(scope="module")
@@ -72,33 +56,6 @@ def _make(dev, c, value_dtype=None, chunk_rows=1 << 22):
         g.vals = g.vals.astype(value_dtype)
     S = dev.System.packed_from_generated(g, device="cuda:0", max_window=c["maxw"], chunk_rows=chunk_rows)
     return g, S
-
-
-def check_aprod1(oracle_lib, g, o, oa, x, y0, scale, y_gpu, tag):
-    """aprod 1 at the product bar: normwise and per element."""
-    ref = oracle_lib.aprod1(o, x, y=y0, scale=scale)
-    bnd = oracle_lib.aprod1(oa, np.abs(x), y=np.abs(y0), scale=abs(scale))
-    e = _rel(y_gpu, ref)
-    worst = float(np.max(np.abs(y_gpu - ref) / np.maximum(bnd, 1e-300)))
-    print(f"  {tag} aprod1 {e:.2e}, worst element {worst / EPS:.2f} eps of |A||x|", flush=True)
-    assert e <= 1e-13
-    assert np.all(np.abs(y_gpu - ref) <= 64 * EPS * bnd)
-    return ref
-
-
-def check_aprod2(oracle_lib, g, o, oa, y, x0, scale, x_gpu, tag):
-    """aprod 2 at the product bar: normwise per block and per element."""
-    ref = oracle_lib.aprod2(o, y, x=x0, scale=scale)
-    bnd = oracle_lib.aprod2(oa, np.abs(y), x=np.abs(x0), scale=abs(scale))
-    for name, sl in _blocks(g.dims).items():
-        e = _rel(x_gpu[sl], ref[sl])
-        print(f"  {tag} aprod2 {name} {e:.2e}", flush=True)
-        assert e <= 1e-13, name
-    d = np.abs(x_gpu - ref)
-    worst = float(np.max(d / np.maximum(bnd, 1e-300)))
-    print(f"  {tag} aprod2 worst element {worst / EPS:.2f} eps of |A|^T|y|", flush=True)
-    assert np.all(d <= 64 * EPS * bnd)
-    return ref
 
 
 @pytest.mark.parametrize("case", list(CASES))
