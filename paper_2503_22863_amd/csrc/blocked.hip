@@ -179,11 +179,12 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
     // of 16 bytes (the products round x to FP32 anyway, so the arithmetic is
     // the same).
     constexpr int NP = PM == 1 ? 3 : 6;  // 16-byte pieces per window
-    double xs;
+    double xs, xs2;
     dd2u cw[NP];
     auto gathers = [&]() {
       const int64_t st0 = (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)rec.x, 0);
       xs = x[min(5 * st0 + lane, xa_last)];
+      xs2 = x[min(5 * st0 + kWave + lane, xa_last)];
       const int ao_l = (int)(rec.y & 0x1FFFu);
 #pragma unroll
       for (int j = 0; j < NP; ++j) {
@@ -225,7 +226,10 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
       const double uo_c = (scale == 0.0) ? 0.0 : scale * uo;
       const int64_t s0 = lane_read(star, 0);
       const int64_t ds = star - s0;
-      const bool far = __ballot(ds >= 12) != 0;  // more than 12 stars in the tile: per-lane gathers
+      // more than 12 stars in the tile: the second shuffle window too; more than 25:
+      // per-lane gathers for the lanes past it
+      const bool far = __ballot(ds >= 12) != 0;
+      const bool farther = __ballot(ds >= 25) != 0;
       u4 cur[CPR];
 #pragma unroll
       for (int j = 0; j < CPR; ++j) cur[j] = tmp[j];
@@ -237,16 +241,25 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
       // u'_r = u_scale * u_r + (A x)_r
       double ax = 0.0;
       {
-        // every lane takes its star's x from the shuffle window (used on every
-        // path, so the load stays where it was issued); lanes whose star lies
-        // past the window gather per lane, consumed inside the branch: a load
-        // still pending where the paths join would make the compiler wait for
-        // the next tile's loads too
-        const int base = 5 * (int)min<int64_t>(ds, 11);
+        // every lane takes its star's x from the shuffle windows (stars st0 ..
+        // st0+12 in xs, the next 12.8 in xs2; both loads are issued for every
+        // tile, so they stay where they were issued); lanes whose star lies past
+        // both windows gather per lane, consumed inside the branch: a load still
+        // pending where the paths join would make the compiler wait for the next
+        // tile's loads too
+        const int base = 5 * (int)min<int64_t>(ds, 24);
         double axa = 0.0;
 #pragma unroll
-        for (int k = 0; k < 5; ++k) axa += prod<PM>(a[k], __shfl(xs, base + k, kWave));
-        if (far && ds >= 12) {
+        for (int k = 0; k < 5; ++k) {
+          const int idx = base + k;
+          double xv = __shfl(xs, idx & (kWave - 1), kWave);
+          if (far) {
+            const double hi = __shfl(xs2, idx & (kWave - 1), kWave);
+            xv = idx >= kWave ? hi : xv;
+          }
+          axa += prod<PM>(a[k], xv);
+        }
+        if (farther && ds >= 25) {
           double xa5[5];
 #pragma unroll
           for (int k = 0; k < 5; ++k) xa5[k] = x[5 * star + k];
