@@ -282,9 +282,9 @@ static void resolve_scratch(int dev);
 static int init_workspaces(gsr_system* s, hipStream_t st) {
   const SysView& v = s->s;
   CHK(dalloc(&s->sc, 1));
-  CHK(dalloc(&s->wk.part_a, kMaxPartials));
-  CHK(dalloc(&s->wk.part_b, kMaxPartials));
-  CHK(dalloc(&s->wk.part_c, kMaxPartials));
+  CHK(dalloc(&s->wk.part_a, kPartialSlots));
+  CHK(dalloc(&s->wk.part_b, kPartialSlots));
+  CHK(dalloc(&s->wk.part_c, kPartialSlots));
   CHK(dalloc(&s->wk.tickets, kTickets));
   CHK(dalloc(&s->acc, (size_t)v.tail_len));
   if (hipHostMalloc((void**)&s->sc_host, sizeof(Scalars), hipHostMallocDefault) != hipSuccess) {
@@ -754,8 +754,7 @@ static int blk_products(gsr_system* s, const double* v, const double* u_in, doub
   HIPCHK(launch_fblk(s->s, bv, square ? GSR_PROD_F64 : product, v, s->x3, s->x3f, s->acc, s->psc, s->wk, st, 0,
                      square));
   if (want_t || square) {
-    HIPCHK(launch_seg_reduce(s->s, bv, s->gA, s->psc, st));
-    HIPCHK(launch_tail_blk(s->s, bv, x, s->acc, nullptr, s->gA, s->psc, s->wk, st, 1));
+    HIPCHK(launch_tail_seg(s->s, bv, x, s->acc, nullptr, s->psc, s->wk, st, 1));
   } else {
     // the pass added its instrumental and global sums into the tail accumulators
     HIPCHK(launch_fill(s->acc + 3 * s->s.n_att, s->s.n_instr + s->s.n_glob, 0.0, st));
@@ -1061,9 +1060,13 @@ static int lsqr_begin(gsr_system* s, const double* b, const double* x0, const gs
     // constraint rows of u stay after the m rows of s->u (uc)
     if (s->con.ncon > 0) HIPCHK(launch_con_aprod1(s->con, s->zvec, uc, 0.0, 1.0, s->sc, s->wk, st));
     HIPCHK(launch_fblk(s->s, s->blk, pm0, vg0, s->x3, s->x3f, s->acc, s->sc, s->wk, st, 1));
-    HIPCHK(launch_seg_reduce(s->s, s->blk, s->gA, s->sc, st));
-    if (s->con.ncon > 0) HIPCHK(launch_con_aprod2(s->con, s->s.n_astro, uc, s->gA, s->acc, s->sc, st));
-    HIPCHK(launch_tail_blk(s->s, s->blk, s->v, s->acc, S, s->gA, s->sc, s->wk, st, 0));
+    if (s->con.ncon > 0) {
+      HIPCHK(launch_seg_reduce(s->s, s->blk, s->gA, s->sc, st));
+      HIPCHK(launch_con_aprod2(s->con, s->s.n_astro, uc, s->gA, s->acc, s->sc, st));
+      HIPCHK(launch_tail_blk(s->s, s->blk, s->v, s->acc, S, s->gA, s->sc, s->wk, st, 0));
+    } else {
+      HIPCHK(launch_tail_seg(s->s, s->blk, s->v, s->acc, S, s->sc, s->wk, st, 0));
+    }
   } else if (s->con.ncon > 0) {
     // beta_1 u_1 = r0 and alpha_1 v_1 = S [A; C]^T u_1 through the iteration's own
     // passes, with x = 0 (u' = u) and the init steps of the scalar recurrences
@@ -1143,17 +1146,18 @@ static int enqueue_iteration(gsr_system* s, hipStream_t st) {
       TimeScope ts(s, 0, st);
       HIPCHK(launch_fblk(s->s, s->blk, s->pmode, vg, s->x3, s->x3f, s->acc, s->sc, s->wk, st));
     }
-    {
-      TimeScope ts(s, 1, st);
-      HIPCHK(launch_seg_reduce(s->s, s->blk, s->gA, s->sc, st));
-    }
     if (s->con.ncon > 0) {
+      // the constraint rows add into the raw sums between the segment reduction and the tail
+      {
+        TimeScope ts(s, 1, st);
+        HIPCHK(launch_seg_reduce(s->s, s->blk, s->gA, s->sc, st));
+      }
       TimeScope ts(s, 2, st);
       HIPCHK(launch_con_aprod2(s->con, s->s.n_astro, uc, s->gA, s->acc, s->sc, st));
-    }
-    {
-      TimeScope ts(s, 2, st);
       HIPCHK(launch_tail_blk(s->s, s->blk, s->v, s->acc, S, s->gA, s->sc, s->wk, st));
+    } else {
+      TimeScope ts(s, 2, st);
+      HIPCHK(launch_tail_seg(s->s, s->blk, s->v, s->acc, S, s->sc, s->wk, st));
     }
   } else if (iteration_fused(s)) {
     const int mode = att_mode(s);

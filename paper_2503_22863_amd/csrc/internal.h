@@ -13,7 +13,8 @@ constexpr int kWave = 64;          // CDNA wavefront
 constexpr int kBlock = 256;        // threads per workgroup (4 waves)
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kSlots = 24;         // coefficients per row: 5 astro, 12 attitude, 6 instr, 1 global
-constexpr int kMaxPartials = 4096; // upper bound on workgroups of a reducing launch
+constexpr int kMaxPartials = 4096; // upper bound on workgroups of most reducing launches
+constexpr int kPartialSlots = 16384; // partial slots in Work (the segment-reducing tail takes up to this many)
 constexpr int kLdsTailMax = 2048;   // tail columns accumulated in LDS when they fit (16 KB)
 constexpr int kXcds = 8;            // XCDs; workgroup b is dispatched to XCD b mod 8
 
@@ -47,9 +48,9 @@ struct Scalars {
 
 // Reduction workspace: per-launch workgroup partials and tickets.
 struct Work {
-  double* part_a;            // [kMaxPartials] partial sums of a reducing launch
-  double* part_b;            // [kMaxPartials] second set (astro part of ||v||^2)
-  double* part_c;            // [kMaxPartials] third set (sum of d^2 in the update pass)
+  double* part_a;            // [kPartialSlots] partial sums of a reducing launch
+  double* part_b;            // [kPartialSlots] second set (astro part of ||v||^2)
+  double* part_c;            // [kPartialSlots] third set (sum of d^2 in the update pass)
   unsigned* tickets;         // [8] last-workgroup tickets, one per kernel kind
 };
 
@@ -224,6 +225,11 @@ hipError_t launch_tail_fused(const SysView& s, const AttView& av, int att_mode, 
 // The same after the regrouped pass: attitude sums from its workgroup windows (gA from launch_seg_reduce).
 hipError_t launch_tail_blk(const SysView& s, const BlkView& bv, double* x, double* acc, const double* S,
                            const double* gA, Scalars* sc, Work w, hipStream_t st, int lsqr_stage = 1);
+// The tail after the regrouped pass with the segment reduction folded in (no gA): every column
+// x_j <- v_scale*x_j + S_j * raw_j / beta, astrometric raw sums from the star's segments, then
+// alpha and the rotations (sc required; sc->raw for a standalone product)
+hipError_t launch_tail_seg(const SysView& s, const BlkView& bv, double* x, double* acc, const double* S, Scalars* sc,
+                           Work w, hipStream_t st, int lsqr_stage = 1);
 // gA[5s + k] <- sum of star s's segment sums P[seg][k] (block order); skipped once the solve has stopped
 hipError_t launch_seg_reduce(const SysView& s, const BlkView& bv, double* gA, Scalars* sc, hipStream_t st);
 
