@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libgsr.so")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build", "gsr")
-SOURCES = ["capi.hip", "aprod.hip", "fused.hip", "blocked.hip", "attitude.hip", "constraints.hip", "lsqr.hip", "mlp.hip"]
+SOURCES = ["capi.hip", "aprod.hip", "fused.hip", "blocked.hip", "segments.hip", "attitude.hip", "constraints.hip", "lsqr.hip", "mlp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
