@@ -14,8 +14,9 @@ boundary moves single elements far past the bar.
 
 LSQR iterates are held to max(floor, 10 s) per block, where s is the
 oracle's own response to last-bit perturbations of b and of every
-coefficient (three runs): past the first iterations the iterates depend on
-the summation order itself.
+coefficient (three runs; at the full shares the coefficients' last mantissa
+bits are flipped at random rather than scaled by 1 + 2.2e-16 N(0,1)): past
+the first iterations the iterates depend on the summation order itself.
 """
 import copy
 import time
@@ -87,11 +88,18 @@ def sensitivity(oracle_lib, g, o, b, **kw):
     t = time.time()
     gp = copy.copy(g)
     gp.vals = g.vals.copy()
-    flat = gp.vals.reshape(-1)
     rng = np.random.default_rng(7)
-    step = 1 << 24  # in place, chunk by chunk: one extra copy of A at the full shares
-    for i in range(0, flat.size, step):
-        flat[i:i + step] *= 1 + 2.2e-16 * rng.standard_normal(min(step, flat.size - i))
+    if gp.vals.size <= 1 << 26:
+        gp.vals *= 1 + 2.2e-16 * rng.standard_normal(gp.vals.shape)
+    else:
+        # the full shares: the last mantissa bit of each coefficient flipped with
+        # probability 1/2 (a relative change of one unit in the last place), in
+        # place, chunk by chunk -- one extra copy of A and no large temporaries
+        bits = gp.vals.reshape(-1).view(np.uint64 if gp.vals.dtype == np.float64 else np.uint32)
+        step = 1 << 26
+        for i in range(0, bits.size, step):
+            n = min(step, bits.size - i)
+            bits[i:i + n] ^= rng.integers(0, 2, n, dtype=np.uint8).astype(bits.dtype)
     op = oracle_lib.OSystem(gp)
     print(f"  A perturbed at the last bit in {time.time() - t:.1f} s", flush=True)
     bps = [b * (1 + 2e-16 * np.random.default_rng(seed).standard_normal(b.size)) for seed in (5, 6)]
