@@ -22,6 +22,9 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 P64, P32 = 0, 1
+# LSQR only: A^T on the unnormalised u', divided by beta afterwards (the order of one pass over
+# the rows per iteration), with FP32 or FP64 products
+P32_1P, P64_1P = 2, 3
 
 
 def build(force: bool = True) -> str:

@@ -55,6 +55,14 @@ typedef struct {
 /* product modes */
 #define ORC_P64 0   /* a*x in FP64 */
 #define ORC_P32 1   /* fl32(fl32(a)*fl32(x)), accumulated in FP64 */
+/* LSQR only: FP32 products as ORC_P32, with the operand of each A^T product the
+ * unnormalised u' = A S v - alpha u (before the division by beta = ||u'||) and the
+ * column sums divided by beta afterwards -- the same vector in exact arithmetic,
+ * but the FP32 rounding falls on u'_r instead of u'_r / beta.  This is the order
+ * in which a single pass over the rows forms both products of an iteration.
+ * ORC_P64_1P: the same order with FP64 products. */
+#define ORC_P32_1P 2
+#define ORC_P64_1P 3
 
 int64_t orc_n_unknowns(const orc_sys *A)
 {
@@ -267,7 +275,7 @@ typedef struct {
     double damp, atol, btol, conlim;
     int64_t itmax;
     int32_t precond; /* 1: diagonal column scaling S = diag(1/||a_j||) */
-    int32_t mode;    /* ORC_P64 or ORC_P32 */
+    int32_t mode;    /* ORC_P64, ORC_P32, ORC_P32_1P or ORC_P64_1P */
 } orc_opts;
 
 typedef struct {
@@ -329,6 +337,8 @@ int orc_lsqr(const orc_sys *A, const double *b, const double *x0, double *x, dou
             t[j] = -x0[j];
         orc_aprod1(A, t, u, 1.0, ORC_P64);
     }
+    const int onepass = o->mode == ORC_P32_1P || o->mode == ORC_P64_1P;
+    const int pmode = o->mode == ORC_P32_1P ? ORC_P32 : o->mode == ORC_P64_1P ? ORC_P64 : o->mode;
     const double damp = o->damp, dampsq = o->damp * o->damp;
     const double ctol = o->conlim > 0.0 ? 1.0 / o->conlim : 0.0;
     double beta = nrm2(u, m), alpha = 0.0;
@@ -337,14 +347,27 @@ int orc_lsqr(const orc_sys *A, const double *b, const double *x0, double *x, dou
     int64_t itn = 0;
     /* initial conditions with aprod 2: beta1 u1 = r0, alpha1 v1 = (A S)^T u1 */
     if (beta > 0.0) {
-        for (int64_t i = 0; i < m; ++i)
-            u[i] /= beta;
-        if (orc_aprod2(A, u, t, 0.0, o->mode)) {
-            rc = -1;
-            goto out;
+        if (onepass) {
+            /* A^T on the unnormalised r0, then divided by beta */
+            if (orc_aprod2(A, u, t, 0.0, pmode)) {
+                rc = -1;
+                goto out;
+            }
+            const double ib = 1.0 / beta;
+            for (int64_t j = 0; j < n; ++j)
+                v[j] = S[j] * (ib * t[j]);
+            for (int64_t i = 0; i < m; ++i)
+                u[i] /= beta;
+        } else {
+            for (int64_t i = 0; i < m; ++i)
+                u[i] /= beta;
+            if (orc_aprod2(A, u, t, 0.0, pmode)) {
+                rc = -1;
+                goto out;
+            }
+            for (int64_t j = 0; j < n; ++j)
+                v[j] = S[j] * t[j];
         }
-        for (int64_t j = 0; j < n; ++j)
-            v[j] = S[j] * t[j];
         alpha = nrm2(v, n);
     } else {
         memset(v, 0, (size_t)n * sizeof(double));
@@ -365,19 +388,28 @@ int orc_lsqr(const orc_sys *A, const double *b, const double *x0, double *x, dou
             /* aprod 1: beta u = A S v - alpha u */
             for (int64_t j = 0; j < n; ++j)
                 t[j] = S[j] * v[j];
-            orc_aprod1(A, t, u, -alpha, o->mode);
+            orc_aprod1(A, t, u, -alpha, pmode);
             beta = nrm2(u, m);
             if (beta > 0.0) {
+                double ib = 1.0;
+                if (onepass) {
+                    /* A^T on the unnormalised u', divided by beta below */
+                    if (orc_aprod2(A, u, t, 0.0, pmode)) {
+                        rc = -1;
+                        goto out;
+                    }
+                    ib = 1.0 / beta;
+                }
                 for (int64_t i = 0; i < m; ++i)
                     u[i] /= beta;
                 anorm = sqrt(anorm * anorm + alpha * alpha + beta * beta + dampsq);
                 /* aprod 2: alpha v = S A^T u - beta v */
-                if (orc_aprod2(A, u, t, 0.0, o->mode)) {
+                if (!onepass && orc_aprod2(A, u, t, 0.0, pmode)) {
                     rc = -1;
                     goto out;
                 }
                 for (int64_t j = 0; j < n; ++j)
-                    v[j] = S[j] * t[j] - beta * v[j];
+                    v[j] = onepass ? S[j] * (ib * t[j]) - beta * v[j] : S[j] * t[j] - beta * v[j];
                 alpha = nrm2(v, n);
                 if (alpha > 0.0)
                     for (int64_t j = 0; j < n; ++j)

@@ -1067,22 +1067,25 @@ static int lsqr_begin(gsr_system* s, const double* b, const double* x0, const gs
     } else {
       HIPCHK(launch_tail_seg(s->s, s->blk, s->v, s->acc, S, s->sc, s->wk, st, 0));
     }
-  } else if (s->con.ncon > 0) {
+  } else if (s->con.ncon > 0 || iteration_fused(s)) {
     // beta_1 u_1 = r0 and alpha_1 v_1 = S [A; C]^T u_1 through the iteration's own
-    // passes, with x = 0 (u' = u) and the init steps of the scalar recurrences
+    // passes, with x = 0 (u' = u) and the init steps of the scalar recurrences: the
+    // first A^T product then takes its operand in the same (unnormalised) form as
+    // every later one
     const int mode = att_mode(s);
     if (!s->zvec) {
       CHK(dalloc(&s->zvec, (size_t)s->s.n));
       HIPCHK(launch_fill(s->zvec, s->s.n, 0.0, st));
     }
     HIPCHK(launch_att_interleave(s->s, s->zvec, s->x3, st));
-    HIPCHK(launch_con_aprod1(s->con, s->zvec, uc, 0.0, 1.0, s->sc, s->wk, st));
-    HIPCHK(launch_fused(s->s, s->sh, mode, 0, s->zvec, s->x3, s->rix, s->u, s->gA, s->acc, s->sc, s->wk, st, 1));
+    if (s->con.ncon > 0) HIPCHK(launch_con_aprod1(s->con, s->zvec, uc, 0.0, 1.0, s->sc, s->wk, st));
+    HIPCHK(launch_fused(s->s, s->sh, mode, product, s->zvec, s->x3, s->rix, s->u, s->gA, s->acc, s->sc, s->wk, st,
+                        1));
     if (mode == 3) {
       HIPCHK(launch_partition(s->s, s->av, s->u, s->sc, st));
-      HIPCHK(launch_att_pass(s->s, s->av, 1.0, 0, 0, s->sc, st, 1));
+      HIPCHK(launch_att_pass(s->s, s->av, 1.0, product, 0, s->sc, st, 1));
     }
-    HIPCHK(launch_con_aprod2(s->con, s->s.n_astro, uc, s->gA, s->acc, s->sc, st));
+    if (s->con.ncon > 0) HIPCHK(launch_con_aprod2(s->con, s->s.n_astro, uc, s->gA, s->acc, s->sc, st));
     HIPCHK(launch_tail_fused(s->s, s->av, mode, s->v, s->acc, S, s->gA, s->sc, s->wk, st, 0));
   } else {
     HIPCHK(launch_norm_init(s->u, s->s.m, s->sc, s->wk, st));

@@ -29,12 +29,14 @@ def dev():
     return gsr
 
 
-def _sensitivity(oracle_lib, g, o, b, **kw):
+def _sensitivity(oracle_lib, g, o, b, nruns=2, **kw):
     """Reference run and the largest relative deviations of x, var and the scalar
     estimates over runs with b and with A perturbed at the last bit."""
     r1 = oracle_lib.lsqr(o, b, **kw)
     runs = []
-    for seed in (5, 6):
+    # nruns perturbations of b (more for FP32 products, whose response is dominated by
+    # rare FP32 rounding flips: a few runs can miss them)
+    for seed in range(5, 5 + nruns):
         bp = b * (1 + 2e-16 * np.random.default_rng(seed).standard_normal(b.size))
         runs.append(oracle_lib.lsqr(o, bp, **kw))
     gp = copy.copy(g)
@@ -149,8 +151,8 @@ def test_blocked_converged_solution(dev, oracle_lib):
 
 def test_blocked_fp32_forms(dev, oracle_lib):
     """FP32 storage with FP64 products against the FP64 oracle on the same values, and
-    FP32 products against the oracle's FP32-product LSQR with the fused pass's bar (its
-    FP32 operand of A^T u is the unnormalised u)."""
+    FP32 products against the oracle's FP32-product LSQR in the one-pass order (its
+    FP32 operand of A^T u is the unnormalised u'), each at the oracle's last-bit bar."""
     print("[blocked] FP32 forms", flush=True)
     c = CASES["many_windows"]
     g32 = _system(c).as_f32()
@@ -169,12 +171,13 @@ def test_blocked_fp32_forms(dev, oracle_lib):
     print(f"  FP64 products: x {ex:.2e} var {ev:.2e}", flush=True)
     assert ex <= max(1e-12, 10 * sx) and ev <= max(1e-10, 10 * sv)
     o32 = oracle_lib.OSystem(g32)
-    ref32 = oracle_lib.lsqr(o32, bn, mode=oracle_lib.P32, **kw)
-    dx, dv = _rel(ref32["x"], ref["x"]), _rel(ref32["var"], ref["var"])
+    ref32, sx32, sv32 = _sensitivity(oracle_lib, g32, o32, bn, nruns=12, mode=oracle_lib.P32_1P, **kw)
+    dx = _rel(ref32["x"], ref["x"])
     x, var, r = S.lsqr_solve(b, product="f32", **kw)
     ex, ev = _rel(x.cpu().numpy(), ref32["x"]), _rel(var.cpu().numpy(), ref32["var"])
-    print(f"  FP32 products: x {ex:.2e} (FP32 effect {dx:.2e}) var {ev:.2e} ({dv:.2e})", flush=True)
-    assert ex <= 5 * dx and ev <= 5 * max(dv, sv)
+    print(f"  FP32 products: x {ex:.2e} (bar {max(1e-12, 10 * sx32):.1e}; FP32 effect {dx:.2e}) var {ev:.2e}",
+          flush=True)
+    assert ex <= max(1e-12, 10 * sx32) and ev <= max(1e-10, 10 * sv32)
     # refinement on the regrouped copy reaches the FP64 solution
     ref_c = oracle_lib.lsqr(o, bn, atol=1e-13, btol=1e-13, itmax=500, precond=True)
     xr, rr = S.lsqr_refine(b, atol=1e-6, btol=1e-6, itmax=1000, precond=True, outer_max=10, outer_tol=1e-11)
@@ -194,7 +197,8 @@ def test_blocked_fp32_forms(dev, oracle_lib):
 def test_blocked_fp32_storage_cases(dev, oracle_lib, case):
     """FP32 coefficients (6 chunks per row: other tile offsets and window loads than
     FP64) with FP64 products against the FP64 oracle on the same values, in every
-    layout case; FP32 products against the oracle's FP32-product LSQR."""
+    layout case; FP32 products against the oracle's FP32-product LSQR in the one-pass
+    order at its last-bit bar."""
     print(f"[blocked] FP32 storage, {case}", flush=True)
     c = CASES[case]
     g32 = _system(c).as_f32()
@@ -215,12 +219,13 @@ def test_blocked_fp32_storage_cases(dev, oracle_lib, case):
     assert ex <= max(1e-12, 10 * sx) and ev <= max(1e-10, 10 * sv)
     for k in ("rnorm", "anorm", "xnorm"):
         assert abs(r[k] - ref[k]) <= max(1e-12, 10 * ref["sens"][k]) * abs(ref[k]), k
-    ref32 = oracle_lib.lsqr(oracle_lib.OSystem(g32), bn, mode=oracle_lib.P32, **kw)
+    ref32, sx32, _ = _sensitivity(oracle_lib, g32, oracle_lib.OSystem(g32), bn, nruns=12, mode=oracle_lib.P32_1P,
+                                  **kw)
     dx = _rel(ref32["x"], ref["x"])
     x, var, r = S.lsqr_solve(b, product="f32", **kw)
     ex = _rel(x.cpu().numpy(), ref32["x"])
-    print(f"  FP32 products: x {ex:.2e} (FP32 effect {dx:.2e})", flush=True)
-    assert ex <= 5 * dx
+    print(f"  FP32 products: x {ex:.2e} (bar {max(1e-12, 10 * sx32):.1e}; FP32 effect {dx:.2e})", flush=True)
+    assert ex <= max(1e-12, 10 * sx32)
     S.close()
 
 

@@ -40,7 +40,7 @@ def tiny(dev, oracle_lib):
     return g, o, b, S
 
 
-def _sensitivity(oracle_lib, g, o, b, **kw):
+def _sensitivity(oracle_lib, g, o, b, nruns=2, **kw):
     """The oracle's own response to last-bit perturbations: b and, separately, every
     coefficient of A scaled by (1 + 2.2e-16 N(0,1)) (the size of the rounding differences
     between two valid summation orders).  Returns the reference run and the largest
@@ -50,7 +50,9 @@ def _sensitivity(oracle_lib, g, o, b, **kw):
 
     r1 = oracle_lib.lsqr(o, b, **kw)
     runs = []
-    for seed in (5, 6):
+    # nruns perturbations of b (more for FP32 products, whose response is dominated by
+    # rare FP32 rounding flips: a few runs can miss them)
+    for seed in range(5, 5 + nruns):
         bp = b * (1 + 2e-16 * np.random.default_rng(seed).standard_normal(b.size))
         runs.append(oracle_lib.lsqr(o, bp, **kw))
     gp = copy.copy(g)
@@ -331,33 +333,33 @@ def test_fused_fp32_storage_fp64_products(dev, oracle_lib):
 def test_fused_fp32_products(dev, oracle_lib, n_att):
     """FP32 products summed in FP64 (the inner solves of the FP32 form) against the
     oracle's FP32-product LSQR, with the attitude tail in LDS (32) and bucketed (1000).
-    Separate aprod 1 / aprod 2 passes round the same operands as the oracle and meet
-    its last-bit bar.  The fused pass forms A^T u' on the unnormalised u' and scales by
-    1/beta afterwards, so its FP32 operands are fl32(u'_r), not fl32(u'_r / beta): a
-    different FP32 rounding of the same products.  Its bar is the size of the FP32
-    product effect itself, the distance between the oracle's FP32-product and FP64
-    runs."""
+    Separate aprod 1 / aprod 2 passes round the same operands as the oracle's textbook
+    order (P32).  The one-pass iteration forms A^T u' on the unnormalised u' and scales
+    by 1/beta afterwards, so its FP32 operands are fl32(u'_r), not fl32(u'_r / beta);
+    the oracle's one-pass order (P32_1P) rounds the same operands.  Each form meets
+    its oracle at the oracle's own last-bit bar, taken over twelve perturbations of b
+    (the response of FP32-product iterates comes from rare FP32 rounding flips)."""
     print(f"[lsqr] fused FP32 products n_att={n_att}", flush=True)
     g = gsr_synth.make_system(300, (20, 40), n_att, 16, 1, seed=19).as_f32()
     o = oracle_lib.OSystem(g)
     bn = oracle_lib.known_terms(o, g.x_true, g.noise)
     kw = dict(atol=0, btol=0, itmax=25, precond=True)
-    ref, sx, sv = _sensitivity(oracle_lib, g, o, bn, mode=oracle_lib.P32, **kw)
+    refs = {False: _sensitivity(oracle_lib, g, o, bn, nruns=12, mode=oracle_lib.P32, **kw),
+            True: _sensitivity(oracle_lib, g, o, bn, nruns=12, mode=oracle_lib.P32_1P, **kw)}
     ref64 = oracle_lib.lsqr(o, bn, **kw)
-    dx, dv = _rel(ref["x"], ref64["x"]), _rel(ref["var"], ref64["var"])
-    print(f"  oracle sensitivity x {sx:.2e} var {sv:.2e}; FP32 vs FP64 products x {dx:.2e} var {dv:.2e}", flush=True)
-    assert dx > 10 * sx  # the FP32 products are visible above the last-bit noise
+    dx = _rel(refs[False][0]["x"], ref64["x"])
+    d1p = _rel(refs[True][0]["x"], refs[False][0]["x"])
+    print(f"  FP32 vs FP64 products x {dx:.2e}; one-pass vs textbook order {d1p:.2e}", flush=True)
+    assert dx > 10 * refs[False][1]  # the FP32 products are visible above the last-bit noise
     S = dev.System.from_generated(g)
     for fused in (False, True):
+        ref, sx, sv = refs[fused]
         S.set_fused(fused)
         x, var, r = S.lsqr_solve(torch.from_numpy(bn).cuda(), product="f32", **kw)
         assert r["itn"] == 25
         ex, ev = _rel(x.cpu().numpy(), ref["x"]), _rel(var.cpu().numpy(), ref["var"])
-        print(f"  fused={fused}: x {ex:.2e} var {ev:.2e}", flush=True)
-        if fused:
-            assert ex <= 5 * dx and ev <= 5 * max(dv, sv)
-        else:
-            assert ex <= max(1e-12, 10 * sx) and ev <= max(1e-10, 10 * sv)
+        print(f"  fused={fused}: x {ex:.2e} (bar {max(1e-12, 10 * sx):.1e}) var {ev:.2e}", flush=True)
+        assert ex <= max(1e-12, 10 * sx) and ev <= max(1e-10, 10 * sv)
     S.close()
 
 

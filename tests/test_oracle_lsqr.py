@@ -336,3 +336,43 @@ def test_machine_precision_stops_match_scipy(oracle_lib, case, expect):
     assert abs(r["itn"] - s["itn"]) <= 0.05 * s["itn"]
     x_ls = np.linalg.lstsq(A, b, rcond=None)[0]
     assert _rel(r["x"], x_ls) < 1e-12
+
+
+@pytest.mark.parametrize("damp", [0.0, 0.3])
+@pytest.mark.parametrize("k", [1, 7, 15])
+def test_one_pass_order_matches_scipy_lsqr(oracle_lib, damp, k):
+    """The one-pass order (A^T applied to the unnormalised u', divided by beta
+    afterwards; mode P64_1P) is the same LSQR: its iterates meet scipy's independent
+    LSQR at the bar of the textbook order."""
+    g = _small(seed=31)
+    o = oracle_lib.OSystem(g)
+    A = dense_A(g)
+    b = oracle_lib.known_terms(o, g.x_true, g.noise)
+    xs = scipy_lsqr(sp.csr_matrix(A), b, damp=damp, atol=0.0, btol=0.0, conlim=0.0, iter_lim=k)[0]
+    r = oracle_lib.lsqr(o, b, damp=damp, atol=0.0, btol=0.0, itmax=k, precond=False, mode=oracle_lib.P64_1P)
+    assert r["itn"] == k and r["istop"] == 7
+    assert _rel(r["x"], xs) < 1e-11
+
+
+def test_one_pass_fp32_products_round_the_unnormalised_operand(oracle_lib):
+    """FP32 products in the one-pass order (mode P32_1P) round u'_r where the textbook
+    order (P32) rounds u'_r / beta.  With b = 1 on 1,024 rows, beta_1 = 32 and
+    u_1 = b / 32 are exact, so both orders round exactly the same operands in the
+    first step and agree bit for bit after one iteration; from the second on the
+    operands differ and so do the iterates, both by the size of the FP32 product
+    effect (their distance from FP64 products)."""
+    g = _small(seed=33, n_stars=64, obs=16).as_f32()
+    assert g.dims.m == 1024
+    o = oracle_lib.OSystem(g)
+    b = np.ones(g.dims.m)
+    kw = dict(atol=0.0, btol=0.0, precond=False)
+    r1 = oracle_lib.lsqr(o, b, itmax=1, mode=oracle_lib.P32, **kw)
+    q1 = oracle_lib.lsqr(o, b, itmax=1, mode=oracle_lib.P32_1P, **kw)
+    assert np.array_equal(r1["x"], q1["x"]) and np.array_equal(r1["var"], q1["var"])
+    r = oracle_lib.lsqr(o, b, itmax=6, mode=oracle_lib.P32, **kw)
+    q = oracle_lib.lsqr(o, b, itmax=6, mode=oracle_lib.P32_1P, **kw)
+    f = oracle_lib.lsqr(o, b, itmax=6, mode=oracle_lib.P64, **kw)
+    d = _rel(q["x"], r["x"])
+    e32, e1p = _rel(r["x"], f["x"]), _rel(q["x"], f["x"])
+    assert d > 0
+    assert 0.1 * e32 < e1p < 10 * e32 and d < 10 * e32
