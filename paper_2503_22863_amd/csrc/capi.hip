@@ -500,6 +500,9 @@ extern "C" int gsr_layout_pack(gsr_layout* L, const void* rows, int64_t row0, in
   if (count == 0) return GSR_OK;
   NEED_DEV(rows, "rows");
   NEED_DEV(packed, "packed");
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev != L->device) return fail(GSR_EINVAL, "the layout's device must be current");
   if ((uintptr_t)rows % 16 || (uintptr_t)packed % 16) return fail(GSR_EINVAL, "rows and packed must be 16-byte aligned");
   HIPCHK(launch_blk_pack(L->bv, rows, row0, count, packed, (hipStream_t)stream));
   return GSR_OK;

@@ -299,3 +299,61 @@ def test_packed_handle_refusals_and_layout_reuse(dev):
     bad[17] = g.dims.n_att  # start past n_att - 4
     with pytest.raises(dev.GsrError, match="row 17"):
         dev.Layout(t(g.star_row_ptr), t(bad), t(g.instr_col), g.dims.n_att, g.dims.n_instr, 1)
+
+
+def test_packed_rows_in_any_chunk_order_give_the_same_products(dev, oracle_lib):
+    """gsr_layout_pack places rows wherever they come from: chunks of 777 rows in
+    reverse order give the same buffer, bit for bit, as one call over all rows."""
+    c = CASES["many_windows"]
+    g = gsr_synth.make_system(c["n_stars"], c["obs"], c["n_att"], c["n_instr"], 1, seed=c["seed"])
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    bufs = []
+    for order in ("whole", "reversed"):
+        L = dev.Layout(t(g.star_row_ptr), t(g.att_start), t(g.instr_col), g.dims.n_att, g.dims.n_instr, 1,
+                       max_window=c["maxw"])
+        P = L.new_buffer()
+        P.fill_(7.0)
+        if order == "whole":
+            L.pack(t(g.vals), 0, P)
+        else:
+            starts = list(range(0, g.dims.m, 777))[::-1]
+            for r0 in starts:
+                L.pack(t(g.vals[r0:r0 + 777]), r0, P)
+        S = dev.System.from_packed(L, P)  # zeroes the padding rows
+        bufs.append(P.cpu().numpy())
+        S.close()
+    assert np.array_equal(bufs[0], bufs[1])
+    # every coefficient appears once, the padding rows are zero
+    assert np.isclose(np.abs(bufs[0]).sum(), np.abs(g.vals).sum(), rtol=1e-12)
+    assert np.count_nonzero(bufs[0]) == np.count_nonzero(g.vals)
+
+
+def test_packed_covariance_export_and_pairs(dev, oracle_lib):
+    """Covariance pipeline versions 1 (export of whole d_i blocks) and 2 (index pairs)
+    on packed rows, against the oracle's stored direction vectors."""
+    c = CASES["many_windows"]
+    g, S = _make(dev, c)
+    o = oracle_lib.OSystem(g)
+    bn = oracle_lib.known_terms(o, g.x_true, g.noise)
+    itmax, block = 20, 8
+    d = g.dims
+    rng = np.random.default_rng(17)
+    pairs = np.stack([rng.integers(0, d.n, 40), rng.integers(0, d.n, 40)], axis=1)
+    U, inv = np.unique(pairs.reshape(-1), return_inverse=True)
+    inv = inv.reshape(-1, 2)
+    ref = oracle_lib.lsqr(o, bn, atol=0, btol=0, itmax=itmax, precond=True, sel=U)
+    host = torch.zeros((itmax // block + 2, block, d.n), dtype=torch.float64).pin_memory()
+    S.cov_export(host, block)
+    S.cov_request_pairs(pairs, block=block)
+    x, var, r = S.lsqr_solve(torch.from_numpy(bn).cuda(), atol=0, btol=0, itmax=itmax, precond=True)
+    nb, lc = S.cov_export_status()
+    assert (nb - 1) * block + lc == itmax
+    D = host.numpy()[:nb].reshape(-1, d.n)[:itmax]
+    ed = _rel(D[:, U], ref["dsel"])
+    Cref = oracle_lib.covariances(ref["dsel"], ref["scale"][U])[inv[:, 0], inv[:, 1]]
+    ep = _rel(S.cov_get_pairs().cpu().numpy(), Cref)
+    print(f"  exported d_i {ed:.2e}  pair covariances {ep:.2e}", flush=True)
+    assert ed <= 1e-10 and ep <= 1e-10
+    S.cov_export(None)
+    S.cov_request_pairs([], block=64)
+    S.close()
