@@ -132,10 +132,14 @@ __global__ void k_finish(int64_t n, const double* __restrict__ y, const double* 
 // C += D D^T over the first `cols` columns of D ([k][ldd], row-major), on the
 // upper triangle of 32 x 32 tiles of C ([k][k], row-major).  A workgroup owns
 // a 64 x 64 tile of C (upper tiles only); its four waves each hold a 32 x 32
-// quadrant in 2 x 2 accumulators of v_mfma_f64_16x16x4f64.  D is staged 32
-// columns at a time: the 64 rows of the tile's row panel and of its column
-// panel go to LDS (row pitch 34 doubles: conflict-free 16-byte reads), the
-// next stage's panels are prefetched into registers meanwhile.  Inside each
+// quadrant in 2 x 2 accumulators of v_mfma_f64_16x16x4f64.  The accumulators
+// start from the quadrant's C values, loaded before anything else, so the
+// read of C from HBM overlaps the staging of D and the MFMA work (C is the
+// bulk of the traffic: 2 k^2 / 2 doubles read and written per call, D only
+// 2 k cols).  D is staged 32 columns at a time: the 64 rows of the tile's row
+// panel and of its column panel go to LDS (row pitch 34 doubles: conflict-free
+// 16-byte reads), the next stage's panels are prefetched into registers
+// meanwhile (16-byte loads when the row pitch is even).  Inside each
 // 16-column half of a stage the k index of MFMA step s for lane group g is
 // 4g + s, so each lane reads 4 consecutive doubles of a row; A and B use the
 // same order, so the contraction is unchanged.  Four waves per SIMD (the
@@ -165,6 +169,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
     const int64_t r0 = ti * kSyT, c0 = tj * kSyT;
     const int qi = wid >> 1, qj = wid & 1;  // this wave's 32 x 32 quadrant
     const int i16 = lane & 15, g = lane >> 4;
+    const bool pairs = (ldd & 1) == 0;  // 16-byte aligned pairs of D (D itself is 256-byte aligned)
     // global -> register staging: thread t moves 16-byte pieces t + 256 h of
     // each 64 x kSyK panel (kSyK / 2 pieces per row)
     constexpr int kPieces = kSyT * kSyK / 2 / kBlock, kRowPieces = kSyK / 2;
@@ -176,23 +181,54 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
         const int64_t col = kk + 2 * part;
         const int64_t ga = r0 + row, gb = c0 + row;
         dd2 va = {0.0, 0.0}, vb = {0.0, 0.0};
-        if (ga < k) {
-          if (col < cols) va.x = D[ga * ldd + col];
-          if (col + 1 < cols) va.y = D[ga * ldd + col + 1];
-        }
-        if (gb < k) {
-          if (col < cols) vb.x = D[gb * ldd + col];
-          if (col + 1 < cols) vb.y = D[gb * ldd + col + 1];
+        if (pairs && col + 1 < cols) {
+          if (ga < k) va = *reinterpret_cast<const dd2*>(D + ga * ldd + col);
+          if (gb < k) vb = *reinterpret_cast<const dd2*>(D + gb * ldd + col);
+        } else {
+          if (ga < k) {
+            if (col < cols) va.x = D[ga * ldd + col];
+            if (col + 1 < cols) va.y = D[ga * ldd + col + 1];
+          }
+          if (gb < k) {
+            if (col < cols) vb.x = D[gb * ldd + col];
+            if (col + 1 < cols) vb.y = D[gb * ldd + col + 1];
+          }
         }
         ra[h] = va;
         rb[h] = vb;
       }
     };
+    // accumulator layout of the 16x16 f64 result: element e of lane l is row (l/16) + 4e,
+    // column l%16.  Only 32 x 32 tiles on or above the diagonal are read and written.
+    const int64_t row32 = r0 + 32 * qi, col32 = c0 + 32 * qj;
+    const bool mine = row32 <= col32;
+    const bool inner = row32 + 32 <= k && col32 + 32 <= k;
+    double* cq = C + (row32 + g) * k + col32 + i16;
     d4 acc[2][2];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+      for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = d4{0.0, 0.0, 0.0, 0.0};
+    if (mine && inner) {
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[bi][bj][e] = cq[(int64_t)(16 * bi + 4 * e) * k + 16 * bj];
+    } else if (mine) {
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (row32 + g + 16 * bi + 4 * e < k && col32 + i16 + 16 * bj < k)
+              acc[bi][bj][e] = cq[(int64_t)(16 * bi + 4 * e) * k + 16 * bj];
+    }
+    // the stores below recompute their addresses from here rather than keep the
+    // 16 load addresses live across the MFMA loop
+    __asm__ volatile("" : "+v"(cq));
     fetch(0);
     for (int64_t kk = 0; kk < cols; kk += kSyK) {
       __syncthreads();  // the previous stage's reads are done
@@ -231,19 +267,15 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
             acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bi][st], bv[bj][st], acc[bi][bj], 0, 0, 0);
       }
     }
-    // accumulator layout of the 16x16 f64 result: element e of lane l is row (l/16) + 4e, column l%16.
-    // Only 32 x 32 tiles on or above the diagonal are written.
-    const int64_t row32 = r0 + 32 * qi, col32 = c0 + 32 * qj;
-    if (row32 <= col32) {
+    if (mine) {
 #pragma unroll
       for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int64_t r = row32 + 16 * bi + g + 4 * e, c = col32 + 16 * bj + i16;
-            if (r < k && c < k) C[r * k + c] += acc[bi][bj][e];
-          }
+          for (int e = 0; e < 4; ++e)
+            if (inner || (row32 + g + 16 * bi + 4 * e < k && col32 + i16 + 16 * bj < k))
+              cq[(int64_t)(16 * bi + 4 * e) * k + 16 * bj] = acc[bi][bj][e];
     }
   }
   if (fixed_cols < 0) {

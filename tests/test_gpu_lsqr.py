@@ -200,7 +200,7 @@ def test_syrk_entry_point(dev):
     """C += D D^T on the upper tiles for ragged sizes and column counts."""
     print("[syrk]", flush=True)
     rng = np.random.default_rng(7)
-    for k, cols, ldd in [(1, 1, 1), (37, 5, 9), (100, 64, 64), (130, 150, 160)]:
+    for k, cols, ldd in [(1, 1, 1), (37, 5, 9), (100, 64, 64), (130, 150, 160), (200, 70, 71)]:
         D = rng.standard_normal((k, ldd))
         C0 = rng.standard_normal((k, k))
         Ct = torch.from_numpy(C0.copy()).cuda()
