@@ -204,14 +204,20 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
     // Targets of the previous tile's stores.  Every lane stores on every tile, so
     // that the in-order memory counter can be tracked exactly (a conditional
     // store makes the compiler wait for everything at the next use of a load);
-    // before the first tile and for lanes that close no segment the targets are
-    // this wave's dummy slots (the lanes writing the dummy line merge into one
-    // request).
+    // before the first tile the u targets, and for lanes past the tile's segment
+    // sums the P targets, are this wave's dummy slots, one per lane (lanes storing
+    // to one address are taken one at a time).  The segment sums of a tile are
+    // compacted through LDS into one contiguous run of 5 x (segments closed)
+    // values; g0 holds values 0..63 of the run, stored with the next tile.  A tile
+    // closing more than 12 segments (rare) stores values 64..127 at once, and one
+    // closing more than 25 the rest directly from the end lanes.
     double* const du = bv.dummy + w * kBlkDummy;
     double* u_dst = du + lane;
-    double* p_dst = du + kWave;
     double u_out = 0.0;
-    double g_out[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double g0 = 0.0;
+    double* pbase = bv.P;
+    int pn = 0;  // segments the previous tile closed
+    auto store_sums = [&]() { *(lane < 5 * pn ? pbase + lane : du + kWave + lane) = g0; };
     fetch(T0);
     gathers();
 #pragma unroll 1
@@ -333,8 +339,7 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
       // this tile's arithmetic to complete
       order_point();
       *u_dst = u_out;
-#pragma unroll
-      for (int k = 0; k < 5; ++k) p_dst[k] = g_out[k];
+      store_sums();
 #pragma unroll
       for (int q = 0; q < 6; ++q) ax += prod<PM>(a[17 + q], xil[ic[q]]);
       if (s.n_glob) ax += prod<PM>(a[23], xg);
@@ -367,9 +372,33 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
       const int seg0 = mine ? 63 - __clzll(mine) : 0;
       seg_scan(p, lane, seg0);
       const int64_t sidx = nstart - 1 + __popcll(mine);
-      p_dst = end ? bv.P + 5 * sidx : du + kWave;
+      // compaction: the end lane of rank r (ends below it) puts its five sums at
+      // 5r .. 5r+4 of the wave's LDS buffer (free between the attitude regroups);
+      // the other lanes at slots of their own past 128
+      const int nend = __popcll(ends);
+      const int rank = __popcll(ends & ((1ull << lane) - 1));
+      {
+        double* cl = reinterpret_cast<double*>(rg[wid]);
+        const int slot = (end && rank < 25) ? 5 * rank : 128 + 5 * lane;
 #pragma unroll
-      for (int k = 0; k < 5; ++k) g_out[k] = p[k];
+        for (int k = 0; k < 5; ++k) cl[slot + k] = p[k];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        g0 = cl[lane];
+        pbase = bv.P + (nend ? 5 * lane_read(sidx, nend ? __builtin_ctzll(ends) : 0) : 0);
+        pn = nend;
+        if (nend > 12) {
+          const double g1 = cl[kWave + lane];
+          if (kWave + lane < 5 * nend) pbase[kWave + lane] = g1;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+      }
+      if (nend > 25 && end && rank >= 25) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) bv.P[5 * sidx + k] = p[k];
+      }
       nstart += __popcll(starts);
       const int lend = (int)(ends >> 63);
 #pragma unroll
@@ -377,8 +406,7 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
       carry_valid = !lend;
     }
     *u_dst = u_out;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) p_dst[k] = g_out[k];
+    store_sums();
   }
   if (s.n_glob) {
     const double gs = wave_sum(gsum);

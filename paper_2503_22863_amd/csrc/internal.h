@@ -144,10 +144,10 @@ struct BlkView {
   double* P;            // [nseg + 1][5] astrometric sums of each segment (the last entry stays zero)
   double* Q;            // [G][3][Wb + 3] attitude window sums of each workgroup
   double* ub;           // [mp] u in this order
-  double* dummy;        // [kBlkWaves*G][72] per-wave store targets of lanes with nothing to store
+  double* dummy;        // [kBlkWaves*G][128] per-wave store targets of lanes with nothing to store
 };
 constexpr int kBlkWaves = 8;  // waves per workgroup of the regrouped pass
-constexpr int kBlkDummy = 72; // doubles per wave in BlkView::dummy: 64 for u, 8 (one 64-byte line) for P
+constexpr int kBlkDummy = 128; // doubles per wave in BlkView::dummy: 64 for u, 64 for the segment sums
 
 // LSQR epilogue arguments of the tail pass.
 struct TailLsqr {
