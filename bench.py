@@ -474,7 +474,9 @@ def main():
     g = _generate(gsr_synth, workload, args.stars)
     g_share = None if args.no_ttt else g  # the FP32 forms are timed on the same system
     out, extra = share_leg(gsr, g, args.steps, args.warmup, layout=layout, cov=args.cov, export=args.export,
-                           pairs=args.pairs, constraints=args.constraints, timed_kernels=min(args.steps, 20))
+                           pairs=args.pairs, constraints=args.constraints,
+                           # with covariances, 64 kernel-timed iterations hold one covariance flush
+                           timed_kernels=64 if (args.cov or args.pairs) else min(args.steps, 20))
     del g
     m, n, ns = out["_m"], out["_n"], out["_ns"]
     res = {
