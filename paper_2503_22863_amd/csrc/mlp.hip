@@ -133,26 +133,30 @@ __global__ void k_destandardize(const float* __restrict__ Ys, int64_t N, int C, 
   }
 }
 
-// Tiled FP32 GEMM with strided operands:
+// Tiled FP32 GEMM with strided operands, on the matrix cores:
 //   C(m, n) = sum_k A(m, k) B(k, n) [+ bias(n)] [then ReLU] [times (mask(m, n) > 0)]
 // A(m, k) = A[m*sam + k*sak], B(k, n) = B[k*sbk + n*sbn], C row-major with ldc.
-// 64 x 64 tile per 256-thread workgroup, 4 x 4 outputs per thread, K in steps
-// of 16 through LDS.  gridDim.z > 1 splits K; partial tiles are added with
-// atomics into a C cleared beforehand.
+// A 64 x 64 tile per 256-thread workgroup, K in steps of 16 through LDS; each
+// wave holds a 32 x 32 quadrant in 2 x 2 accumulators of v_mfma_f32_16x16x4f32
+// (per instruction lane l gives A(row l%16, k l/16) and B(k l/16, column l%16);
+// element r of the result is row 4 (l/16) + r, column l%16).  gridDim.z > 1
+// splits K; partial tiles are added with atomics into a C cleared beforehand.
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
   __shared__ float As[16][64 + 4];
   __shared__ float Bs[16][64 + 4];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int qi = wid >> 1, qj = wid & 1, i16 = lane & 15, grp = lane >> 4;
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
   const int splits = gridDim.z;
   const int kper = ((g.K + splits - 1) / splits + 15) / 16 * 16;
   const int kbeg = blockIdx.z * kper, kend = min(g.K, kbeg + kper);
-  float acc[4][4];
+  f4 acc[2][2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.f;
+    for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
   for (int k0 = kbeg; k0 < kend; k0 += 16) {
     // 1024 elements of each tile, 4 per thread
 #pragma unroll
@@ -166,39 +170,42 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      float a[4], b[4];
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int kk = 4 * s4 + grp;
+      float a[2], b[2];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty * 4 + i];
+      for (int i = 0; i < 2; ++i) a[i] = As[kk][32 * qi + 16 * i + i16];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx * 4 + j];
+      for (int j = 0; j < 2; ++j) b[j] = Bs[kk][32 * qj + 16 * j + i16];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(a[i], b[j], acc[i][j]);
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int gm = m0 + ty * 4 + i;
-    if (gm >= g.M) continue;
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int gn = n0 + tx * 4 + j;
-      if (gn >= g.N) continue;
-      const int64_t o = (int64_t)gm * g.ldc + gn;
-      if (splits > 1) {
-        atomicAdd(g.C + o, acc[i][j]);
-        continue;
+    for (int r = 0; r < 4; ++r) {
+      const int gm = m0 + 32 * qi + 16 * i + 4 * grp + r;
+      if (gm >= g.M) continue;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int gn = n0 + 32 * qj + 16 * j + i16;
+        if (gn >= g.N) continue;
+        const int64_t o = (int64_t)gm * g.ldc + gn;
+        if (splits > 1) {
+          atomicAdd(g.C + o, acc[i][j][r]);
+          continue;
+        }
+        float z = acc[i][j][r] + (g.bias ? g.bias[gn] : 0.f);
+        if (g.Zout) g.Zout[o] = z;
+        if (g.relu) z = fmaxf(z, 0.f);
+        if (g.mask) z = g.mask[o] > 0.f ? z : 0.f;
+        g.C[o] = z;
       }
-      float z = acc[i][j] + (g.bias ? g.bias[gn] : 0.f);
-      if (g.Zout) g.Zout[o] = z;
-      if (g.relu) z = fmaxf(z, 0.f);
-      if (g.mask) z = g.mask[o] > 0.f ? z : 0.f;
-      g.C[o] = z;
     }
-  }
 }
 
 // dY = 2 (Y - T) / (N*O) and the loss mean((Y - T)^2) (loss accumulated in FP64).
