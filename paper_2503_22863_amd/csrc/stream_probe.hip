@@ -28,12 +28,14 @@ typedef unsigned u4 __attribute__((ext_vector_type(4)));
 constexpr int kMaxChunks = 12;  // 16-byte chunks per row (24 FP64 coefficients; 6 for FP32)
 constexpr int kWaves = 8;       // waves per workgroup
 constexpr int kStage = 16;      // tiles per burst in the LDS-staged form
+constexpr int kSeg = 35;        // values per tile of the second stream (7 segment sums of 5)
 
 // Two tiles ahead: tiles in pairs, each pair's loads issued while the other
 // pair member is consumed (no register copy of loads still in flight).
 template <int CH, bool STORE>
 __global__ void __launch_bounds__(kWaves * 64) k_stream2(const u4* __restrict__ T, const u4* __restrict__ R,
-                                                          double* __restrict__ u, long ntiles, double* sink) {
+                                                          double* __restrict__ u, double* __restrict__ p, long ntiles,
+                                                          double* sink) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const long W = (long)gridDim.x * kWaves, w = (long)blockIdx.x * kWaves + wid;
   const long t0 = ntiles * w / W, t1 = ntiles * (w + 1) / W;
@@ -90,10 +92,14 @@ __global__ void __launch_bounds__(kWaves * 64) k_stream2(const u4* __restrict__ 
 
 // Store forms: 0 none, 1 plain, 2 nontemporal, 3 into a 1 MB wrap-around buffer
 // (never reaches HBM), 4 from every fourth wave only, 5 staged in LDS and
-// written kStage tiles at a time.
+// written kStage tiles at a time; with a second stream of kSeg values per tile
+// (the size of a tile's segment sums): 6 into a buffer of its own beside u,
+// 7 interleaved with u in one buffer (u of a tile, then its kSeg values), so
+// that each wave writes one sequential stream of the same bytes as in 6.
 template <int kChunks, int STORE>
 __global__ void __launch_bounds__(kWaves * 64) k_stream(const u4* __restrict__ T, const u4* __restrict__ R,
-                                                         double* __restrict__ u, long ntiles, double* sink) {
+                                                         double* __restrict__ u, double* __restrict__ p, long ntiles,
+                                                         double* sink) {
   extern __shared__ double lds[];  // sized to leave one workgroup per CU
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const long W = (long)gridDim.x * kWaves, w = (long)blockIdx.x * kWaves + wid;
@@ -128,6 +134,15 @@ __global__ void __launch_bounds__(kWaves * 64) k_stream(const u4* __restrict__ T
         if (STORE == 2) __builtin_nontemporal_store(u_out, u + r_out);
         if (STORE == 3) u[r_out & ((1 << 17) - 1)] = u_out;
         if (STORE == 4 && (w & 3) == 0) u[r_out] = u_out;
+        if (STORE == 6) {
+          u[r_out] = u_out;
+          p[lane < kSeg ? (r_out >> 6) * kSeg + lane : ntiles * kSeg + w * 64 + lane] = u_out;
+        }
+        if (STORE == 7) {
+          constexpr int kRun = 64 + kSeg;
+          p[(r_out >> 6) * kRun + lane] = u_out;
+          p[lane < kSeg ? (r_out >> 6) * kRun + 64 + lane : ntiles * kRun + w * 64 + lane] = u_out;
+        }
         if (STORE == 5) {
           double* st = lds + wid * kStage * 64;
           const long k = (t - 1 - t0) % kStage;
@@ -158,20 +173,20 @@ __global__ void __launch_bounds__(kWaves * 64) k_stream(const u4* __restrict__ T
 }
 
 template <typename K>
-static void run(K kernel, int chunks, int depth, const char* name, const u4* T, const u4* R, double* u, long ntiles,
-                double* sink, int blocks, size_t lds) {
+static void run(K kernel, int chunks, int depth, const char* name, const u4* T, const u4* R, double* u, double* p,
+                long ntiles, double* sink, int blocks, size_t lds) {
   (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   (void)hipGetLastError();
   hipEvent_t a, b;
   CHK(hipEventCreate(&a));
   CHK(hipEventCreate(&b));
   for (int i = 0; i < 2; ++i)
-    hipLaunchKernelGGL(kernel, dim3(blocks), dim3(kWaves * 64), lds, 0, T, R, u, ntiles, sink);
+    hipLaunchKernelGGL(kernel, dim3(blocks), dim3(kWaves * 64), lds, 0, T, R, u, p, ntiles, sink);
   CHK(hipGetLastError());
   const int reps = 10;
   CHK(hipEventRecord(a));
   for (int i = 0; i < reps; ++i)
-    hipLaunchKernelGGL(kernel, dim3(blocks), dim3(kWaves * 64), lds, 0, T, R, u, ntiles, sink);
+    hipLaunchKernelGGL(kernel, dim3(blocks), dim3(kWaves * 64), lds, 0, T, R, u, p, ntiles, sink);
   CHK(hipEventRecord(b));
   CHK(hipEventSynchronize(b));
   float ms = 0.0f;
@@ -197,32 +212,38 @@ int main(int argc, char** argv) {
   const size_t lds = (size_t)lmax * 3 / 4;
   if (lds < sizeof(double) * kWaves * kStage * 64) return 1;
   u4 *T, *R;
-  double *u, *sink;
+  double *u, *p, *sink;
+  const int blocks = 2 * cus;
+  const size_t pn = (size_t)ntiles * (64 + kSeg) + (size_t)blocks * kWaves * 64;  // forms 6 and 7
   CHK(hipMalloc(&T, (size_t)ntiles * 64 * kMaxChunks * 16));
   CHK(hipMalloc(&R, (size_t)ntiles * 64 * 16));
   CHK(hipMalloc(&u, (size_t)ntiles * 64 * 8));
+  CHK(hipMalloc(&p, pn * 8));
+  CHK(hipMemset(p, 0, pn * 8));
   CHK(hipMalloc(&sink, 64));
   CHK(hipMemset(T, 0, (size_t)ntiles * 64 * kMaxChunks * 16));
   CHK(hipMemset(R, 0, (size_t)ntiles * 64 * 16));
   CHK(hipMemset(u, 0, (size_t)ntiles * 64 * 8));
   CHK(hipDeviceSynchronize());
-  const int blocks = 2 * cus;
   // FP64 rows, one tile ahead, every store form
-  run(k_stream<12, 0>, 12, 1, "none", T, R, u, ntiles, sink, blocks, lds);
-  run(k_stream<12, 1>, 12, 1, "plain", T, R, u, ntiles, sink, blocks, lds);
-  run(k_stream<12, 2>, 12, 1, "nontemporal", T, R, u, ntiles, sink, blocks, lds);
-  run(k_stream<12, 3>, 12, 1, "1 MB wrap-around buffer", T, R, u, ntiles, sink, blocks, lds);
-  run(k_stream<12, 4>, 12, 1, "every fourth wave only", T, R, u, ntiles, sink, blocks, lds);
-  run(k_stream<12, 5>, 12, 1, "LDS-staged, 16 tiles per burst", T, R, u, ntiles, sink, blocks, lds);
+  run(k_stream<12, 0>, 12, 1, "none", T, R, u, p, ntiles, sink, blocks, lds);
+  run(k_stream<12, 1>, 12, 1, "plain", T, R, u, p, ntiles, sink, blocks, lds);
+  run(k_stream<12, 2>, 12, 1, "nontemporal", T, R, u, p, ntiles, sink, blocks, lds);
+  run(k_stream<12, 3>, 12, 1, "1 MB wrap-around buffer", T, R, u, p, ntiles, sink, blocks, lds);
+  run(k_stream<12, 4>, 12, 1, "every fourth wave only", T, R, u, p, ntiles, sink, blocks, lds);
+  run(k_stream<12, 5>, 12, 1, "LDS-staged, 16 tiles per burst", T, R, u, p, ntiles, sink, blocks, lds);
+  run(k_stream<12, 6>, 12, 1, "u + 35 values per tile, two streams", T, R, u, p, ntiles, sink, blocks, lds);
+  run(k_stream<12, 7>, 12, 1, "u + 35 values per tile, one merged stream", T, R, u, p, ntiles, sink, blocks, lds);
   // two tiles ahead; FP32 rows one and two tiles ahead
-  run(k_stream2<12, true>, 12, 2, "plain", T, R, u, ntiles, sink, blocks, lds);
-  run(k_stream<6, 0>, 6, 1, "none", T, R, u, ntiles, sink, blocks, lds);
-  run(k_stream<6, 1>, 6, 1, "plain", T, R, u, ntiles, sink, blocks, lds);
-  run(k_stream2<6, false>, 6, 2, "none", T, R, u, ntiles, sink, blocks, lds);
-  run(k_stream2<6, true>, 6, 2, "plain", T, R, u, ntiles, sink, blocks, lds);
+  run(k_stream2<12, true>, 12, 2, "plain", T, R, u, p, ntiles, sink, blocks, lds);
+  run(k_stream<6, 0>, 6, 1, "none", T, R, u, p, ntiles, sink, blocks, lds);
+  run(k_stream<6, 1>, 6, 1, "plain", T, R, u, p, ntiles, sink, blocks, lds);
+  run(k_stream2<6, false>, 6, 2, "none", T, R, u, p, ntiles, sink, blocks, lds);
+  run(k_stream2<6, true>, 6, 2, "plain", T, R, u, p, ntiles, sink, blocks, lds);
   CHK(hipFree(T));
   CHK(hipFree(R));
   CHK(hipFree(u));
+  CHK(hipFree(p));
   CHK(hipFree(sink));
   return 0;
 }
