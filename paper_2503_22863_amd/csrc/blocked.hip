@@ -390,7 +390,7 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
         pn = nend;
         if (nend > 12) {
           const double g1 = cl[kWave + lane];
-          if (kWave + lane < 5 * nend) pbase[kWave + lane] = g1;
+          if (kWave + lane < 5 * min(nend, 25)) pbase[kWave + lane] = g1;  // ranks past 24 store their own
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
