@@ -11,7 +11,13 @@ every output is compared, not a sample:
     (tests/_checks.py);
   * five column-scaled LSQR iterations and two unscaled ones, x and the
     variances per block at max(1e-13, 10 s), s the oracle's own response to
-    last-bit perturbations."""
+    last-bit perturbations;
+  * the FP32 forms bench.py times, on FP32 values placed by the caller: the
+    one-pass product with FP32 products against the oracle's FP32-product
+    emulation and with FP64 products (exact upcasts) against the plain oracle,
+    at the same bars, and five column-scaled LSQR iterations with FP32
+    products against the oracle's one-pass FP32-product LSQR (the same
+    operand rounded: fl32 of the unnormalised u')."""
 import numpy as np
 import pytest
 import torch
@@ -120,3 +126,56 @@ def test_full_share_lsqr_iterations(oracle_lib, share, precond, it):
         assert abs(r[k] - ref[k]) <= max(1e-13, 10 * sens[k]) * abs(ref[k]), k
     info = S.blocked_info()
     assert info["active"] == 1 and info["values_owned"] == 0  # the configuration bench.py times
+
+
+@pytest.fixture(scope="module")
+def share32(oracle_lib, share):
+    import paper_2503_22863_amd as gsr
+
+    g = share[0].as_f32()
+    print("[full fp32] packing the FP32 rows in the regrouped order", flush=True)
+    S = gsr.System.packed_from_generated(g)
+    yield g, oracle_lib.OSystem(g), abs_system(oracle_lib, g), S
+    S.close()
+
+
+@pytest.mark.timeout(600)
+def test_full_share_fp32_one_pass_product(oracle_lib, share32):
+    """FP32 values: u' = s_u u + A v and x' = A^T u' in one pass, with FP32 products
+    (each formed in FP32 from fl32 operands, sums in FP64) and with FP64 products."""
+    g, o, oa, S = share32
+    d = g.dims
+    rng = np.random.default_rng(59)
+    v, u0 = rng.standard_normal(d.n), rng.standard_normal(d.m)
+    for product, mode in (("f32", oracle_lib.P32), ("f64", oracle_lib.P64)):
+        print(f"[full fp32] one-pass product, {product} products", flush=True)
+        u = torch.from_numpy(u0).cuda()
+        _, xg = S.aprod12(torch.from_numpy(v).cuda(), u, scale_u=-0.5, product=product)
+        u_gpu, x_gpu = u.cpu().numpy(), xg.cpu().numpy()
+        del u, xg
+        check_aprod1(oracle_lib, o, oa, v, u0, -0.5, u_gpu, f"{product} products", mode=mode)
+        check_aprod2(oracle_lib, g, o, oa, u_gpu, np.zeros(d.n), 0.0, x_gpu,
+                     f"{product} products (on the GPU's u')", mode=mode)
+
+
+@pytest.mark.timeout(900)
+def test_full_share_fp32_lsqr_iterations(oracle_lib, share32):
+    """Five column-scaled LSQR iterations with FP32 products (the inner solves of
+    the refinement bench.py times) against the oracle's one-pass FP32-product LSQR."""
+    g, o, _, S = share32
+    d = g.dims
+    b = oracle_lib.known_terms(o, g.x_true, g.noise)
+    it = 5
+    print(f"[full fp32] {it} LSQR iterations with FP32 products on the GPU", flush=True)
+    x, var, r = S.lsqr_solve(torch.from_numpy(b).cuda(), atol=0, btol=0, itmax=it, precond=True, product="f32")
+    assert r["itn"] == it
+    print(f"[full fp32] {it} oracle LSQR iterations (one-pass FP32 products), and six with b perturbed",
+          flush=True)
+    ref, sens = sensitivity(oracle_lib, g, o, b, nruns_b=6, atol=0, btol=0, itmax=it, precond=True,
+                            mode=oracle_lib.P32_1P)
+    x, var = x.cpu().numpy(), var.cpu().numpy()
+    for name, sl in blocks(d).items():
+        ex, ev = rel(x[sl], ref["x"][sl]), rel(var[sl], ref["var"][sl])
+        bx, bv = max(1e-13, 10 * sens[("x", name)]), max(1e-13, 10 * sens[("var", name)])
+        print(f"  {name}: x {ex:.2e} (bar {bx:.1e}) var {ev:.2e} (bar {bv:.1e})", flush=True)
+        assert ex <= bx and ev <= bv, name
