@@ -11,10 +11,12 @@ library holds no copy of A.
 
 Prints one JSON line: iterations/s (graph replay on, as shipped), the
 roofline of the dominant kernel (HIP events around every kernel over a
-separate run of iterations right after the timed region), the same for the
-3e6-star share with the covariances of 4,000 unknowns, the time to 1e-10 of
-the FP32 forms and of the warm start, and the CPU oracle timed on a bounded
-sample of the same workload.
+separate run of iterations right after the timed region; besides the HBM
+peak, its rate against the memory probe's stream of the same reads with the
+pass's two write streams, measured first in a child process), the same for
+the 3e6-star share with the covariances of 4,000 unknowns, the time to 1e-10
+of the FP32 forms and of the warm start, and the CPU oracle timed on a
+bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -388,6 +390,41 @@ def syrk_bench(gsr, k=4000, reps=20):
     return {"metric": "covariance SYRK FP64 MFMA rate", "unit": "TFLOP/s", "peak": 78.6, "results": rows}
 
 
+def stream_probe_rows():
+    """Rows of the memory-system probe (csrc/stream_probe.hip), run as a child process
+    of its own; None if it is not built."""
+    import subprocess
+
+    probe = os.path.join(ROOT, "paper_2503_22863_amd", "stream_probe")
+    if not os.path.exists(probe):
+        return None
+    r = subprocess.run([probe], capture_output=True, text=True, timeout=600)
+    if r.returncode != 0:
+        raise SystemExit(f"stream_probe failed ({r.returncode}): {r.stderr.strip()}")
+    return [json.loads(line) for line in r.stdout.splitlines() if line.startswith("{")]
+
+
+def _attach_floor(roof, floor):
+    """The row pass's rate against the probe's two-stream floor (FP64 rows only)."""
+    if floor and roof.get("kernel") == "k_fblk" and roof.get("bytes_per_launch"):
+        roof["probe_floor"] = floor
+        roof["frac_of_probe_floor"] = roof["achieved"] / floor["GBps"]
+
+
+def two_stream_floor(rows):
+    """The probe's FP64 form with both of the row pass's write streams (u, and 35
+    values per 64-row tile: a tile's segment sums), as bytes read + written per
+    second."""
+    if not rows:
+        return None
+    r = next((x for x in rows if x["chunks"] == 12 and x["store"].endswith("two streams")), None)
+    if r is None:
+        return None
+    n, tiles = r["rows"], (r["rows"] + 63) // 64
+    by = n * (12 * 16 + 16 + 8) + n * 8 + tiles * 35 * 8
+    return {"form": r["store"], "rows": n, "ms": r["ms"], "GBps": by / (r["ms"] * 1e-3) / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -432,18 +469,15 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     if args.stream_probe:
-        # a child process of its own, started before this one touches the GPU
-        import subprocess
-
-        probe = os.path.join(ROOT, "paper_2503_22863_amd", "stream_probe")
-        if not os.path.exists(probe):
+        rows = stream_probe_rows()
+        if rows is None:
             raise SystemExit("stream_probe is not built (run the package build first)")
-        r = subprocess.run([probe], capture_output=True, text=True, timeout=600)
-        if r.returncode != 0:
-            raise SystemExit(f"stream_probe failed ({r.returncode}): {r.stderr.strip()}")
-        rows = [json.loads(line) for line in r.stdout.splitlines() if line.startswith("{")]
         print(json.dumps({"stream_probe": rows}), flush=True)
         return
+    # the row pass's own memory floor on this chip, measured before this process
+    # touches the GPU: the probe's stream of the same reads with u and a
+    # segment-sized second store stream
+    probe_floor = None if args.aprods or args.syrk_bench else two_stream_floor(stream_probe_rows())
 
     import numpy as np
     import torch
@@ -498,6 +532,7 @@ def main():
         "row_layout": out["row_layout"],
     }
     res.update(extra)
+    _attach_floor(res["roofline"], probe_floor)
     if "covariances" in out:
         res["covariances"] = out["covariances"]
     if not args.no_large and workload == "share_1m" and args.stars == 1_000_000 and layout == "packed":
@@ -508,6 +543,7 @@ def main():
         o3, _ = share_leg(gsr, g3, 64, 64, layout="packed", cov=4000, timed_kernels=64)
         del g3
         res["share_3m_cov4000"] = {k: v for k, v in o3.items() if not k.startswith("_")}
+        _attach_floor(res["share_3m_cov4000"]["roofline"], probe_floor)
     if not args.no_ttt:
         import gsr_synth as _gs
 
