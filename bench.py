@@ -130,7 +130,7 @@ def _usable_cores() -> int:
         n = len(os.sched_getaffinity(0))
     except (AttributeError, OSError):
         n = os.cpu_count() or 1
-    return max(1, min(n, 16))  # at most the machine's CPU share for one GPU
+    return max(1, min(n, 16))  # at most 16 threads: the host cores that go with one GPU
 
 
 def cpu_baseline(full_m: int, budget_s: float = 12.0):
