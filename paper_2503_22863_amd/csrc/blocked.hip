@@ -126,8 +126,8 @@ __global__ void k_blk_unpermute(BlkView bv, double* __restrict__ dst) {
 // each term a^2 in FP64), for the column norms of the preconditioner.
 template <typename VT, int PM, int SQ>
 __global__ void __launch_bounds__(kBlkThreads) __attribute__((amdgpu_waves_per_eu(2)))
-k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __restrict__ x3,
-       const float* __restrict__ x3f, double* __restrict__ acc, Scalars* sc, Work wk, int init) {
+k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __restrict__ xr,
+       const float* __restrict__ xrf, double* __restrict__ acc, Scalars* sc, Work wk, int init) {
   constexpr int CPR = Geo<VT>::CPR;
   __shared__ dd2u rg[kBlkWaves][(kWave / 2) * 7];
   __shared__ double red[kBlkWaves];
@@ -147,8 +147,8 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
   __syncthreads();
 
   const int64_t g = bv.wg_block[blockIdx.x];
-  const double* xw = x3 + 3 * g * bv.Wb;  // interleaved x of the block's window
-  const float* xwf = x3f + 3 * g * bv.Wb;  // the same rounded to FP32 (FP32 products only)
+  const double* xw = xr + kAttRec * g * bv.Wb;   // window records of the block's starts
+  const float* xwf = xrf + kAttRec * g * bv.Wb;  // the same rounded to FP32 (FP32 products only)
   const int64_t w = (int64_t)blockIdx.x * kBlkWaves + wid;
   const int64_t T0 = bv.wave_tile[w], T1 = bv.wave_tile[w + 1];
   double sumsq = 0.0, gsum = 0.0;
@@ -171,13 +171,13 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
     };
     // x for the tile whose record is in `rec`: the astrometric x of the 12.8
     // stars from its first (one contiguous load, shuffled per row later) and
-    // its 64 attitude windows of 96 bytes, loaded cooperatively (piece
-    // j*64 + lane of the tile's windows in cw[j]; consecutive lanes take
-    // consecutive 16-byte pieces of one window) and regrouped through LDS.
-    // Issued a tile ahead, in the middle of the previous tile.  With FP32
-    // products the windows come from the FP32 copy: 48 bytes each, 3 pieces
-    // of 16 bytes (the products round x to FP32 anyway, so the arithmetic is
-    // the same).
+    // its 64 attitude windows of 96 bytes, each the first 96 bytes of one
+    // 128-byte record line, loaded cooperatively (piece j*64 + lane of the
+    // tile's windows in cw[j]; consecutive lanes take consecutive 16-byte
+    // pieces of one window) and regrouped through LDS.  Issued a tile ahead,
+    // in the middle of the previous tile.  With FP32 products the windows come
+    // from the FP32 records: 48 bytes each, 3 pieces of 16 bytes (the products
+    // round x to FP32 anyway, so the arithmetic is the same).
     constexpr int NP = PM == 1 ? 3 : 6;  // 16-byte pieces per window
     double xs, xs2;
     dd2u cw[NP];
@@ -191,10 +191,10 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
         const int c = j * kWave + lane, i = c / NP, q = c - NP * i;
         const int ao = __shfl(ao_l, i, kWave);
         if constexpr (PM == 1) {
-          const f4u v = *reinterpret_cast<const f4u*>(xwf + 3 * ao + 4 * q);
+          const f4u v = *reinterpret_cast<const f4u*>(xwf + kAttRec * ao + 4 * q);
           __builtin_memcpy(&cw[j], &v, sizeof v);
         } else {
-          cw[j] = *reinterpret_cast<const dd2u*>(xw + 3 * ao + 2 * q);
+          cw[j] = *reinterpret_cast<const dd2u*>(xw + kAttRec * ao + 2 * q);
         }
       }
     };
@@ -430,23 +430,23 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
   }
 }
 
-hipError_t launch_fblk(const SysView& s, const BlkView& bv, int pmode, const double* vg, const double* x3,
-                       const float* x3f, double* acc, Scalars* sc, Work w, hipStream_t st, int init, int square) {
+hipError_t launch_fblk(const SysView& s, const BlkView& bv, int pmode, const double* vg, const double* xr,
+                       const float* xrf, double* acc, Scalars* sc, Work w, hipStream_t st, int init, int square) {
   if (!bv.ready || bv.G < 1 || bv.G > kMaxPartials) return hipErrorInvalidValue;
-  if (pmode == 1 && (s.value_type != GSR_F32 || x3f == nullptr)) return hipErrorInvalidValue;
+  if (xr == nullptr || (pmode == 1 && (s.value_type != GSR_F32 || xrf == nullptr))) return hipErrorInvalidValue;
   const dim3 g(bv.G), b(kBlkThreads);
   if (square) {
     if (pmode != 0) return hipErrorInvalidValue;
     if (s.value_type == GSR_F32)
-      hipLaunchKernelGGL((k_fblk<float, 0, 1>), g, b, bv.lds, st, s, bv, vg, x3, x3f, acc, sc, w, init);
+      hipLaunchKernelGGL((k_fblk<float, 0, 1>), g, b, bv.lds, st, s, bv, vg, xr, xrf, acc, sc, w, init);
     else
-      hipLaunchKernelGGL((k_fblk<double, 0, 1>), g, b, bv.lds, st, s, bv, vg, x3, x3f, acc, sc, w, init);
+      hipLaunchKernelGGL((k_fblk<double, 0, 1>), g, b, bv.lds, st, s, bv, vg, xr, xrf, acc, sc, w, init);
   } else if (s.value_type == GSR_F32 && pmode == 1) {
-    hipLaunchKernelGGL((k_fblk<float, 1, 0>), g, b, bv.lds, st, s, bv, vg, x3, x3f, acc, sc, w, init);
+    hipLaunchKernelGGL((k_fblk<float, 1, 0>), g, b, bv.lds, st, s, bv, vg, xr, xrf, acc, sc, w, init);
   } else if (s.value_type == GSR_F32) {
-    hipLaunchKernelGGL((k_fblk<float, 0, 0>), g, b, bv.lds, st, s, bv, vg, x3, x3f, acc, sc, w, init);
+    hipLaunchKernelGGL((k_fblk<float, 0, 0>), g, b, bv.lds, st, s, bv, vg, xr, xrf, acc, sc, w, init);
   } else {
-    hipLaunchKernelGGL((k_fblk<double, 0, 0>), g, b, bv.lds, st, s, bv, vg, x3, x3f, acc, sc, w, init);
+    hipLaunchKernelGGL((k_fblk<double, 0, 0>), g, b, bv.lds, st, s, bv, vg, xr, xrf, acc, sc, w, init);
   }
   return hipGetLastError();
 }

@@ -69,7 +69,8 @@ struct gsr_system {
   double *u = nullptr, *v = nullptr, *vg = nullptr, *w = nullptr, *y = nullptr, *var = nullptr;
   double* gA = nullptr;  // raw astrometric sums of the fused iteration pass
   double* x3 = nullptr;  // attitude part of vg, axes interleaved, for the fused pass
-  float* x3f = nullptr;  // the same rounded to FP32, for the regrouped pass with FP32 products
+  double* awr = nullptr;  // attitude window records of vg [n_att][kAttRec], for the regrouped pass
+  float* awrf = nullptr;  // the same rounded to FP32, for the regrouped pass with FP32 products
   double* x3a = nullptr;  // the attitude part of aprod 1's x, axes interleaved (aprod 1's workspace)
   void* rix = nullptr;   // packed row indices for the fused pass (16 B per row); null: no fused pass
   int fused = 1;         // one pass over the rows per iteration (FP64 products, attitude mode 0 or 3)
@@ -253,7 +254,8 @@ static void release(gsr_system* s) {
   for (hipEvent_t e : {s->eev[0], s->eev[1], s->efill})
     if (e) (void)hipEventDestroy(e);
   dfree(s->x3);
-  dfree(s->x3f);
+  dfree(s->awr);
+  dfree(s->awrf);
   dfree(s->x3a);
   dfree(s->rix);
   dfree(s->xr);
@@ -719,9 +721,9 @@ static int ensure_blk(gsr_system* s, hipStream_t st) {
 
 // Work vectors of the standalone passes over the regrouped rows.
 static int ensure_blk_vectors(gsr_system* s, int32_t product, hipStream_t st) {
-  const size_t n3 = (size_t)std::max<int64_t>(3 * s->s.n_att, 1);
-  if (!s->x3) CHK(dalloc(&s->x3, n3));
-  if (product == GSR_PROD_F32 && !s->x3f) CHK(dalloc(&s->x3f, n3));
+  const size_t nr = (size_t)std::max<int64_t>(kAttRec * s->s.n_att, 1);
+  if (!s->awr) CHK(dalloc(&s->awr, nr));
+  if (product == GSR_PROD_F32 && !s->awrf) CHK(dalloc(&s->awrf, nr));
   if (!s->gA) CHK(dalloc(&s->gA, (size_t)std::max<int64_t>(s->s.n_astro, 1)));
   if (!s->zvec) {
     CHK(dalloc(&s->zvec, (size_t)s->s.n));
@@ -752,9 +754,9 @@ static int blk_products(gsr_system* s, const double* v, const double* u_in, doub
     HIPCHK(launch_blk_permute(bv, u_in, st));
   else
     su = 0.0;
-  HIPCHK(launch_att_interleave(s->s, v, s->x3, st, product == GSR_PROD_F32 ? s->x3f : nullptr));
+  HIPCHK(launch_att_records(s->s, v, s->awr, st, product == GSR_PROD_F32 ? s->awrf : nullptr));
   HIPCHK(launch_raw_scalars(s->psc, su, sx, st));
-  HIPCHK(launch_fblk(s->s, bv, square ? GSR_PROD_F64 : product, v, s->x3, s->x3f, s->acc, s->psc, s->wk, st, 0,
+  HIPCHK(launch_fblk(s->s, bv, square ? GSR_PROD_F64 : product, v, s->awr, s->awrf, s->acc, s->psc, s->wk, st, 0,
                      square));
   if (want_t || square) {
     HIPCHK(launch_tail_seg(s->s, bv, x, s->acc, nullptr, s->psc, s->wk, st, 1));
@@ -963,8 +965,13 @@ static int blk_applies(const gsr_system* s) {
          s->s.n_instr + 1 <= kLdsTailMax;
 }
 
-// The FP32 copy of the interleaved attitude x that the regrouped pass reads with FP32 products.
-static float* x3f_for(const gsr_system* s) { return s->use_blk && s->pmode == GSR_PROD_F32 ? s->x3f : nullptr; }
+// The attitude x that the next row pass reads: window records for the regrouped
+// pass (and their FP32 rounding with FP32 products), the interleaved copy for the
+// star-order fused pass.
+static hipError_t att_copy_for_pass(gsr_system* s, const double* v, hipStream_t st) {
+  if (s->use_blk) return launch_att_records(s->s, v, s->awr, st, s->pmode == GSR_PROD_F32 ? s->awrf : nullptr);
+  return launch_att_interleave(s->s, v, s->x3, st);
+}
 
 // fold_r0: on the regrouped copy, form r0 = b - A x0 inside the first pass
 // (u' = u + A vg with vg = -x0, FP64 products) instead of by a separate aprod 1;
@@ -993,8 +1000,11 @@ static int lsqr_begin(gsr_system* s, const double* b, const double* x0, const gs
     s->use_blk = s->blk.ready;
   }
   if (!s->use_blk) CHK(ensure_att(s, st));
-  if (s->use_blk && product == GSR_PROD_F32 && !s->x3f)
-    CHK(dalloc(&s->x3f, (size_t)std::max<int64_t>(3 * s->s.n_att, 1)));
+  if (s->use_blk) {
+    const size_t nr = (size_t)std::max<int64_t>(kAttRec * s->s.n_att, 1);
+    if (!s->awr) CHK(dalloc(&s->awr, nr));
+    if (product == GSR_PROD_F32 && !s->awrf) CHK(dalloc(&s->awrf, nr));
+  }
   if (s->con.ncon > 0 && !s->use_blk && !fused_for(s, product))
     return fail(GSR_EINVAL, "constraint equations need the fused iteration (no memory for the regrouped copy "
                             "and no bucketed attitude view)");
@@ -1059,10 +1069,10 @@ static int lsqr_begin(gsr_system* s, const double* b, const double* x0, const gs
     } else {
       HIPCHK(launch_blk_permute(s->blk, x0 ? s->u : b, st));
     }
-    HIPCHK(launch_att_interleave(s->s, vg0, s->x3, st, pm0 == GSR_PROD_F32 ? s->x3f : nullptr));
+    HIPCHK(launch_att_records(s->s, vg0, s->awr, st, pm0 == GSR_PROD_F32 ? s->awrf : nullptr));
     // constraint rows of u stay after the m rows of s->u (uc)
     if (s->con.ncon > 0) HIPCHK(launch_con_aprod1(s->con, s->zvec, uc, 0.0, 1.0, s->sc, s->wk, st));
-    HIPCHK(launch_fblk(s->s, s->blk, pm0, vg0, s->x3, s->x3f, s->acc, s->sc, s->wk, st, 1));
+    HIPCHK(launch_fblk(s->s, s->blk, pm0, vg0, s->awr, s->awrf, s->acc, s->sc, s->wk, st, 1));
     if (s->con.ncon > 0) {
       HIPCHK(launch_seg_reduce(s->s, s->blk, s->gA, s->sc, st));
       HIPCHK(launch_con_aprod2(s->con, s->s.n_astro, uc, s->gA, s->acc, s->sc, st));
@@ -1096,8 +1106,7 @@ static int lsqr_begin(gsr_system* s, const double* b, const double* x0, const gs
     CHK(aprod2_launches(s, s->u, s->v, S, 0.0, product, 0, s->sc, 0, st));
   }
   HIPCHK(launch_init_vectors(s->s.n, s->v, s->vg, s->w, s->y, s->var, S, s->sc, st));
-  if (s->use_blk || iteration_fused(s))
-    HIPCHK(launch_att_interleave(s->s, o->precond ? s->vg : s->v, s->x3, st, x3f_for(s)));
+  if (s->use_blk || iteration_fused(s)) HIPCHK(att_copy_for_pass(s, o->precond ? s->vg : s->v, st));
   s->in_session = 1;
   return GSR_OK;
 }
@@ -1150,7 +1159,7 @@ static int enqueue_iteration(gsr_system* s, hipStream_t st) {
     }
     {
       TimeScope ts(s, 0, st);
-      HIPCHK(launch_fblk(s->s, s->blk, s->pmode, vg, s->x3, s->x3f, s->acc, s->sc, s->wk, st));
+      HIPCHK(launch_fblk(s->s, s->blk, s->pmode, vg, s->awr, s->awrf, s->acc, s->sc, s->wk, st));
     }
     if (s->con.ncon > 0) {
       // the constraint rows add into the raw sums between the segment reduction and the tail
@@ -1204,7 +1213,7 @@ static int enqueue_iteration(gsr_system* s, hipStream_t st) {
     TimeScope ts(s, 3, st);
     HIPCHK(launch_update(s->s.n, s->v, vg, s->w, s->y, s->var, S, s->sc, s->wk, st, s->eblock ? s->ering : nullptr,
                          s->eblock ? s->eblock : 1));
-    if (s->use_blk || iteration_fused(s)) HIPCHK(launch_att_interleave(s->s, vg, s->x3, st, x3f_for(s)));
+    if (s->use_blk || iteration_fused(s)) HIPCHK(att_copy_for_pass(s, vg, st));
   }
   s->enq += 1;
   if (s->nsel > 0 && s->enq % s->dblock == 0) {

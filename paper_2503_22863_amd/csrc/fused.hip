@@ -37,14 +37,30 @@ __global__ void k_pack_rows(SysView s, u4* __restrict__ rix) {
 // x3[3c + a] = x[n_astro + a*n_att + c]: the attitude unknowns with the three
 // axes interleaved, so that the 12 attitude unknowns of a row (4 consecutive
 // columns on each axis) are 96 contiguous bytes.
-__global__ void k_att_interleave(SysView s, const double* __restrict__ x, double* __restrict__ x3,
-                                 float* __restrict__ x3f) {
+__global__ void k_att_interleave(SysView s, const double* __restrict__ x, double* __restrict__ x3) {
   const int64_t n3 = 3 * s.n_att;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n3; e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t c = e / 3, axs = e - 3 * c;
     const double v = x[s.n_astro + axs * s.n_att + c];
     x3[e] = v;
-    if (x3f) x3f[e] = (float)v;
+  }
+}
+
+// Window records for the regrouped pass: record a holds the 12 attitude x of
+// starts a .. a+3 (element 3j + axis: axis `axis` at start a+j), padded to
+// kAttRec = 16 values, so that the window a row reads is one 128-byte cache
+// line (64 bytes in the FP32 copy) instead of 96 bytes at a 24-byte stride,
+// which straddles two lines for 11 of every 16 starts.  Written once per
+// iteration (16 n_att values).
+__global__ void k_att_records(SysView s, const double* __restrict__ x, double* __restrict__ xr,
+                              float* __restrict__ xrf) {
+  const int64_t nr = kAttRec * s.n_att;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nr; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t a = e / kAttRec;
+    const int k = (int)(e - a * kAttRec), j = k / 3, axs = k - 3 * j;
+    const double v = (k < 12 && a + j < s.n_att) ? x[s.n_astro + axs * s.n_att + a + j] : 0.0;
+    xr[e] = v;
+    if (xrf) xrf[e] = (float)v;
   }
 }
 
@@ -304,11 +320,19 @@ hipError_t launch_pack_rows(const SysView& s, void* rix, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_att_interleave(const SysView& s, const double* x, double* x3, hipStream_t st, float* x3f) {
+hipError_t launch_att_records(const SysView& s, const double* x, double* xr, hipStream_t st, float* xrf) {
+  const int64_t nr = kAttRec * s.n_att;
+  if (nr == 0) return hipSuccess;
+  const int blocks = (int)std::min<int64_t>(2048, (nr + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_att_records, dim3(blocks), dim3(kBlock), 0, st, s, x, xr, xrf);
+  return hipGetLastError();
+}
+
+hipError_t launch_att_interleave(const SysView& s, const double* x, double* x3, hipStream_t st) {
   const int64_t n3 = 3 * s.n_att;
   if (n3 == 0) return hipSuccess;
   const int blocks = (int)std::min<int64_t>(1024, (n3 + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_att_interleave, dim3(blocks), dim3(kBlock), 0, st, s, x, x3, x3f);
+  hipLaunchKernelGGL(k_att_interleave, dim3(blocks), dim3(kBlock), 0, st, s, x, x3);
   return hipGetLastError();
 }
 

@@ -215,8 +215,12 @@ hipError_t launch_fused(const SysView& s, StreamShape sh, int att_mode, int pmod
 // rix[r] <- {att_start[r], instr_col[r][0..5] as 16-bit pairs} (16 bytes per row; needs n_instr <= 65536)
 hipError_t launch_pack_rows(const SysView& s, void* rix, hipStream_t st);
 // x3 <- attitude part of x with the three axes interleaved (the fused pass's copy of vg)
-hipError_t launch_att_interleave(const SysView& s, const double* x, double* x3, hipStream_t st,
-                                 float* x3f = nullptr);
+hipError_t launch_att_interleave(const SysView& s, const double* x, double* x3, hipStream_t st);
+// Values per attitude window record of the regrouped pass (12 used: 4 starts x 3 axes).
+constexpr int kAttRec = 16;
+// xr [n_att][kAttRec] <- the attitude window of every start (the regrouped pass's copy of
+// vg), and the same rounded to FP32 into xrf when it is not null
+hipError_t launch_att_records(const SysView& s, const double* x, double* xr, hipStream_t st, float* xrf = nullptr);
 // Tail of the fused iteration: every column x_j <- v_scale*x_j + S_j * raw_j / beta (raw_j from gA, acc
 // or the attitude windows), then alpha_{i+1} and the rotations, as launch_tail.
 hipError_t launch_tail_fused(const SysView& s, const AttView& av, int att_mode, double* x, double* acc,
@@ -254,10 +258,11 @@ hipError_t launch_blk_permute(const BlkView& bv, const double* src, hipStream_t 
 // dst (rows in the caller's order) <- ub
 hipError_t launch_blk_unpermute(const BlkView& bv, double* dst, hipStream_t st);
 // The iteration's pass as launch_fused, on the regrouped copy (u in bv.ub).
-// x3f: the interleaved attitude x rounded to FP32, required with pmode 1.
+// xr / xrf: the attitude window records of vg (launch_att_records) and their FP32
+// rounding, the latter required with pmode 1.
 // square = 1: column sums of squares (pmode 0; u taken as 1, the sums as for A^T u).
-hipError_t launch_fblk(const SysView& s, const BlkView& bv, int pmode, const double* vg, const double* x3,
-                       const float* x3f, double* acc, Scalars* sc, Work w, hipStream_t st, int init = 0,
+hipError_t launch_fblk(const SysView& s, const BlkView& bv, int pmode, const double* vg, const double* xr,
+                       const float* xrf, double* acc, Scalars* sc, Work w, hipStream_t st, int init = 0,
                        int square = 0);
 // Covariance column of the iteration: D[p][dcount] = w[sel[p]] / rho_i for p < nsel (after the tail);
 // the last workgroup advances dcount.  Skipped once the solve has stopped or the block is full.
