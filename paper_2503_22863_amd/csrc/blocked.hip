@@ -116,7 +116,16 @@ __global__ void k_blk_unpermute(BlkView bv, double* __restrict__ dst) {
     dst[r] = bv.ub[bv.ipos[r]];
 }
 
-// The iteration's pass.  Workgroup b streams tiles of block wg_block[b]; its
+// Logical workgroup of physical workgroup b out of G.  Workgroups are dispatched
+// to the chip's 8 XCDs round-robin (b on XCD b % 8); numbering them so that XCD x
+// takes a contiguous eighth of the logical workgroups (which run in tile order)
+// keeps each XCD's L2 on the attitude window records of about one block.
+__device__ __forceinline__ int64_t xcd_logical(int64_t b, int64_t G) {
+  const int64_t q = G / 8, r = G % 8, x = b % 8;
+  return x * q + min<int64_t>(x, r) + b / 8;
+}
+
+// The iteration's pass.  Logical workgroup b streams tiles of block wg_block[b]; its
 // waves take consecutive sub-ranges.  Per tile a wave waits for the tile's
 // record, chunks and u (loaded one tile ahead) and for its x gathers (issued
 // during the previous tile), issues the next tile's loads, forms A x, issues
@@ -146,10 +155,11 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
   for (int64_t j = threadIdx.x; j < s.n_instr; j += kBlkThreads) xil[j] = x[NI + j];
   __syncthreads();
 
-  const int64_t g = bv.wg_block[blockIdx.x];
+  const int64_t lb = xcd_logical(blockIdx.x, gridDim.x);
+  const int64_t g = bv.wg_block[lb];
   const double* xw = xr + kAttRec * g * bv.Wb;   // window records of the block's starts
   const float* xwf = xrf + kAttRec * g * bv.Wb;  // the same rounded to FP32 (FP32 products only)
-  const int64_t w = (int64_t)blockIdx.x * kBlkWaves + wid;
+  const int64_t w = lb * kBlkWaves + wid;
   const int64_t T0 = bv.wave_tile[w], T1 = bv.wave_tile[w + 1];
   double sumsq = 0.0, gsum = 0.0;
   if (T0 < T1) {
@@ -413,7 +423,7 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
     if (lane == 0) atomicAdd(tl + s.n_instr, gs);
   }
   __syncthreads();
-  double* q = bv.Q + (int64_t)blockIdx.x * 3 * W3;
+  double* q = bv.Q + lb * 3 * W3;
   for (int64_t k = threadIdx.x; k < 3 * W3; k += kBlkThreads) q[k] = win[k];
   for (int64_t j = threadIdx.x; j < ntl; j += kBlkThreads) {
     const double v = tl[j];
