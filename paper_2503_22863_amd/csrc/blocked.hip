@@ -589,27 +589,71 @@ int blk_plan(const SysView& s, BlkView* bv, int cus, int max_window, int lds_max
   }
   const int64_t nseg = (int64_t)seg_star.size();
   bv->nseg = nseg;
-  // per group of 64 stars: entry i, lane l = id of star 64g+l's i-th segment (in
-  // block order, since segments are numbered block-major), padded with nseg
-  std::vector<int32_t> nper((size_t)S, 0);
-  for (int64_t q = 0; q < nseg; ++q) ++nper[(size_t)seg_star[(size_t)q]];
+  // Per group of 64 stars, the segment ids of its stars as entries [column][lane]
+  // (lane l: star 64g+l), aligned by window: one column per window that some star
+  // of the group has rows in (in window order), then columns for a star's second
+  // and later segments inside one window (a wave boundary inside the star's rows);
+  // empty slots hold nseg (the zero entry of P).  Neighbouring stars' segments in
+  // one window are consecutive in P, so each column's loads are contiguous.
+  std::vector<int32_t> seg_blk((size_t)nseg);
+  for (int64_t w = 0; w < W; ++w) {
+    const int64_t q1 = w + 1 < W ? seg_base[(size_t)w + 1] : nseg;
+    for (int64_t q = seg_base[(size_t)w]; q < q1; ++q) seg_blk[(size_t)q] = wg_block[(size_t)(w / kBlkWaves)];
+  }
+  // each star's segments in id order (window order: ids are numbered block-major)
+  std::vector<int64_t> sptr((size_t)S + 1, 0);
+  for (int64_t q = 0; q < nseg; ++q) ++sptr[(size_t)seg_star[(size_t)q] + 1];
+  for (int64_t st_ = 0; st_ < S; ++st_) sptr[(size_t)st_ + 1] += sptr[(size_t)st_];
+  std::vector<int32_t> ssegs((size_t)std::max<int64_t>(nseg, 1));
+  {
+    std::vector<int64_t> fill(sptr.begin(), sptr.end() - 1);
+    for (int64_t q = 0; q < nseg; ++q) ssegs[(size_t)fill[(size_t)seg_star[(size_t)q]]++] = (int32_t)q;
+  }
   const int64_t ngroups = (S + kWave - 1) / kWave;
   bv->ngroups = ngroups;
   std::vector<int64_t> grp_base((size_t)ngroups + 1, 0);
   std::vector<int32_t> grp_cnt((size_t)ngroups, 0);
+  std::vector<int32_t> col_of((size_t)nb, -1);
+  std::vector<int32_t> ncols_prim((size_t)ngroups, 0);
   for (int64_t g = 0; g < ngroups; ++g) {
-    int32_t c = 0;
-    for (int64_t st_ = g * kWave; st_ < std::min<int64_t>(S, (g + 1) * kWave); ++st_) c = std::max(c, nper[(size_t)st_]);
-    grp_cnt[(size_t)g] = c;
-    grp_base[(size_t)g + 1] = grp_base[(size_t)g] + (int64_t)c * kWave;
+    const int64_t s0 = g * kWave, s1 = std::min<int64_t>(S, (g + 1) * kWave);
+    std::vector<char> touched((size_t)nb, 0);
+    int32_t extra = 0;
+    for (int64_t st_ = s0; st_ < s1; ++st_) {
+      int32_t e = 0;
+      for (int64_t i = sptr[(size_t)st_]; i < sptr[(size_t)st_ + 1]; ++i) {
+        const int32_t b = seg_blk[(size_t)ssegs[(size_t)i]];
+        if (i > sptr[(size_t)st_] && b == seg_blk[(size_t)ssegs[(size_t)i - 1]])
+          ++e;
+        else
+          touched[(size_t)b] = 1;
+      }
+      extra = std::max(extra, e);
+    }
+    int32_t t = 0;
+    for (int64_t b = 0; b < nb; ++b) t += touched[(size_t)b];
+    ncols_prim[(size_t)g] = t;
+    grp_cnt[(size_t)g] = t + extra;
+    grp_base[(size_t)g + 1] = grp_base[(size_t)g] + (int64_t)(t + extra) * kWave;
   }
   bv->nlist = grp_base[(size_t)ngroups];
   std::vector<int32_t> grp_list((size_t)std::max<int64_t>(bv->nlist, 1), (int32_t)nseg);
-  {
-    std::vector<int32_t> fill((size_t)S, 0);
-    for (int64_t q = 0; q < nseg; ++q) {
-      const int64_t st_ = seg_star[(size_t)q], g = st_ / kWave;
-      grp_list[(size_t)(grp_base[(size_t)g] + (int64_t)fill[(size_t)st_]++ * kWave + (st_ - g * kWave))] = (int32_t)q;
+  for (int64_t g = 0; g < ngroups; ++g) {
+    const int64_t s0 = g * kWave, s1 = std::min<int64_t>(S, (g + 1) * kWave);
+    std::fill(col_of.begin(), col_of.end(), -1);
+    for (int64_t st_ = s0; st_ < s1; ++st_)
+      for (int64_t i = sptr[(size_t)st_]; i < sptr[(size_t)st_ + 1]; ++i) col_of[(size_t)seg_blk[(size_t)ssegs[(size_t)i]]] = 0;
+    int32_t c = 0;
+    for (int64_t b = 0; b < nb; ++b)
+      if (col_of[(size_t)b] == 0) col_of[(size_t)b] = c++;
+    for (int64_t st_ = s0; st_ < s1; ++st_) {
+      int32_t e = 0;
+      for (int64_t i = sptr[(size_t)st_]; i < sptr[(size_t)st_ + 1]; ++i) {
+        const int32_t q = ssegs[(size_t)i], b = seg_blk[(size_t)q];
+        const bool again = i > sptr[(size_t)st_] && b == seg_blk[(size_t)ssegs[(size_t)i - 1]];
+        const int64_t col = again ? ncols_prim[(size_t)g] + e++ : col_of[(size_t)b];
+        grp_list[(size_t)(grp_base[(size_t)g] + col * kWave + (st_ - s0))] = q;
+      }
     }
   }
 
