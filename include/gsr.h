@@ -111,9 +111,10 @@ int gsr_destroy(gsr_system *sys);
  *   x device [n], y device [m] (must not overlap).  scale_y = 1 gives the
  *   paper's "b += A x"; scale_y = 0 overwrites y without reading it.
  *   product GSR_PROD_F32 (FP32 systems only) forms each a*x in FP32 from
- *   fl32(x); sums are always FP64.  The attitude part of x is first copied,
- *   axes interleaved, into a handle workspace (3 n_att doubles), from which
- *   each tile's 12-value windows are loaded together.
+ *   fl32(x); sums are always FP64.  The attitude part of x is first copied
+ *   into a handle workspace of window records (16 n_att doubles: for each
+ *   attitude start the 12 values of its window, one 128-byte line), from
+ *   which each tile's windows are loaded together.
  */
 int gsr_aprod1(gsr_system *sys, const double *x, double *y, double scale_y, int32_t product,
                gsr_stream stream);
@@ -121,9 +122,10 @@ int gsr_aprod1(gsr_system *sys, const double *x, double *y, double scale_y, int3
  * gsr_aprod1 without any allocation, for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc).  Same arguments, kernels and results as gsr_aprod1, on
- * handles made by gsr_create.  Its workspace, the interleaved attitude part
- * of x, lives in a static device array of 4 MiB per GPU held until the
- * process ends: 3 * n_att must not exceed 524,288 (GSR_EINVAL otherwise).
+ * handles made by gsr_create.  Its workspace, the attitude window records
+ * of x (16 values per attitude start), lives in a static device array of
+ * 16 MiB per GPU held until the process ends: 16 * n_att must not exceed
+ * 2,097,152, i.e. n_att <= 131,072 (GSR_EINVAL otherwise).
  * The handle's device must be current.  Every call on one GPU shares that
  * array, so calls that overlap on one GPU (other streams, other threads,
  * other handles) race and must be ordered by the caller.

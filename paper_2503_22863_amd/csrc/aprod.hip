@@ -111,7 +111,7 @@ __global__ void __launch_bounds__(kBlock) k_aprod1(SysView s, int waves, const d
       scur = tile_next(s, bv_c, t0, sf);
       // gathers of x for this tile, issued before the next tile's loads: the
       // astrometric x of the tile's first stars, and the tile's 64 attitude
-      // windows of the axis-interleaved x3 (96 bytes each), loaded
+      // windows (96 bytes each, one 128-byte record line) of x3, loaded
       // cooperatively (piece j*64 + lane in cw[j]; consecutive lanes take
       // consecutive 16-byte pieces of one window)
       const double xs = x[min(5 * sf + lane, xa_last)];
@@ -120,7 +120,7 @@ __global__ void __launch_bounds__(kBlock) k_aprod1(SysView s, int waves, const d
       for (int j = 0; j < 6; ++j) {
         const int c = j * kWave + lane, i = c / 6, q = c - 6 * i;
         const int at_i = __shfl(at_c, i, kWave);
-        cw[j] = *reinterpret_cast<const dd2u*>(x3 + 3 * (int64_t)at_i + 2 * q);
+        cw[j] = *reinterpret_cast<const dd2u*>(x3 + kAttRec * (int64_t)at_i + 2 * q);
       }
       bnds[wid][lane] = bv_c;
       lds_put<CPR>(tmp, nrow, slabs[wid], lane);
@@ -544,7 +544,7 @@ StreamShape stream_shape(const SysView& s, int cus, int waves_per_cu) {
 hipError_t launch_aprod1(const SysView& s, StreamShape sh, const double* x, double* x3w, double* y, double scale,
                          double ax, int pmode, Scalars* sc, Work w, int lsqr_stage, hipStream_t st) {
   if (x3w == nullptr) return hipErrorInvalidValue;
-  const hipError_t e = launch_att_interleave(s, x, x3w, st);
+  const hipError_t e = launch_att_records(s, x, x3w, st);
   if (e != hipSuccess) return e;
   const dim3 g(sh.blocks), b(kBlock);
   const size_t lb = sizeof(double) * (size_t)std::max<int64_t>(s.n_instr, 1);

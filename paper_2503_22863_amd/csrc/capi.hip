@@ -68,10 +68,10 @@ struct gsr_system {
   // LSQR vectors
   double *u = nullptr, *v = nullptr, *vg = nullptr, *w = nullptr, *y = nullptr, *var = nullptr;
   double* gA = nullptr;  // raw astrometric sums of the fused iteration pass
-  double* x3 = nullptr;  // attitude part of vg, axes interleaved, for the fused pass
+  double* x3 = nullptr;  // attitude window records of vg [n_att][kAttRec], for the star-order fused pass
   double* awr = nullptr;  // attitude window records of vg [n_att][kAttRec], for the regrouped pass
   float* awrf = nullptr;  // the same rounded to FP32, for the regrouped pass with FP32 products
-  double* x3a = nullptr;  // the attitude part of aprod 1's x, axes interleaved (aprod 1's workspace)
+  double* x3a = nullptr;  // attitude window records of aprod 1's x (aprod 1's workspace)
   void* rix = nullptr;   // packed row indices for the fused pass (16 B per row); null: no fused pass
   int fused = 1;         // one pass over the rows per iteration (FP64 products, attitude mode 0 or 3)
   // rows regrouped by attitude window (one pass per iteration where the attitude block exceeds LDS)
@@ -698,7 +698,7 @@ static int check_product(gsr_system* s, int32_t product) {
 }
 
 static int ensure_x3a(gsr_system* s) {
-  if (!s->x3a) CHK(dalloc(&s->x3a, (size_t)std::max<int64_t>(3 * s->s.n_att, 1)));
+  if (!s->x3a) CHK(dalloc(&s->x3a, (size_t)std::max<int64_t>(kAttRec * s->s.n_att, 1)));
   return GSR_OK;
 }
 
@@ -803,14 +803,14 @@ extern "C" int gsr_aprod1(gsr_system* s, const double* x, double* y, double scal
 }
 
 // ------------------------------------------------- aprod 1 without allocation
-// The only workspace of the standalone aprod 1 is the interleaved attitude
-// part of x (3 n_att doubles).  gsr_aprod1_noalloc takes it from this
+// The only workspace of the standalone aprod 1 is the attitude window records
+// of x (kAttRec n_att doubles).  gsr_aprod1_noalloc takes it from this
 // file-scope device array instead of a handle allocation; every GPU the
 // library runs on holds its own copy for the life of the process.  Host code
 // never passes the array's name to a kernel (on the host it is only a
 // stand-in symbol): its device address is looked up once per device, with that
 // device current, when the first handle on the device is created.
-constexpr int64_t kScratchDoubles = (int64_t)1 << 19;  // 4 MiB: attitude blocks up to 174,762 per axis
+constexpr int64_t kScratchDoubles = (int64_t)1 << 21;  // 16 MiB: attitude blocks up to 131,072 per axis
 static __device__ __align__(256) double scratch[kScratchDoubles];
 constexpr int kMaxDevices = 64;
 static double* g_scratch[kMaxDevices] = {};
@@ -838,9 +838,9 @@ extern "C" int gsr_aprod1_noalloc(gsr_system* s, const double* x, double* y, dou
   NEED_DEV(x, "x");
   if (s->s.m > 0) NEED_DEV(y, "y");
   if (s->packed) return fail(GSR_EINVAL, "gsr_aprod1_noalloc runs on handles made by gsr_create");
-  if (3 * s->s.n_att > kScratchDoubles)
-    return fail(GSR_EINVAL, "3 * n_att = %lld exceeds the no-allocation scratch of %lld doubles",
-                (long long)(3 * s->s.n_att), (long long)kScratchDoubles);
+  if (kAttRec * s->s.n_att > kScratchDoubles)
+    return fail(GSR_EINVAL, "16 * n_att = %lld exceeds the no-allocation scratch of %lld doubles",
+                (long long)(kAttRec * s->s.n_att), (long long)kScratchDoubles);
   if (s->s.m == 0) return GSR_OK;
   int dev = -1;
   HIPCHK(hipGetDevice(&dev));
@@ -944,7 +944,7 @@ static int ensure_vectors(gsr_system* s) {
   if (!s->y) CHK(dalloc(&s->y, n));
   if (!s->var) CHK(dalloc(&s->var, n));
   if (!s->gA) CHK(dalloc(&s->gA, (size_t)std::max<int64_t>(s->s.n_astro, 1)));
-  if (!s->x3) CHK(dalloc(&s->x3, (size_t)std::max<int64_t>(3 * s->s.n_att, 1)));
+  if (!s->x3) CHK(dalloc(&s->x3, (size_t)std::max<int64_t>(kAttRec * s->s.n_att, 1)));
   CHK(ensure_x3a(s));
   return GSR_OK;
 }
@@ -965,12 +965,11 @@ static int blk_applies(const gsr_system* s) {
          s->s.n_instr + 1 <= kLdsTailMax;
 }
 
-// The attitude x that the next row pass reads: window records for the regrouped
-// pass (and their FP32 rounding with FP32 products), the interleaved copy for the
-// star-order fused pass.
+// The attitude window records that the next row pass reads: the regrouped pass's
+// (and their FP32 rounding with FP32 products), or the star-order fused pass's.
 static hipError_t att_copy_for_pass(gsr_system* s, const double* v, hipStream_t st) {
   if (s->use_blk) return launch_att_records(s->s, v, s->awr, st, s->pmode == GSR_PROD_F32 ? s->awrf : nullptr);
-  return launch_att_interleave(s->s, v, s->x3, st);
+  return launch_att_records(s->s, v, s->x3, st);
 }
 
 // fold_r0: on the regrouped copy, form r0 = b - A x0 inside the first pass
@@ -1090,7 +1089,7 @@ static int lsqr_begin(gsr_system* s, const double* b, const double* x0, const gs
       CHK(dalloc(&s->zvec, (size_t)s->s.n));
       HIPCHK(launch_fill(s->zvec, s->s.n, 0.0, st));
     }
-    HIPCHK(launch_att_interleave(s->s, s->zvec, s->x3, st));
+    HIPCHK(launch_att_records(s->s, s->zvec, s->x3, st));
     if (s->con.ncon > 0) HIPCHK(launch_con_aprod1(s->con, s->zvec, uc, 0.0, 1.0, s->sc, s->wk, st));
     HIPCHK(launch_fused(s->s, s->sh, mode, product, s->zvec, s->x3, s->rix, s->u, s->gA, s->acc, s->sc, s->wk, st,
                         1));

@@ -34,19 +34,8 @@ __global__ void k_pack_rows(SysView s, u4* __restrict__ rix) {
   }
 }
 
-// x3[3c + a] = x[n_astro + a*n_att + c]: the attitude unknowns with the three
-// axes interleaved, so that the 12 attitude unknowns of a row (4 consecutive
-// columns on each axis) are 96 contiguous bytes.
-__global__ void k_att_interleave(SysView s, const double* __restrict__ x, double* __restrict__ x3) {
-  const int64_t n3 = 3 * s.n_att;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n3; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t c = e / 3, axs = e - 3 * c;
-    const double v = x[s.n_astro + axs * s.n_att + c];
-    x3[e] = v;
-  }
-}
-
-// Window records for the regrouped pass: record a holds the 12 attitude x of
+// Attitude window records, the copy of x that every row pass reads its
+// attitude x from: record a holds the 12 attitude x of
 // starts a .. a+3 (element 3j + axis: axis `axis` at start a+j), padded to
 // kAttRec = 16 values, so that the window a row reads is one 128-byte cache
 // line (64 bytes in the FP32 copy) instead of 96 bytes at a 24-byte stride,
@@ -154,7 +143,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
       for (int j = 0; j < 6; ++j) {
         const int c = j * kWave + lane, i = c / 6, q = c - 6 * i;
         const int at_i = __shfl(at_c, i, kWave);
-        cw[j] = *reinterpret_cast<const dd2u*>(x3 + 3 * (int64_t)at_i + 2 * q);
+        cw[j] = *reinterpret_cast<const dd2u*>(x3 + kAttRec * (int64_t)at_i + 2 * q);
       }
       bnds[wid][lane] = bv_c;
       lds_put<CPR>(tmp, nrow, slabs[wid], lane);
@@ -328,12 +317,5 @@ hipError_t launch_att_records(const SysView& s, const double* x, double* xr, hip
   return hipGetLastError();
 }
 
-hipError_t launch_att_interleave(const SysView& s, const double* x, double* x3, hipStream_t st) {
-  const int64_t n3 = 3 * s.n_att;
-  if (n3 == 0) return hipSuccess;
-  const int blocks = (int)std::min<int64_t>(1024, (n3 + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_att_interleave, dim3(blocks), dim3(kBlock), 0, st, s, x, x3);
-  return hipGetLastError();
-}
 
 }  // namespace gsr

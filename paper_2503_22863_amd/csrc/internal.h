@@ -139,14 +139,16 @@ struct BlkView {
   int64_t ngroups;      // groups of 64 consecutive stars
   int64_t nlist;        // entries of grp_list
   int64_t* grp_base;    // [ngroups + 1] start of each group's ids in grp_list
-  int32_t* grp_cnt;     // [ngroups] most segments of a star in the group
-  int32_t* grp_list;    // segment ids, per group [grp_cnt][64] (star = lane), padded with nseg
+  int32_t* grp_cnt;     // [ngroups] columns of the group's list (windows touched + a star's extra segments)
+  int32_t* grp_list;    // segment ids, per group [grp_cnt][64] (star = lane), aligned by window, padded with nseg
   double* P;            // [nseg + 1][5] astrometric sums of each segment (the last entry stays zero)
   double* Q;            // [G][3][Wb + 3] attitude window sums of each workgroup
   double* ub;           // [mp] u in this order
   double* dummy;        // [kBlkWaves*G][128] per-wave store targets of lanes with nothing to store
 };
 constexpr int kBlkWaves = 8;  // waves per workgroup of the regrouped pass
+// Values per attitude window record (12 used: 4 starts x 3 axes; 128 bytes in FP64).
+constexpr int kAttRec = 16;
 constexpr int kBlkDummy = 128; // doubles per wave in BlkView::dummy: 64 for u, 64 for the segment sums
 
 // LSQR epilogue arguments of the tail pass.
@@ -159,8 +161,8 @@ struct TailLsqr {
 // ---- launchers (all asynchronous on `st`) ---------------------------------
 // y <- scale*y + ax * A x (or with the LSQR scalars: scale = sc->u_scale, ax = 1,
 // and the last workgroup forms beta_{i+1}); mode: 0 FP64 products, 1 FP32 products.
-// x3w: 3 n_att doubles of workspace, which first takes the attitude part of x with
-// the axes interleaved (the kernel loads each row's 12 values as one window).
+// x3w: kAttRec n_att doubles of workspace, which first takes the attitude window
+// records of x (the kernel loads each row's 12 values as one window).
 hipError_t launch_aprod1(const SysView& s, StreamShape sh, const double* x, double* x3w, double* y, double scale,
                          double ax, int pmode, Scalars* sc, Work w, int lsqr_stage, hipStream_t st);
 // astro part of x <- scale*x + S*(A^T (inv_beta*y)); tail part accumulated in acc
@@ -214,12 +216,8 @@ hipError_t launch_fused(const SysView& s, StreamShape sh, int att_mode, int pmod
                         int init = 0);
 // rix[r] <- {att_start[r], instr_col[r][0..5] as 16-bit pairs} (16 bytes per row; needs n_instr <= 65536)
 hipError_t launch_pack_rows(const SysView& s, void* rix, hipStream_t st);
-// x3 <- attitude part of x with the three axes interleaved (the fused pass's copy of vg)
-hipError_t launch_att_interleave(const SysView& s, const double* x, double* x3, hipStream_t st);
-// Values per attitude window record of the regrouped pass (12 used: 4 starts x 3 axes).
-constexpr int kAttRec = 16;
-// xr [n_att][kAttRec] <- the attitude window of every start (the regrouped pass's copy of
-// vg), and the same rounded to FP32 into xrf when it is not null
+// xr [n_att][kAttRec] <- the attitude window of every start (the row passes' copy of
+// the attitude x), and the same rounded to FP32 into xrf when it is not null
 hipError_t launch_att_records(const SysView& s, const double* x, double* xr, hipStream_t st, float* xrf = nullptr);
 // Tail of the fused iteration: every column x_j <- v_scale*x_j + S_j * raw_j / beta (raw_j from gA, acc
 // or the attitude windows), then alpha_{i+1} and the rotations, as launch_tail.
