@@ -40,10 +40,12 @@ FUSED_B_STAR = 40 + 40
 # the same with FP32 values (the FP32 forms)
 FUSED_B_ROW_F32 = 96 + 4 + 24 + 8 + 8
 # The pass over the copy regrouped by attitude window: per row the 24 coefficients,
-# the 16-byte row record, u read and u written; per star segment the star's 5 v read
-# and the 5 partial sums written; per workgroup its attitude window of sums written.
-FBLK_B_ROW = 192 + 16 + 8 + 8
-FBLK_B_ROW_F32 = 96 + 16 + 8 + 8
+# the 12-byte row record, u read and u written; per 64-row tile the star of its
+# first row; per star segment the star's 5 v read and the 5 partial sums written;
+# per workgroup its attitude window of sums written.
+FBLK_B_ROW = 192 + 12 + 8 + 8
+FBLK_B_ROW_F32 = 96 + 12 + 8 + 8
+FBLK_B_TILE = 4
 FBLK_B_SEG = 40 + 40
 # The standalone products on the caller's rows: aprod 1 reads the coefficients, the
 # attitude start and the 6 instrumental columns and reads and writes y; aprod 2
@@ -56,8 +58,8 @@ APROD2_B_STAR = 40 + 40
 def pass_bytes(info, m, ns, f32=False):
     """(kernel, algorithmic bytes per launch) of the iteration's row pass."""
     if info and info.get("active"):
-        by = (FBLK_B_ROW_F32 if f32 else FBLK_B_ROW) * m + FBLK_B_SEG * info["segments"] + \
-            24 * (info["window"] + 3) * info["workgroups"]
+        by = (FBLK_B_ROW_F32 if f32 else FBLK_B_ROW) * m + FBLK_B_TILE * (info["padded_rows"] // 64) + \
+            FBLK_B_SEG * info["segments"] + 24 * (info["window"] + 3) * info["workgroups"]
         return "k_fblk", by
     return "k_fused", (FUSED_B_ROW_F32 if f32 else FUSED_B_ROW) * m + FUSED_B_STAR * ns
 

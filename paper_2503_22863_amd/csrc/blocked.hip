@@ -34,21 +34,24 @@ constexpr int kBlkThreads = kBlkWaves * kWave;
 // static LDS of the pass: the attitude-window regroup buffers and the reduction slots
 constexpr size_t kBlkStaticLds = sizeof(double) * 2 * kBlkWaves * (kWave / 2) * 7 + sizeof(double) * kBlkWaves + 64;
 
-// Row records: star id, attitude start within the block's window (13 bits),
-// six instrumental columns (11 bits each) and the end-of-segment bit.
-__device__ __forceinline__ void rec_pack(uint32_t* R, int64_t pos, uint32_t star, uint32_t off, const int* ic,
+// Row records, 12 bytes: word 0 = attitude start within the block's window (13
+// bits) | end-of-segment bit << 13 | instrumental column 0 (11 bits) << 14 | the
+// low 7 bits of the star's offset d from its tile's first star << 25; words 1-2
+// (64 bits) = instrumental columns 1..5 (11 bits each) | the high 9 bits of d << 55.
+__device__ __forceinline__ void rec_pack(uint32_t* R, int64_t pos, uint32_t d, uint32_t off, const int* ic,
                                          uint32_t end) {
-  const uint64_t A = (uint64_t)star | ((uint64_t)off << 32) | ((uint64_t)ic[0] << 45) | ((uint64_t)end << 63);
+  const uint32_t w0 = off | (end << 13) | ((uint32_t)ic[0] << 14) | ((d & 0x7Fu) << 25);
   const uint64_t B = (uint64_t)ic[1] | ((uint64_t)ic[2] << 11) | ((uint64_t)ic[3] << 22) | ((uint64_t)ic[4] << 33) |
-                     ((uint64_t)ic[5] << 44);
-  u4 v = {(unsigned)A, (unsigned)(A >> 32), (unsigned)B, (unsigned)(B >> 32)};
-  reinterpret_cast<u4*>(R)[pos] = v;
+                     ((uint64_t)ic[5] << 44) | ((uint64_t)(d >> 7) << 55);
+  R[3 * pos] = w0;
+  R[3 * pos + 1] = (uint32_t)B;
+  R[3 * pos + 2] = (uint32_t)(B >> 32);
 }
 
 // Row records of every position: for original row r at ipos[r] its star, the
 // attitude start within the block's window and the instrumental columns; for
-// a padding position the star it repeats and zero columns.  se[pos]:
-// star | end << 31.
+// a padding position the star it repeats and zero columns; and the star of
+// every tile's first position.  se[pos]: star | end << 31.
 __global__ void k_blk_records(SysView s, BlkView bv, const uint32_t* __restrict__ se) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < bv.m + bv.npad;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -61,7 +64,9 @@ __global__ void k_blk_records(SysView s, BlkView bv, const uint32_t* __restrict_
       for (int q = 0; q < 6; ++q) ic[q] = s.instr_col[6 * i + q];
     }
     const uint32_t e = se[pos];
-    rec_pack(bv.R, pos, e & 0x7FFFFFFFu, off, ic, e >> 31);
+    const uint32_t first = se[(pos / kWave) * kWave] & 0x7FFFFFFFu;
+    if (pos % kWave == 0) bv.tstar[pos / kWave] = first;
+    rec_pack(bv.R, pos, (e & 0x7FFFFFFFu) - first, off, ic, e >> 31);
   }
 }
 
@@ -166,14 +171,20 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
     const double xg = s.n_glob ? x[NI + s.n_instr] : 0.0;
     const int64_t xa_last = 5 * s.n_stars - 1;
     const u4* cb = reinterpret_cast<const u4*>(bv.T);
-    const u4* rb = reinterpret_cast<const u4*>(bv.R);
+    const uint32_t* rb = bv.R;
     u4 tmp[CPR];
-    u4 rec;
+    u4 rec;  // x, y, z: the row's record; w: the star of the tile's first row
     double uo;
     // the record first: the next tile's gathers need only it
     auto fetch = [&](int64_t t) {
       const int64_t tt = min(t, T1 - 1);  // past the range: re-read its last tile (the registers are not used)
-      rec = ld_stream(rb + tt * kWave + lane);
+      {
+        const uint32_t* rr = rb + 3 * (tt * kWave + lane);  // three 4-byte loads, merged into one
+        rec.x = __builtin_nontemporal_load(rr);
+        rec.y = __builtin_nontemporal_load(rr + 1);
+        rec.z = __builtin_nontemporal_load(rr + 2);
+        rec.w = bv.tstar[tt];
+      }
       const u4* base = cb + tt * CPR * kWave + lane;
 #pragma unroll
       for (int j = 0; j < CPR; ++j) tmp[j] = ld_stream(base + j * kWave);
@@ -192,10 +203,10 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
     double xs, xs2;
     dd2u cw[NP];
     auto gathers = [&]() {
-      const int64_t st0 = (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)rec.x, 0);
+      const int64_t st0 = (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)rec.w, 0);
       xs = x[min(5 * st0 + lane, xa_last)];
       xs2 = x[min(5 * st0 + kWave + lane, xa_last)];
-      const int ao_l = (int)(rec.y & 0x1FFFu);
+      const int ao_l = (int)(rec.x & 0x1FFFu);
 #pragma unroll
       for (int j = 0; j < NP; ++j) {
         const int c = j * kWave + lane, i = c / NP, q = c - NP * i;
@@ -232,13 +243,13 @@ k_fblk(SysView s, BlkView bv, const double* __restrict__ x, const double* __rest
     gathers();
 #pragma unroll 1
     for (int64_t t = T0; t < T1; ++t) {
-      const uint64_t A = (uint64_t)rec.x | ((uint64_t)rec.y << 32);
-      const uint64_t B = (uint64_t)rec.z | ((uint64_t)rec.w << 32);
-      const int64_t star = (int64_t)(uint32_t)A;
-      const int aoff = (int)((A >> 32) & 0x1FFFu);
-      const int ic[6] = {(int)((A >> 45) & 0x7FFu), (int)(B & 0x7FFu),         (int)((B >> 11) & 0x7FFu),
-                         (int)((B >> 22) & 0x7FFu), (int)((B >> 33) & 0x7FFu), (int)((B >> 44) & 0x7FFu)};
-      const bool end = (A >> 63) != 0;
+      const uint32_t w0 = rec.x;
+      const uint64_t B = (uint64_t)rec.y | ((uint64_t)rec.z << 32);
+      const int64_t star = (int64_t)(rec.w + ((w0 >> 25) | ((uint32_t)(B >> 55) << 7)));
+      const int aoff = (int)(w0 & 0x1FFFu);
+      const int ic[6] = {(int)((w0 >> 14) & 0x7FFu), (int)(B & 0x7FFu),         (int)((B >> 11) & 0x7FFu),
+                         (int)((B >> 22) & 0x7FFu),  (int)((B >> 33) & 0x7FFu), (int)((B >> 44) & 0x7FFu)};
+      const bool end = ((w0 >> 13) & 1u) != 0;
       const double uo_c = (scale == 0.0) ? 0.0 : scale * uo;
       const int64_t s0 = lane_read(star, 0);
       const int64_t ds = star - s0;
@@ -478,7 +489,7 @@ hipError_t launch_blk_permute(const BlkView& bv, const double* src, hipStream_t 
 
 void blk_free(BlkView* bv) {
   if (bv->t_owned && bv->T) (void)hipFree(bv->T);
-  for (void* p : {(void*)bv->R, (void*)bv->ipos, (void*)bv->pad, (void*)bv->wg_block, (void*)bv->wave_tile,
+  for (void* p : {(void*)bv->R, (void*)bv->tstar, (void*)bv->ipos, (void*)bv->pad, (void*)bv->wg_block, (void*)bv->wave_tile,
                   (void*)bv->seg_base, (void*)bv->bsub, (void*)bv->grp_base, (void*)bv->grp_cnt,
                   (void*)bv->grp_list, (void*)bv->P, (void*)bv->Q, (void*)bv->ub, (void*)bv->dummy})
     if (p) (void)hipFree(p);
@@ -520,30 +531,53 @@ int blk_plan(const SysView& s, BlkView* bv, int cus, int max_window, int lds_max
   if (hipMemcpy(att.data(), s.att_start, sizeof(int32_t) * (size_t)m, hipMemcpyDeviceToHost) != hipSuccess ||
       hipMemcpy(rp.data(), s.row_ptr, sizeof(int64_t) * (size_t)(S + 1), hipMemcpyDeviceToHost) != hipSuccess)
     return failed(GSR_EHIP, "reading the row indices failed");
-  std::vector<int64_t> cnt((size_t)nb, 0), tb((size_t)nb + 1, 0);
-  for (int64_t r = 0; r < m; ++r) ++cnt[(size_t)(att[(size_t)r] / Wb)];
-  for (int64_t g = 0; g < nb; ++g) tb[(size_t)g + 1] = tb[(size_t)g] + (cnt[(size_t)g] + kWave - 1) / kWave;
+  // Positions per block, star order inside a block.  A row record holds its star
+  // as an offset below kStarSpan from the star of its tile's first row, so a row
+  // whose star lies that far past it starts a new tile: the rest of the current
+  // tile is padding.  The walk below is repeated to place the rows.
+  auto walk = [&](auto&& place, auto&& pad) {
+    std::vector<int64_t> k((size_t)nb, 0), first((size_t)nb, 0);
+    for (int64_t st_ = 0; st_ < S; ++st_)
+      for (int64_t r = rp[(size_t)st_]; r < rp[(size_t)st_ + 1]; ++r) {
+        const int64_t g = att[(size_t)r] / Wb;
+        int64_t& kg = k[(size_t)g];
+        if (kg % kWave != 0 && st_ - first[(size_t)g] >= kStarSpan)
+          for (; kg % kWave != 0; ++kg) pad(g, kg);
+        if (kg % kWave == 0) first[(size_t)g] = st_;
+        place(g, kg++, r, st_);
+      }
+    return k;
+  };
+  std::vector<int64_t> tb((size_t)nb + 1, 0);
+  {
+    const std::vector<int64_t> cnt = walk([](int64_t, int64_t, int64_t, int64_t) {}, [](int64_t, int64_t) {});
+    for (int64_t g = 0; g < nb; ++g) tb[(size_t)g + 1] = tb[(size_t)g] + (cnt[(size_t)g] + kWave - 1) / kWave;
+  }
   const int64_t ntiles = tb[(size_t)nb], mp = ntiles * kWave;
   if (mp >= ((int64_t)1 << 31)) return failed(GSR_EINVAL, "too many rows for the regrouped pass");
   bv->ntiles = ntiles;
   bv->mp = mp;
   bv->m = m;
 
-  // positions: block-major, star order inside a block; padding repeats the block's last star
+  // positions: block-major, star order inside a block; a padding position repeats
+  // the star of the position before it
   std::vector<int32_t> ipos((size_t)m);
   std::vector<int32_t> pads;
   std::vector<uint32_t> se((size_t)mp, 0);
   {
-    std::vector<int64_t> fill((size_t)nb);
-    for (int64_t g = 0; g < nb; ++g) fill[(size_t)g] = tb[(size_t)g] * kWave;
-    for (int64_t st_ = 0; st_ < S; ++st_)
-      for (int64_t r = rp[(size_t)st_]; r < rp[(size_t)st_ + 1]; ++r) {
-        const int64_t pos = fill[(size_t)(att[(size_t)r] / Wb)]++;
-        ipos[(size_t)r] = (int32_t)pos;
-        se[(size_t)pos] = (uint32_t)st_;
-      }
+    const std::vector<int64_t> used = walk(
+        [&](int64_t g, int64_t kg, int64_t r, int64_t st_) {
+          const int64_t pos = tb[(size_t)g] * kWave + kg;
+          ipos[(size_t)r] = (int32_t)pos;
+          se[(size_t)pos] = (uint32_t)st_;
+        },
+        [&](int64_t g, int64_t kg) {
+          const int64_t pos = tb[(size_t)g] * kWave + kg;
+          se[(size_t)pos] = se[(size_t)pos - 1];
+          pads.push_back((int32_t)pos);
+        });
     for (int64_t g = 0; g < nb; ++g)
-      for (int64_t pos = fill[(size_t)g]; pos < tb[(size_t)g + 1] * kWave; ++pos) {
+      for (int64_t pos = tb[(size_t)g] * kWave + used[(size_t)g]; pos < tb[(size_t)g + 1] * kWave; ++pos) {
         se[(size_t)pos] = se[(size_t)pos - 1];
         pads.push_back((int32_t)pos);
       }
@@ -659,7 +693,7 @@ int blk_plan(const SysView& s, BlkView* bv, int cus, int max_window, int lds_max
 
   uint32_t* se_d = nullptr;
   auto dalloc_ = [](void** p, size_t bytes) { return hipMalloc(p, std::max<size_t>(bytes, 16)) == hipSuccess; };
-  if (!dalloc_((void**)&bv->R, (size_t)mp * 16) || !dalloc_((void**)&bv->ipos, (size_t)m * 4) ||
+  if (!dalloc_((void**)&bv->R, (size_t)mp * 12) || !dalloc_((void**)&bv->tstar, (size_t)ntiles * 4) || !dalloc_((void**)&bv->ipos, (size_t)m * 4) ||
       !dalloc_((void**)&bv->pad, pads.size() * 4) || !dalloc_((void**)&bv->wg_block, (size_t)G * 4) ||
       !dalloc_((void**)&bv->wave_tile, (size_t)(W + 1) * 4) || !dalloc_((void**)&bv->seg_base, (size_t)W * 4) ||
       !dalloc_((void**)&bv->bsub, (size_t)(nb + 1) * 4) ||
@@ -718,7 +752,7 @@ size_t blk_value_bytes(const BlkView& bv) {
 
 size_t blk_index_bytes(const BlkView& bv) {
   const int64_t W = (int64_t)bv.G * kBlkWaves;
-  return (size_t)bv.mp * 16 + (size_t)bv.m * 4 + (size_t)bv.npad * 4 + (size_t)bv.G * 4 + (size_t)(W + 1) * 4 +
+  return (size_t)bv.mp * 12 + (size_t)bv.ntiles * 4 + (size_t)bv.m * 4 + (size_t)bv.npad * 4 + (size_t)bv.G * 4 + (size_t)(W + 1) * 4 +
          (size_t)W * 4 + (size_t)(bv.nb + 1) * 4 + (size_t)(bv.ngroups + 1) * 8 + (size_t)bv.ngroups * 4 +
          (size_t)std::max<int64_t>(bv.nlist, 1) * 4 + (size_t)(bv.nseg + 1) * 40 +
          (size_t)bv.G * 3 * (bv.Wb + 3) * 8 + (size_t)bv.mp * 8 + (size_t)W * kBlkDummy * 8;

@@ -127,7 +127,9 @@ struct BlkView {
   void* T;              // [ntiles][CPR][64] 16-byte chunks of the coefficients
   int t_owned;          // 1: T is the library's copy (freed with the view); 0: the caller's buffer
   int32_t value_type;   // GSR_F64 or GSR_F32
-  uint32_t* R;          // [mp][4] row records: star | att_start - g*Wb (13 bits) << 32 | instr (11 bits each) | end bit
+  uint32_t* R;          // [mp][3] row records (12 bytes): attitude offset in the window, end bit, the
+                        // 6 instrumental columns and the star's offset from its tile's first star
+  uint32_t* tstar;      // [mp / 64] star of each tile's first row
   int64_t m;            // rows of the system
   int32_t* ipos;        // [m] position of each original row
   int32_t* pad;         // [npad] padding positions
@@ -149,6 +151,8 @@ struct BlkView {
 constexpr int kBlkWaves = 8;  // waves per workgroup of the regrouped pass
 // Values per attitude window record (12 used: 4 starts x 3 axes; 128 bytes in FP64).
 constexpr int kAttRec = 16;
+// Stars a row record can lie past its tile's first star (16-bit offsets).
+constexpr int64_t kStarSpan = 65536;
 constexpr int kBlkDummy = 128; // doubles per wave in BlkView::dummy: 64 for u, 64 for the segment sums
 
 // LSQR epilogue arguments of the tail pass.

@@ -357,3 +357,45 @@ def test_packed_covariance_export_and_pairs(dev, oracle_lib):
     S.cov_export(None)
     S.cov_request_pairs([], block=64)
     S.close()
+
+
+def _with_empty_stars(g, at, gap):
+    """The same rows, with `gap` stars that have no rows inserted before star `at`."""
+    rp = g.star_row_ptr
+    rp2 = np.concatenate([rp[:at + 1], np.full(gap, rp[at], dtype=rp.dtype), rp[at + 1:]])
+    xt = np.concatenate([g.x_true[:5 * at], np.zeros(5 * gap), g.x_true[5 * at:]])
+    d = gsr_synth.Dims(g.dims.n_stars + gap, g.dims.m, g.dims.n_att, g.dims.n_instr, g.dims.n_glob)
+    return gsr_synth.System(d, g.vals, rp2, g.att_start, g.instr_col, xt, g.noise, g.seed, dict(g.meta))
+
+
+def test_packed_star_gap_beyond_record_span(dev, oracle_lib):
+    """Rows of one window whose stars lie 150,000 apart (that many stars without
+    rows between them): a row record holds its star as an offset below 65,536
+    from its tile's first star, so the layout starts a new tile at the gap
+    (padding rows).  Products and LSQR iterates against the oracle."""
+    c = CASES["many_windows"]
+    g0 = gsr_synth.make_system(c["n_stars"], c["obs"], c["n_att"], c["n_instr"], 1, seed=c["seed"])
+    g = _with_empty_stars(g0, c["n_stars"] // 2, 150_000)
+    d = g.dims
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    pad0 = dev.Layout(t(g0.star_row_ptr), t(g0.att_start), t(g0.instr_col), d.n_att, d.n_instr, 1,
+                      max_window=c["maxw"]).info()["padded_rows"]
+    S = dev.System.packed_from_generated(g, device="cuda:0", max_window=c["maxw"])
+    info = S.blocked_info()
+    print(f"[packed] star gap: padded rows {info['padded_rows']} (without the gap {pad0})", flush=True)
+    assert info["padded_rows"] > pad0  # the gap closed tiles early in some windows
+    o, oa = oracle_lib.OSystem(g), _abs_system(oracle_lib, g)
+    rng = np.random.default_rng(67)
+    x, y0 = rng.standard_normal(d.n), rng.standard_normal(d.m)
+    y = t(y0)
+    S.aprod1(t(x), y, scale=-0.75)
+    check_aprod1(oracle_lib, g, o, oa, x, y0, -0.75, y.cpu().numpy(), "star gap")
+    check_aprod2(oracle_lib, g, o, oa, y0, np.zeros(d.n), 0.0, S.aprod2(t(y0)).cpu().numpy(), "star gap")
+    bn = oracle_lib.known_terms(o, g.x_true, g.noise)
+    ref, sx, sv = _sensitivity(oracle_lib, g, o, bn, atol=0, btol=0, itmax=25, precond=True)
+    tol_x, tol_v = max(1e-12, 10 * sx), max(1e-10, 10 * sv)
+    xs, var, r = S.lsqr_solve(t(bn), atol=0, btol=0, itmax=25, precond=True)
+    ex, ev = _rel(xs.cpu().numpy(), ref["x"]), _rel(var.cpu().numpy(), ref["var"])
+    print(f"  x {ex:.2e} (bar {tol_x:.1e}) var {ev:.2e} (bar {tol_v:.1e})", flush=True)
+    assert r["itn"] == 25 and ex <= tol_x and ev <= tol_v
+    S.close()
