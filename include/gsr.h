@@ -349,7 +349,7 @@ typedef struct {
     int64_t padded_rows;  /* rows including the padding to 64-row tiles */
     int64_t segments;     /* star segments (astrometric partial sums per pass) */
     int64_t bytes;        /* device bytes the library holds for the layout besides the
-                             coefficients: row records (16 B per row), positions, segment
+                             coefficients: row records (12 B per row), positions, segment
                              lists and sums, workgroup windows, u in this order */
     int64_t value_bytes;  /* coefficient bytes of the regrouped rows (padding included):
                              padded_rows * 24 * sizeof(value) */
@@ -373,7 +373,7 @@ int gsr_blocked_info(gsr_system *sys, gsr_blocked_layout *info);
  *   pointers, as for gsr_create; validated the same way); max_window > 0
  *   caps Wb (>= 4), 0 takes the widest window that fits in LDS.  Needs
  *   m > 0, n_att >= 8 and n_instr <= 2047.  The caller may free its index
- *   arrays afterwards: the layout keeps 16-byte records per row (star,
+ *   arrays afterwards: the layout keeps 12-byte records per row (star,
  *   attitude start, instrumental columns).  Synchronous.
  * gsr_layout_info: sizes of the layout (active = 0, values_owned = 0); the
  *   caller allocates value_bytes of device memory for the packed rows
